@@ -1,0 +1,271 @@
+#!/usr/bin/env python
+"""Throughput of the fused split-step path on one MI355X.
+
+Metric: screen-steps/s at N = 1024, complex64.  One screen-step is one
+realization advanced through one diffraction + screen step, including the
+synthesis (or evolution) of that step's screen.  A benchmark step is one pass
+of the whole path over one batch:
+
+  forward  (value): headline workload, 64 realizations x 8 fresh screens per
+           step (t advances every step), screens synthesised inside the passes,
+           ensemble moments accumulated (turpy_propagate + turpy_stats);
+  fwd+bwd: the same with screen-plane checkpoints and the adjoint
+           (turpy_propagate_backward, dL/du_in and dL/dphi);
+  ar:      the N = 1024 autoregressive workload, one time step =
+           turpy_evolve (8 screens x 16 pairs) + turpy_propagate from the
+           stored spectra + turpy_stats (256 screen-steps);
+  plain:   the same forward physics as one PyTorch op per kernel
+           (torch.fft, elementwise exp and multiplies), screens materialised.
+
+Prints one JSON line.  Inputs are seeded and synthetic and already resident in
+HBM when the timed region starts.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+METRIC = "screen-steps/s at N=1024 c64 (fwd, fwd+bwd) vs plain GPU; % HBM roofline"
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--realizations", type=int, default=64)
+    ap.add_argument("--only", choices=["all", "fwd", "fwdbwd", "ar", "plain", "copy"], default="all",
+                    help="run one leg (profiling runs)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-pairs", type=int, default=2, help="realization pairs in the oracle sample")
+    return ap.parse_args()
+
+
+def algorithmic_bytes(path, family, checkpoints=False):
+    """Minimum HBM bytes one launch of a kernel family moves (see the design notes)."""
+    plane = path.n * path.n * 8
+    r, p = path.realizations, (path.realizations + 1) // 2
+    if family == "row_fwd":
+        return (2 * r + p) * plane + (r * plane if checkpoints else 0)
+    if family == "row_bwd":
+        # g read + write, scratch read, checkpoint read, dL/dphi write (4 B/px)
+        return (3 * r + p) * plane + r * plane // 2
+    if family == "col":
+        return 2 * r * plane
+    if family == "synth":
+        return p * plane
+    if family == "copy":
+        return 2 * r * plane
+    if family == "evolve":
+        return 2 * p * path.num_screens * plane
+    return None
+
+
+def timed_region(torch, fn, steps, warmup, binding, families):
+    for i in range(warmup):
+        fn(i)
+    torch.cuda.synchronize()
+    binding.profile(True)
+    t0 = time.perf_counter()
+    for i in range(steps):
+        fn(warmup + i)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    per = {}
+    for f in families:
+        n, ms = binding.profile_read(f)
+        if n:
+            per[f] = {"launches": n, "avg_us": 1e3 * ms / n, "total_ms": ms}
+    binding.profile(False)
+    return (t1 - t0) / steps, per
+
+
+def kernel_table(path, per, checkpoints):
+    out = {}
+    for f, d in per.items():
+        b = algorithmic_bytes(path, f, checkpoints)
+        e = dict(d)
+        if b is not None:
+            e["bytes_per_launch"] = b
+            e["GBps"] = b / (d["avg_us"] * 1e-6) / 1e9
+            e["frac_hbm"] = e["GBps"] / HBM_PEAK_GBPS
+        out[f] = e
+    return out
+
+
+def plain_forward(torch, plan, path, u0, seed, t, H, phi):
+    """One PyTorch op per kernel: the paper's own formulation of Eq. 1."""
+    plan.screens(seed, t, out=phi)
+    u = u0.expand(path.realizations, path.n, path.n)
+    for i in range(path.num_screens):
+        u = torch.fft.ifft2(torch.fft.fft2(u) * H[i])
+        u = u * torch.exp(1j * phi[:, i])
+    if path.dz[-1] > 0:
+        u = torch.fft.ifft2(torch.fft.fft2(u) * H[-1])
+    return u
+
+
+def fresnel_tables(torch, np, path, device):
+    kh = np.fft.fftfreq(path.n) * path.n
+    df = 1.0 / (path.n * path.dx)
+    f2 = (kh[:, None] ** 2 + kh[None, :] ** 2) * df * df
+    out = []
+    for dz in path.dz:
+        rev = -0.5 * (path.wavelength / path.n0) * dz * f2
+        rev -= np.rint(rev)
+        out.append(torch.from_numpy(np.exp(2j * np.pi * rev).astype(np.complex64)).to(device))
+    return out
+
+
+def cpu_baseline(w, pairs):
+    """The FP64 oracle as it stands, on a bounded sample of the forward workload."""
+    import numpy as np
+
+    from oracle import propagate as opr
+    from oracle import screens as osc
+    path = w.path.with_(realizations=2 * pairs)
+    u0 = w.source_field().astype(np.complex64).astype(np.complex128)
+    t0 = time.perf_counter()
+    phi = osc.phase_screens(path, w.seed, t=0)
+    opr.propagate(u0, path, phi)
+    dt = time.perf_counter() - t0
+    ss = path.realizations * path.num_screens
+    return {"value": ss / dt, "unit": "screen-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{path.realizations} realizations x {path.num_screens} screens of the forward workload "
+                      f"at N={path.n} (synthesis + propagation), numpy float64, single thread, {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported by this build "
+              f"(realizations shard without communication, see the design notes)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2604_07248_amd import api, binding, workloads
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    binding.lib()
+    fams = ["row_fwd", "row_bwd", "row_plain", "col", "synth", "sh", "evolve", "stats", "finalize", "copy"]
+
+    w = workloads.headline(args.realizations)
+    path = w.path
+    plan = api.Plan(path)
+    u0 = torch.from_numpy(w.source_field().astype(np.complex64)).to(dev)
+    u_out = torch.empty((path.realizations, path.n, path.n), dtype=torch.complex64, device=dev)
+    moments = api.Moments(path.n, path.dx)
+    ss_per_step = path.realizations * path.num_screens
+    plane_px = path.n * path.n
+    result = {"metric": METRIC, "unit": "screen-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+              "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c64",
+              "data": "synthetic (seeded Philox screens, Gaussian source)",
+              "config": {"workload": w.name + " (N=1024 over 1 m, 1064 nm, 1.5 km, Cn2=2e-14, l0=5 mm, L0=20 m, "
+                                              "8 fresh screens per step, W0=5 cm)",
+                         "n": path.n, "realizations": path.realizations, "screens": path.num_screens,
+                         "screen_steps_per_step": ss_per_step}}
+
+    def fwd(i):
+        plan.propagate(u0, seed=w.seed, t=i, out=u_out)
+        moments.add(u_out)
+
+    if args.only in ("all", "fwd"):
+        sec, per = timed_region(torch, fwd, args.steps, args.warmup, binding, fams)
+        result["value"] = ss_per_step / sec
+        result["ms_per_step"] = 1e3 * sec
+        ktab = kernel_table(path, per, False)
+        result["kernels"] = ktab
+        # whole-path effective bandwidth: 32 B/px field + 8 B/px per pair of screen scratch
+        result["path_effective_GBps"] = (32 + 16 / 2) * plane_px * ss_per_step / sec / 1e9
+        dom = max((f for f in ktab if "GBps" in ktab[f]), key=lambda f: ktab[f]["total_ms"])
+        d = ktab[dom]
+        result["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": d["GBps"], "peak": HBM_PEAK_GBPS,
+                              "unit": "GB/s", "frac": d["GBps"] / HBM_PEAK_GBPS, "traffic": None,
+                              "bytes_per_launch": d["bytes_per_launch"], "avg_us": d["avg_us"]}
+
+    if args.only in ("all", "fwdbwd"):
+        ck = torch.empty((path.realizations, path.num_screens, path.n, path.n), dtype=torch.complex64, device=dev)
+
+        def fwdbwd(i):
+            out, c = plan.propagate(u0, seed=w.seed, t=i, out=u_out, checkpoints=ck)
+            plan.propagate_backward(out, c, seed=w.seed, t=i)
+
+        sec, per = timed_region(torch, fwdbwd, args.steps, args.warmup, binding, fams)
+        result["fwd_bwd"] = {"value": ss_per_step / sec, "unit": "screen-steps/s", "ms_per_step": 1e3 * sec,
+                             "kernels": kernel_table(path, per, True)}
+        del ck
+
+    if args.only in ("all", "ar"):
+        w3 = workloads.config3()
+        p3 = w3.path
+        plan3 = api.Plan(p3)
+        spec = plan3.init_spectra(w3.seed)
+        u3 = torch.from_numpy(w3.source_field().astype(np.complex64)).to(dev)
+        o3 = torch.empty((p3.realizations, p3.n, p3.n), dtype=torch.complex64, device=dev)
+        m3 = api.Moments(p3.n, p3.dx)
+        ex = w3.extra
+
+        def ar(i):
+            plan3.evolve(spec, w3.seed, i + 1, ex["alpha"], ex["shift_x"], ex["shift_y"])
+            plan3.propagate(u3, spectra=spec, out=o3)
+            m3.add(o3)
+
+        sec, per = timed_region(torch, ar, args.steps, args.warmup, binding, fams)
+        ss3 = p3.realizations * p3.num_screens
+        result["ar"] = {"value": ss3 / sec, "unit": "screen-steps/s", "ms_per_step": 1e3 * sec,
+                        "workload": w3.name + " (32 sequences, alpha=0.99, shift 0.5 px/step)",
+                        "seconds_for_1000_steps": 1000 * sec, "kernels": kernel_table(p3, per, False)}
+        plan3.close()
+        del spec
+
+    if args.only in ("all", "plain"):
+        H = fresnel_tables(torch, np, path, dev)
+        phi = torch.empty((path.realizations, path.num_screens, path.n, path.n), dtype=torch.float32, device=dev)
+
+        def plain(i):
+            u = plain_forward(torch, plan, path, u0, w.seed, i, H, phi)
+            moments.add(u)
+
+        sec, _ = timed_region(torch, plain, max(2, args.steps // 5), 2, binding, [])
+        # same screens, same physics: report the agreement of the two versions
+        fused = plan.propagate(u0, seed=w.seed, t=0)
+        ref = plain_forward(torch, plan, path, u0, w.seed, 0, H, phi)
+        diff = float(torch.linalg.vector_norm(fused - ref) / torch.linalg.vector_norm(ref))
+        result["plain_gpu"] = {"value": ss_per_step / sec, "unit": "screen-steps/s", "ms_per_step": 1e3 * sec,
+                               "kind": "one PyTorch op per kernel (torch.fft + elementwise), same screens",
+                               "rel_l2_vs_fused": diff}
+        if "value" in result:
+            result["speedup_vs_plain"] = result["value"] / result["plain_gpu"]["value"]
+        del phi, H
+
+    if args.only == "copy":
+        # calibration: the library's plain copy kernel (no screens, no diffraction) of known size
+        pc = workloads.Path(n=path.n, dx=path.dx, wavelength=path.wavelength, dz=(0.0,), cn2dz=(),
+                            realizations=path.realizations)
+        planc = api.Plan(pc)
+        src = torch.empty_like(u_out).copy_(u0.expand_as(u_out))
+        sec, per = timed_region(torch, lambda i: planc.propagate(src, out=u_out), args.steps, args.warmup, binding,
+                                fams)
+        result["copy"] = kernel_table(pc, per, False)
+        result["value"] = 0.0
+
+    if args.only == "all" and not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(w, args.cpu_pairs)
+
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,199 @@
+/*
+ * turpy.h -- C ABI of the MI355X (gfx950) split-step turbulence propagator.
+ *
+ * The library computes the data-parallel hot path of TurPy (arXiv 2604.07248):
+ * phase-screen synthesis from the modified von Karman PSD with Lane
+ * subharmonics, split-step Fresnel / angular-spectrum propagation of batched
+ * complex64 fields through those screens, AR(1) + frozen-flow evolution of the
+ * stored screen spectra, the adjoint of the propagation, ensemble statistics
+ * and the dual-domain two-mask receiver.
+ *
+ * Conventions shared by every call
+ *  - Arrays are row-major [batch][screen][y][x]; complex values are interleaved
+ *    (re, im) float pairs (complex64).  Index i0 is y, i1 is x; a pixel's
+ *    centred coordinate is (i - N/2) dx.
+ *  - All array arguments are DEVICE pointers owned by the caller (for example
+ *    PyTorch tensors), 16-byte aligned at least; nothing here allocates or frees
+ *    caller memory.  Plans own small device tables (twiddles, transfer-function
+ *    chirps, subharmonic phasors) that turpy_plan_destroy releases.
+ *  - Calls are asynchronous and stream-ordered on the given hipStream_t
+ *    (passed as void*; NULL means the default stream).  Input validation runs on
+ *    the host before anything is launched: on any non-OK status nothing has been
+ *    enqueued, and turpy_last_error() returns a message for this thread.
+ *  - Noise is Philox4x32-10 keyed by the 64-bit seed with counter
+ *    (e, t, j, tag<<28 | s): t time step, j realization pair, s screen, tag 1
+ *    main spectrum / 2 subharmonics / 3 AR innovation.  Realizations 2j and
+ *    2j+1 take the real and imaginary parts of one complex screen.
+ *  - Gradients follow PyTorch's convention for real losses:
+ *    g = dL/dRe(u) + i dL/dIm(u).
+ */
+#ifndef TURPY_H_
+#define TURPY_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TURPY_OK = 0,
+  TURPY_E_INVALID = 1,      /* malformed argument or descriptor              */
+  TURPY_E_UNSUPPORTED = 2,  /* well-formed but outside what is implemented   */
+  TURPY_E_ALIASING = 3,     /* a step exceeds the transfer-function sampling limit (Sec. 2.4, Eq. 7) */
+  TURPY_E_WORKSPACE = 4,    /* workspace NULL or smaller than turpy_workspace_size() */
+  TURPY_E_HIP = 5           /* a HIP runtime call failed (message has the HIP error) */
+} turpy_status;
+
+typedef enum { TURPY_TF_FRESNEL = 0, TURPY_TF_ANGULAR_SPECTRUM = 1 } turpy_tf_kind;
+
+/* Where the screens of a propagation come from. */
+typedef enum {
+  TURPY_SCREENS_SYNTH = 0,        /* synthesised from (seed, t) inside the passes (Eq. S16, Eq. 2-3) */
+  TURPY_SCREENS_MATERIALIZED = 1, /* float [R][M][N][N] radians supplied by the caller               */
+  TURPY_SCREENS_SPECTRA = 2       /* complex64 [ceil(R/2)][M][N][N] pair spectra (AR state, Eq. 5)   */
+} turpy_screen_src;
+
+/* Plan flags. */
+#define TURPY_ALLOW_ALIASING 1u   /* accept steps beyond the Eq. 7 limit */
+
+/* One propagation path (Sec. 2.1, Fig. 1A inputs). */
+typedef struct turpy_path {
+  int32_t n;                /* grid size N: power of two, 16..2048                              */
+  int32_t num_screens;      /* M >= 0                                                           */
+  double dx;                /* grid spacing [m], > 0                                            */
+  double wavelength;        /* vacuum wavelength [m], > 0                                       */
+  double n0;                /* mean refractive index, > 0                                       */
+  const double* dz;         /* HOST [M+1]: diffraction distance before screen i (i < M) and after the
+                               last screen (i = M), each >= 0; dz[i] for 0 < i < M must be > 0    */
+  const double* cn2dz;      /* HOST [M]: integral of Cn^2 over screen i's interval [m^(1/3)], >= 0 */
+  double l0;                /* inner scale [m]; <= 0 disables the inner-scale cutoff            */
+  double L0;                /* outer scale [m]; <= 0 or infinite disables it                    */
+  int32_t sh_levels;        /* Lane subharmonic levels 0..3 (scale 3 per level, Sec. 2.2)        */
+  int32_t tf_kind;          /* turpy_tf_kind                                                    */
+  int32_t inner_scale_conv; /* 0: fm = 1/l0 (Eq. S17 as printed, in cycles/m); 1: fm = 5.92/(2 pi l0) */
+  int64_t realizations;     /* R >= 1                                                           */
+} turpy_path;
+
+typedef struct turpy_plan turpy_plan;
+
+/* Operations for turpy_workspace_size. */
+typedef enum {
+  TURPY_OP_SCREEN_GENERATE = 0,
+  TURPY_OP_PROPAGATE = 1,
+  TURPY_OP_PROPAGATE_BACKWARD = 2,
+  TURPY_OP_EVOLVE = 3
+} turpy_op;
+
+/* Library version string (static storage). */
+const char* turpy_version(void);
+
+/* Message for the last non-OK status returned on this thread (static
+ * thread-local storage; empty string when none). */
+const char* turpy_last_error(void);
+
+/* Validate `path`, compute the per-screen scalars (Fried parameter r0_i from
+ * Eq. S18 and the PSD scale of Eq. S17), and build the FP64-derived tables on
+ * the current HIP device: FFT twiddles, per-distance Fresnel chirps
+ * exp(-i pi (lambda/n0) dz f^2) with exact FP64 range reduction, and the
+ * subharmonic phasors of Eq. 2.  The host arrays dz/cn2dz are copied; the
+ * caller may free them on return.  *out receives a plan owned by the caller
+ * (release with turpy_plan_destroy).  Errors: INVALID (NULL pointers, N not a
+ * power of two, non-finite or negative values), UNSUPPORTED (N outside 16..2048,
+ * sh_levels > 3, a zero interior distance), ALIASING (a distance beyond
+ * N dx^2 n0 / lambda, Eq. 7 with the Nyquist frequency, unless flags has
+ * TURPY_ALLOW_ALIASING), HIP. */
+turpy_status turpy_plan_create(turpy_plan** out, const turpy_path* path, uint32_t flags);
+turpy_status turpy_plan_destroy(turpy_plan* plan);
+
+/* Bytes of device workspace an operation needs for this plan (0 allowed). */
+turpy_status turpy_workspace_size(const turpy_plan* plan, int32_t op, size_t* bytes);
+
+/* Phase screens (App. B Eq. S16 with the Eq. S17 PSD, Sec. 2.2 Eq. 2-3, piston
+ * removed): writes float screens[R][M][N][N] in radians for time step t (0 for
+ * static screens).  `ws` must hold turpy_workspace_size(TURPY_OP_SCREEN_GENERATE). */
+turpy_status turpy_screen_generate(turpy_plan* plan, uint64_t seed, int64_t t, float* screens,
+                                   void* ws, size_t ws_bytes, void* stream);
+
+/* Forward split-step (Sec. 2.1 Eq. 1): for i < M, diffract by dz[i] and
+ * multiply by exp(i phi_i); finally diffract by dz[M].
+ *  u_in       complex64 [R][N][N] (u_in_stride = N*N) or one shared source
+ *             [N][N] (u_in_stride = 0).  Read only.  May equal u_out only when
+ *             u_in_stride = N*N.
+ *  src/screens_or_spectra  per turpy_screen_src (NULL for SYNTH).
+ *  u_out      complex64 [R][N][N], written.
+ *  checkpoints complex64 [R][M][N][N] or NULL: the field just after each
+ *             screen, for turpy_propagate_backward.
+ *  ws         turpy_workspace_size(TURPY_OP_PROPAGATE) bytes. */
+turpy_status turpy_propagate(turpy_plan* plan, uint64_t seed, int64_t t, const void* u_in,
+                             int64_t u_in_stride, int32_t src, const void* screens_or_spectra,
+                             void* u_out, void* checkpoints, void* ws, size_t ws_bytes, void* stream);
+
+/* Screen-spectrum evolution (Sec. 2.3): with t == 0 initialise
+ * spectra[ceil(R/2)][M][N][N] to the static main spectra of Eq. S16 (DC zero);
+ * with t >= 1 apply the frozen-flow shift of Eq. 4 by (shift_x, shift_y)
+ * pixels (= T v / dx) and then the AR(1) blend of Eq. 5 with innovation noise
+ * drawn at time step t.  0 <= alpha <= 1.  In place. */
+turpy_status turpy_evolve(turpy_plan* plan, uint64_t seed, int64_t t, double alpha, double shift_x,
+                          double shift_y, void* spectra, void* ws, size_t ws_bytes, void* stream);
+
+/* Adjoint of turpy_propagate with the same plan, seed, t and screens.
+ *  grad_u_out  complex64 [R][N][N], read only.
+ *  checkpoints complex64 [R][M][N][N] written by the forward call.
+ *  grad_u_in   complex64 [R][N][N] per realization (sum over R for a shared
+ *              source), or NULL.  Also used as the working buffer when
+ *              non-NULL; otherwise the workspace holds it.
+ *  grad_screens float [R][M][N][N] dL/dphi_i, or NULL.
+ *  ws          turpy_workspace_size(TURPY_OP_PROPAGATE_BACKWARD) bytes. */
+turpy_status turpy_propagate_backward(turpy_plan* plan, uint64_t seed, int64_t t, const void* grad_u_out,
+                                      const void* checkpoints, int32_t src, const void* screens_or_spectra,
+                                      void* grad_u_in, float* grad_screens, void* ws, size_t ws_bytes,
+                                      void* stream);
+
+/* Ensemble statistics of received fields (Sec. 3.2-3.3, Eq. S25).
+ *  If batch > 0: accumulate I = |u|^2 of u[batch][n][n] into
+ *  moments float [4][n][n] = (sum I, its compensation, sum I^2, its
+ *  compensation), Kahan-compensated; zero `moments` before the first batch.
+ *  If finalize != 0: with count = total realizations accumulated, write
+ *  si_map float [n][n] = m2/m1^2 - 1 (m = sums / count; may be NULL) and
+ *  summary double[4] (device) = (SI averaged over |x|,|y| < n dx / 4,
+ *  W_2nd = sqrt(2 sum r^2 m1 / sum m1), W_fit from a least-squares fit of
+ *  ln m1 = a - 2 r^2/W^2 over m1 >= e^-2 max m1, count). */
+turpy_status turpy_stats(int32_t n, double dx, int64_t batch, const void* u, float* moments,
+                         int64_t count, int32_t finalize, float* si_map, double* summary, void* stream);
+
+/* Dual-domain two-mask receiver (Sec. 2.5, Sec. 4.1):
+ *  U1 = A u exp(i theta1) (A: disc of `aperture_diameter` metres centred on
+ *  pixel (n/2, n/2)); Z = DFT{U1} exp(i theta2') with theta2' the natural-order
+ *  view of theta2 (theta2 stored centred, fftshift order);
+ *  u_out = IDFT{Z} (1/n^2 inverse).  u, u_out complex64 [batch][n][n];
+ *  theta1, theta2 float [n][n].  ws: turpy_receiver_workspace_size bytes. */
+turpy_status turpy_receiver_workspace_size(int32_t n, int64_t batch, size_t* bytes);
+turpy_status turpy_receiver(int32_t n, double dx, double aperture_diameter, int64_t batch, const void* u,
+                            const float* theta1, const float* theta2, void* u_out, void* ws,
+                            size_t ws_bytes, void* stream);
+
+/* Adjoint of turpy_receiver: given grad_out [batch][n][n] returns
+ * grad_u [batch][n][n] (or NULL), and dL/dtheta1, dL/dtheta2 [n][n] summed
+ * over the batch (theta2 gradient in centred order; either may be NULL). */
+turpy_status turpy_receiver_backward(int32_t n, double dx, double aperture_diameter, int64_t batch,
+                                     const void* u, const float* theta1, const float* theta2,
+                                     const void* grad_out, void* grad_u, float* grad_theta1,
+                                     float* grad_theta2, void* ws, size_t ws_bytes, void* stream);
+
+/* Per-kernel timing for benchmarking.  turpy_profile(1) clears the record and
+ * starts bracketing every kernel the library enqueues with a pair of HIP events
+ * on that kernel's stream; turpy_profile(0) stops recording.  Kernel families:
+ * "row_fwd", "row_bwd", "row_plain", "col", "synth", "sh", "evolve", "stats",
+ * "finalize", "copy".  turpy_profile_read waits for the recorded events and
+ * returns the launch count and summed duration (ms) of one family (zero when it
+ * never ran).  Host-side state, process-wide; not thread-safe. */
+turpy_status turpy_profile(int32_t enable);
+turpy_status turpy_profile_read(const char* family, int64_t* launches, double* total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TURPY_H_ */

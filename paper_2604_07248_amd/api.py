@@ -1,0 +1,187 @@
+"""PyTorch-facing wrapper of the HIP library: plans, tensors and streams.
+
+Everything numeric happens inside libturpy.so; this module only checks
+shapes, allocates output tensors and passes device pointers and the current
+HIP stream.
+"""
+
+import ctypes
+
+import torch
+
+from . import binding as B
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _need(t, dtype, shape, name):
+    if t.dtype != dtype or tuple(t.shape) != tuple(shape) or not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{name}: expected contiguous {dtype} {tuple(shape)} on the GPU, got "
+                         f"{t.dtype} {tuple(t.shape)} on {t.device}")
+
+
+class Plan:
+    """A propagation plan for one path (workloads.Path) on the current device."""
+
+    def __init__(self, path, flags=0, device=None):
+        self.path = path
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        with torch.cuda.device(self.device):
+            self.handle = B.plan_create(path, flags)
+        self.n, self.m, self.r = path.n, len(path.cn2dz), path.realizations
+        self.pairs = (self.r + 1) // 2
+        self._ws = {}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            B.plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace(self, op):
+        size = B.workspace_size(self.handle, op)
+        buf = self._ws.get(op)
+        if buf is None or buf.numel() < size:
+            buf = torch.empty(max(size, 256), dtype=torch.uint8, device=self.device)
+            self._ws[op] = buf
+        return buf, size
+
+    # -- screens -------------------------------------------------------------
+    def screens(self, seed, t=0, out=None):
+        """Phase screens float32 [R][M][N][N] (radians)."""
+        shape = (self.r, self.m, self.n, self.n)
+        out = torch.empty(shape, dtype=torch.float32, device=self.device) if out is None else out
+        _need(out, torch.float32, shape, "screens")
+        ws, size = self.workspace(B.OP_SCREEN_GENERATE)
+        B.screen_generate(self.handle, seed, t, _ptr(out), _ptr(ws), size, _stream())
+        return out
+
+    def init_spectra(self, seed):
+        """AR state complex64 [ceil(R/2)][M][N][N] at t = 0 (static main spectra)."""
+        spec = torch.empty((self.pairs, self.m, self.n, self.n), dtype=torch.complex64, device=self.device)
+        B.evolve(self.handle, seed, 0, 0.0, 0.0, 0.0, _ptr(spec), None, 0, _stream())
+        return spec
+
+    def evolve(self, spectra, seed, t, alpha, shift_x=0.0, shift_y=0.0):
+        _need(spectra, torch.complex64, (self.pairs, self.m, self.n, self.n), "spectra")
+        if t < 1:
+            raise ValueError("evolve: t must be >= 1 (t = 0 is init_spectra)")
+        B.evolve(self.handle, seed, t, alpha, shift_x, shift_y, _ptr(spectra), None, 0, _stream())
+        return spectra
+
+    # -- propagation -----------------------------------------------------------
+    def _source(self, u_in):
+        if u_in.dim() == 2:
+            _need(u_in, torch.complex64, (self.n, self.n), "u_in")
+            return 0
+        _need(u_in, torch.complex64, (self.r, self.n, self.n), "u_in")
+        return self.n * self.n
+
+    def _screen_src(self, screens, spectra):
+        if screens is not None and spectra is not None:
+            raise ValueError("give screens or spectra, not both")
+        if screens is not None:
+            _need(screens, torch.float32, (self.r, self.m, self.n, self.n), "screens")
+            return B.SCREENS_MATERIALIZED, screens
+        if spectra is not None:
+            _need(spectra, torch.complex64, (self.pairs, self.m, self.n, self.n), "spectra")
+            return B.SCREENS_SPECTRA, spectra
+        return B.SCREENS_SYNTH, None
+
+    def propagate(self, u_in, seed=0, t=0, screens=None, spectra=None, checkpoints=False, out=None):
+        """Forward split-step; returns u_out [R][N][N], and the checkpoints [R][M][N][N]
+        when `checkpoints` is True (allocated) or a tensor (filled)."""
+        stride = self._source(u_in)
+        src, sbuf = self._screen_src(screens, spectra)
+        shape = (self.r, self.n, self.n)
+        u_out = torch.empty(shape, dtype=torch.complex64, device=self.device) if out is None else out
+        _need(u_out, torch.complex64, shape, "u_out")
+        ck = None
+        if isinstance(checkpoints, torch.Tensor):
+            ck = checkpoints
+            _need(ck, torch.complex64, (self.r, self.m, self.n, self.n), "checkpoints")
+        elif checkpoints:
+            ck = torch.empty((self.r, self.m, self.n, self.n), dtype=torch.complex64, device=self.device)
+        ws, size = self.workspace(B.OP_PROPAGATE)
+        B.propagate(self.handle, seed, t, _ptr(u_in), stride, src, _ptr(sbuf), _ptr(u_out), _ptr(ck), _ptr(ws), size,
+                    _stream())
+        return (u_out, ck) if ck is not None else u_out
+
+    def propagate_backward(self, grad_out, checkpoints, seed=0, t=0, screens=None, spectra=None, want_input=True,
+                           want_screens=True):
+        shape = (self.r, self.n, self.n)
+        _need(grad_out, torch.complex64, shape, "grad_out")
+        src, sbuf = self._screen_src(screens, spectra)
+        if self.m > 0:
+            _need(checkpoints, torch.complex64, (self.r, self.m, self.n, self.n), "checkpoints")
+        g_in = torch.empty(shape, dtype=torch.complex64, device=self.device) if want_input else None
+        g_phi = (torch.empty((self.r, self.m, self.n, self.n), dtype=torch.float32, device=self.device)
+                 if want_screens else None)
+        ws, size = self.workspace(B.OP_PROPAGATE_BACKWARD)
+        B.propagate_backward(self.handle, seed, t, _ptr(grad_out), _ptr(checkpoints), src, _ptr(sbuf), _ptr(g_in),
+                             _ptr(g_phi), _ptr(ws), size, _stream())
+        return g_in, g_phi
+
+
+class Moments:
+    """Running ensemble moments of |U|^2 on the GPU (turpy_stats)."""
+
+    def __init__(self, n, dx, device=None):
+        self.n, self.dx = n, dx
+        self.device = torch.device(device) if device is not None else torch.device("cuda")
+        self.buf = torch.zeros((4, n, n), dtype=torch.float32, device=self.device)
+        self.count = 0
+
+    def add(self, u):
+        if u.dim() == 2:
+            u = u.unsqueeze(0)
+        _need(u, torch.complex64, (u.shape[0], self.n, self.n), "u")
+        B.stats(self.n, self.dx, u.shape[0], _ptr(u), _ptr(self.buf), 0, 0, None, None, _stream())
+        self.count += u.shape[0]
+
+    def finalize(self):
+        si = torch.empty((self.n, self.n), dtype=torch.float32, device=self.device)
+        summary = torch.empty(4, dtype=torch.float64, device=self.device)
+        B.stats(self.n, self.dx, 0, None, _ptr(self.buf), self.count, 1, _ptr(si), _ptr(summary), _stream())
+        s = summary.cpu().tolist()
+        return si, {"si_plane": s[0], "w_2nd": s[1], "w_fit": s[2], "count": int(s[3])}
+
+
+class Propagate(torch.autograd.Function):
+    """u_out = propagate(u_in, phi) with the hand-written adjoint as backward.
+
+    Fields are checkpointed at the screen planes only; the backward regenerates
+    synthesised screens from (seed, t).  `screens` may be None (synthesised) or a
+    float32 [R][M][N][N] tensor (materialised; receives dL/dphi)."""
+
+    @staticmethod
+    def forward(ctx, u_in, screens, plan, seed, t):
+        u_out, ck = plan.propagate(u_in.contiguous(), seed, t,
+                                   screens=screens.contiguous() if screens is not None else None, checkpoints=True)
+        ctx.plan, ctx.seed, ctx.t = plan, seed, t
+        ctx.shared = u_in.dim() == 2
+        ctx.save_for_backward(ck, screens)
+        return u_out
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        ck, screens = ctx.saved_tensors
+        plan = ctx.plan
+        want_in = ctx.needs_input_grad[0]
+        want_phi = ctx.needs_input_grad[1] or screens is None
+        g_in, g_phi = plan.propagate_backward(grad_out.contiguous(), ck, ctx.seed, ctx.t, screens=screens,
+                                              want_input=want_in, want_screens=want_phi and screens is not None)
+        if g_in is not None and ctx.shared:
+            g_in = g_in.sum(dim=0)
+        return g_in, (g_phi if screens is not None and ctx.needs_input_grad[1] else None), None, None, None

@@ -1,0 +1,173 @@
+"""Thin ctypes binding of libturpy.so (include/turpy.h).
+
+Argument marshalling only: every step of the path runs in the HIP library.
+PyTorch supplies device memory (tensors) and the stream.  Loading fails loudly
+when the library has not been built; there is no fallback.
+"""
+
+import ctypes
+import os
+from ctypes import POINTER, c_char_p, c_double, c_float, c_int32, c_int64, c_size_t, c_uint32, c_uint64, c_void_p
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libturpy.so")
+
+OK, E_INVALID, E_UNSUPPORTED, E_ALIASING, E_WORKSPACE, E_HIP = range(6)
+TF_FRESNEL, TF_ANGULAR_SPECTRUM = 0, 1
+SCREENS_SYNTH, SCREENS_MATERIALIZED, SCREENS_SPECTRA = 0, 1, 2
+ALLOW_ALIASING = 1
+OP_SCREEN_GENERATE, OP_PROPAGATE, OP_PROPAGATE_BACKWARD, OP_EVOLVE = range(4)
+
+# Every symbol the header declares (checked by the CPU tests).
+EXPORTS = [
+    "turpy_version", "turpy_last_error", "turpy_plan_create", "turpy_plan_destroy", "turpy_workspace_size",
+    "turpy_screen_generate", "turpy_propagate", "turpy_evolve", "turpy_propagate_backward", "turpy_stats",
+    "turpy_receiver_workspace_size", "turpy_receiver", "turpy_receiver_backward", "turpy_profile",
+    "turpy_profile_read",
+]
+
+
+class TurpyError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"turpy status {status}: {message}")
+        self.status = status
+
+
+class CPath(ctypes.Structure):
+    _fields_ = [
+        ("n", c_int32), ("num_screens", c_int32), ("dx", c_double), ("wavelength", c_double), ("n0", c_double),
+        ("dz", POINTER(c_double)), ("cn2dz", POINTER(c_double)), ("l0", c_double), ("L0", c_double),
+        ("sh_levels", c_int32), ("tf_kind", c_int32), ("inner_scale_conv", c_int32), ("realizations", c_int64),
+    ]
+
+
+_LIB = None
+
+
+def lib():
+    """Load libturpy.so once; raises if it is missing or cannot be loaded."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2604_07248_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        L.turpy_version.restype = c_char_p
+        L.turpy_last_error.restype = c_char_p
+        L.turpy_plan_create.argtypes = [POINTER(c_void_p), POINTER(CPath), c_uint32]
+        L.turpy_plan_destroy.argtypes = [c_void_p]
+        L.turpy_workspace_size.argtypes = [c_void_p, c_int32, POINTER(c_size_t)]
+        L.turpy_screen_generate.argtypes = [c_void_p, c_uint64, c_int64, c_void_p, c_void_p, c_size_t, c_void_p]
+        L.turpy_propagate.argtypes = [c_void_p, c_uint64, c_int64, c_void_p, c_int64, c_int32, c_void_p, c_void_p,
+                                      c_void_p, c_void_p, c_size_t, c_void_p]
+        L.turpy_evolve.argtypes = [c_void_p, c_uint64, c_int64, c_double, c_double, c_double, c_void_p, c_void_p,
+                                   c_size_t, c_void_p]
+        L.turpy_propagate_backward.argtypes = [c_void_p, c_uint64, c_int64, c_void_p, c_void_p, c_int32, c_void_p,
+                                               c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]
+        L.turpy_stats.argtypes = [c_int32, c_double, c_int64, c_void_p, c_void_p, c_int64, c_int32, c_void_p,
+                                  c_void_p, c_void_p]
+        L.turpy_receiver_workspace_size.argtypes = [c_int32, c_int64, POINTER(c_size_t)]
+        L.turpy_receiver.argtypes = [c_int32, c_double, c_double, c_int64, c_void_p, c_void_p, c_void_p, c_void_p,
+                                     c_void_p, c_size_t, c_void_p]
+        L.turpy_receiver_backward.argtypes = [c_int32, c_double, c_double, c_int64, c_void_p, c_void_p, c_void_p,
+                                              c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]
+        L.turpy_profile.argtypes = [c_int32]
+        L.turpy_profile_read.argtypes = [c_char_p, POINTER(c_int64), POINTER(c_double)]
+        for name in EXPORTS:
+            if name not in ("turpy_version", "turpy_last_error"):
+                getattr(L, name).restype = c_int32
+        _LIB = L
+    return _LIB
+
+
+def check(status):
+    if status != OK:
+        raise TurpyError(status, lib().turpy_last_error().decode())
+
+
+def last_error():
+    return lib().turpy_last_error().decode()
+
+
+def make_cpath(path):
+    """ctypes descriptor for a workloads.Path (the arrays stay referenced by the result)."""
+    m = len(path.cn2dz)
+    dz = (c_double * (m + 1))(*path.dz)
+    cn2 = (c_double * max(m, 1))(*(path.cn2dz if m else [0.0]))
+    cp = CPath(n=path.n, num_screens=m, dx=path.dx, wavelength=path.wavelength, n0=path.n0,
+               dz=ctypes.cast(dz, POINTER(c_double)), cn2dz=ctypes.cast(cn2, POINTER(c_double)),
+               l0=path.l0, L0=path.L0, sh_levels=path.sh_levels, tf_kind=path.tf_kind,
+               inner_scale_conv=path.inner_scale_conv, realizations=path.realizations)
+    cp._keep = (dz, cn2)
+    return cp
+
+
+def plan_create(path, flags=0):
+    cp = make_cpath(path)
+    handle = c_void_p()
+    check(lib().turpy_plan_create(ctypes.byref(handle), ctypes.byref(cp), flags))
+    return handle
+
+
+def plan_destroy(handle):
+    if handle:
+        check(lib().turpy_plan_destroy(handle))
+
+
+def workspace_size(handle, op):
+    out = c_size_t()
+    check(lib().turpy_workspace_size(handle, op, ctypes.byref(out)))
+    return out.value
+
+
+def screen_generate(handle, seed, t, screens_ptr, ws_ptr, ws_bytes, stream):
+    check(lib().turpy_screen_generate(handle, seed, t, screens_ptr, ws_ptr, ws_bytes, stream))
+
+
+def propagate(handle, seed, t, u_in_ptr, u_in_stride, src, screens_ptr, u_out_ptr, ckpt_ptr, ws_ptr, ws_bytes,
+              stream):
+    check(lib().turpy_propagate(handle, seed, t, u_in_ptr, u_in_stride, src, screens_ptr, u_out_ptr, ckpt_ptr,
+                                ws_ptr, ws_bytes, stream))
+
+
+def evolve(handle, seed, t, alpha, sx, sy, spectra_ptr, ws_ptr, ws_bytes, stream):
+    check(lib().turpy_evolve(handle, seed, t, alpha, sx, sy, spectra_ptr, ws_ptr, ws_bytes, stream))
+
+
+def propagate_backward(handle, seed, t, gout_ptr, ckpt_ptr, src, screens_ptr, gin_ptr, gscreens_ptr, ws_ptr,
+                       ws_bytes, stream):
+    check(lib().turpy_propagate_backward(handle, seed, t, gout_ptr, ckpt_ptr, src, screens_ptr, gin_ptr,
+                                         gscreens_ptr, ws_ptr, ws_bytes, stream))
+
+
+def stats(n, dx, batch, u_ptr, moments_ptr, count, finalize, si_ptr, summary_ptr, stream):
+    check(lib().turpy_stats(n, dx, batch, u_ptr, moments_ptr, count, finalize, si_ptr, summary_ptr, stream))
+
+
+def receiver_workspace_size(n, batch):
+    out = c_size_t()
+    check(lib().turpy_receiver_workspace_size(n, batch, ctypes.byref(out)))
+    return out.value
+
+
+def receiver(n, dx, diameter, batch, u_ptr, th1_ptr, th2_ptr, out_ptr, ws_ptr, ws_bytes, stream):
+    check(lib().turpy_receiver(n, dx, diameter, batch, u_ptr, th1_ptr, th2_ptr, out_ptr, ws_ptr, ws_bytes, stream))
+
+
+def receiver_backward(n, dx, diameter, batch, u_ptr, th1_ptr, th2_ptr, gout_ptr, gu_ptr, g1_ptr, g2_ptr, ws_ptr,
+                      ws_bytes, stream):
+    check(lib().turpy_receiver_backward(n, dx, diameter, batch, u_ptr, th1_ptr, th2_ptr, gout_ptr, gu_ptr, g1_ptr,
+                                        g2_ptr, ws_ptr, ws_bytes, stream))
+
+
+def profile(enable):
+    check(lib().turpy_profile(1 if enable else 0))
+
+
+def profile_read(family):
+    n, ms = c_int64(), c_double()
+    check(lib().turpy_profile_read(family.encode(), ctypes.byref(n), ctypes.byref(ms)))
+    return n.value, ms.value
+
+
+__all__ = [n for n in dir() if not n.startswith("_")]
+_ = (c_float,)

@@ -1,0 +1,701 @@
+// Host runtime of the C ABI declared in include/turpy.h: validation, plans
+// with FP64-generated tables, workspace layout and the pass schedule of each
+// entry point.  Every kernel is enqueued on the caller's stream; nothing here
+// synchronises except plan creation / destruction (table upload / free).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "turpy.h"
+
+using namespace turpy;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+turpy_status fail(turpy_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+turpy_status hip_fail(hipError_t e, const char* where) {
+  return fail(TURPY_E_HIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+#define TURPY_HIP(call, where)                 \
+  do {                                         \
+    hipError_t e_ = (call);                    \
+    if (e_ != hipSuccess) return hip_fail(e_, where); \
+  } while (0)
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kLog2e = 1.4426950408889634;
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+bool pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+
+// exp(2 pi i rev) with exact range reduction of rev in FP64.
+float2 phasor(double rev) {
+  rev -= std::rint(rev);
+  return make_float2(static_cast<float>(std::cos(2.0 * kPi * rev)), static_cast<float>(std::sin(2.0 * kPi * rev)));
+}
+
+int signed_bin(int k, int n) { return k < n / 2 ? k : k - n; }
+
+// Per-kernel event timing (turpy_profile).
+struct EventPair {
+  hipEvent_t start, stop;
+};
+struct Profiler {
+  bool on = false;
+  std::map<std::string, std::vector<EventPair>> live;
+  std::vector<EventPair> pool;
+  EventPair take() {
+    if (!pool.empty()) {
+      EventPair e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    EventPair e{};
+    (void)hipEventCreate(&e.start);
+    (void)hipEventCreate(&e.stop);
+    return e;
+  }
+  void recycle() {
+    for (auto& kv : live)
+      for (auto& e : kv.second) pool.push_back(e);
+    live.clear();
+  }
+};
+Profiler g_prof;
+
+// Launch `fn` (returning hipError_t) bracketed by events when profiling is on.
+template <class Fn>
+hipError_t timed(const char* family, hipStream_t st, Fn&& fn) {
+  if (!g_prof.on) return fn();
+  EventPair e = g_prof.take();
+  (void)hipEventRecord(e.start, st);
+  const hipError_t r = fn();
+  (void)hipEventRecord(e.stop, st);
+  g_prof.live[family].push_back(e);
+  return r;
+}
+
+}  // namespace
+
+struct turpy_plan {
+  int device = 0;
+  int n = 0, M = 0, sh_levels = 0, tf_kind = 0, conv = 0;
+  int64_t R = 0, P = 0;
+  double dx = 0, wavelength = 0, n0 = 1, l0 = 0, L0 = 0, df = 0;
+  std::vector<double> dz, cn2dz;
+  // per-screen synthesis constants
+  std::vector<float> amp_rev;   // sqrt(0.023) r0^(-5/6) df / (2 pi)
+  std::vector<float> amp_rad;   // sqrt(0.023) r0^(-5/6) df
+  float df2 = 0, inner = 0, f02 = 0;
+  float2 sh_mean_fac[3] = {};
+  // device tables (owned)
+  float2* d_tw = nullptr;        // [N]
+  float2* d_row = nullptr;       // [M+1][N] h_i[k]
+  float2* d_col = nullptr;       // [M+1][N] h_i[k] / N
+  float2* d_sh_phasor = nullptr; // [3][N]
+  float* d_sh_amp = nullptr;     // [M][3][2]
+  float* d_amp_rad = nullptr;    // [M]
+
+  size_t plane_bytes() const { return static_cast<size_t>(n) * n * sizeof(float2); }
+  size_t off_sh() const { return align_up(static_cast<size_t>(P) * plane_bytes()); }
+  size_t off_src() const {
+    return off_sh() + align_up(sh_levels > 0 ? static_cast<size_t>(P) * (M > 0 ? M : 1) * 32 * sizeof(float2) : 0);
+  }
+  size_t off_gbuf() const { return off_src() + align_up(plane_bytes()); }
+  size_t ws_forward() const { return off_gbuf(); }
+  size_t ws_backward() const { return off_gbuf() + align_up(static_cast<size_t>(R) * plane_bytes()); }
+};
+
+extern "C" {
+
+const char* turpy_version(void) { return "turpy-mi355x 0.1 (gfx950)"; }
+
+const char* turpy_last_error(void) { return g_last_error.c_str(); }
+
+turpy_status turpy_plan_create(turpy_plan** out, const turpy_path* p, uint32_t flags) {
+  if (!out || !p) return fail(TURPY_E_INVALID, "plan_create: NULL argument");
+  *out = nullptr;
+  if (!pow2(p->n)) return fail(TURPY_E_INVALID, "plan_create: n=%d is not a power of two", p->n);
+  if (p->n < 16 || p->n > 2048) return fail(TURPY_E_UNSUPPORTED, "plan_create: n=%d outside 16..2048", p->n);
+  if (p->num_screens < 0) return fail(TURPY_E_INVALID, "plan_create: num_screens < 0");
+  if (p->num_screens > (1 << 20)) return fail(TURPY_E_UNSUPPORTED, "plan_create: num_screens too large");
+  if (!(p->dx > 0) || !std::isfinite(p->dx)) return fail(TURPY_E_INVALID, "plan_create: dx must be > 0");
+  if (!(p->wavelength > 0) || !std::isfinite(p->wavelength))
+    return fail(TURPY_E_INVALID, "plan_create: wavelength must be > 0");
+  if (!(p->n0 > 0) || !std::isfinite(p->n0)) return fail(TURPY_E_INVALID, "plan_create: n0 must be > 0");
+  if (!p->dz) return fail(TURPY_E_INVALID, "plan_create: dz is NULL");
+  if (p->num_screens > 0 && !p->cn2dz) return fail(TURPY_E_INVALID, "plan_create: cn2dz is NULL");
+  if (p->sh_levels < 0 || p->sh_levels > 3)
+    return fail(TURPY_E_UNSUPPORTED, "plan_create: sh_levels=%d outside 0..3", p->sh_levels);
+  if (p->tf_kind != TURPY_TF_FRESNEL && p->tf_kind != TURPY_TF_ANGULAR_SPECTRUM)
+    return fail(TURPY_E_INVALID, "plan_create: unknown tf_kind %d", p->tf_kind);
+  if (p->inner_scale_conv != 0 && p->inner_scale_conv != 1)
+    return fail(TURPY_E_INVALID, "plan_create: inner_scale_conv must be 0 or 1");
+  if (p->realizations < 1 || p->realizations > (int64_t(1) << 31))
+    return fail(TURPY_E_INVALID, "plan_create: realizations=%lld out of range", (long long)p->realizations);
+  if (std::isnan(p->l0) || std::isnan(p->L0)) return fail(TURPY_E_INVALID, "plan_create: l0/L0 is NaN");
+  const int M = p->num_screens, n = p->n;
+  const double limit = n * p->dx * p->dx * p->n0 / p->wavelength;  // Eq. 7 at the Nyquist frequency
+  for (int i = 0; i <= M; ++i) {
+    const double d = p->dz[i];
+    if (!(d >= 0) || !std::isfinite(d)) return fail(TURPY_E_INVALID, "plan_create: dz[%d] must be >= 0", i);
+    if (i > 0 && i < M && d == 0)
+      return fail(TURPY_E_UNSUPPORTED, "plan_create: dz[%d] = 0 between two screens (merge them)", i);
+    if (d > limit && !(flags & TURPY_ALLOW_ALIASING))
+      return fail(TURPY_E_ALIASING, "plan_create: dz[%d] = %g m exceeds the sampling limit N dx^2 n0/lambda = %g m",
+                  i, d, limit);
+  }
+  for (int i = 0; i < M; ++i)
+    if (!(p->cn2dz[i] >= 0) || !std::isfinite(p->cn2dz[i]))
+      return fail(TURPY_E_INVALID, "plan_create: cn2dz[%d] must be >= 0", i);
+
+  turpy_plan* pl = new turpy_plan();
+  (void)hipGetDevice(&pl->device);
+  pl->n = n;
+  pl->M = M;
+  pl->sh_levels = p->sh_levels;
+  pl->tf_kind = p->tf_kind;
+  pl->conv = p->inner_scale_conv;
+  pl->R = p->realizations;
+  pl->P = (p->realizations + 1) / 2;
+  pl->dx = p->dx;
+  pl->wavelength = p->wavelength;
+  pl->n0 = p->n0;
+  pl->l0 = p->l0;
+  pl->L0 = p->L0;
+  pl->df = 1.0 / (n * p->dx);
+  pl->dz.assign(p->dz, p->dz + M + 1);
+  if (M > 0) pl->cn2dz.assign(p->cn2dz, p->cn2dz + M);
+
+  // PSD constants (Eq. S17, frequencies in cycles/m)
+  const double df = pl->df;
+  double fm2 = 0.0;  // 0: no inner-scale cutoff
+  if (p->l0 > 0) {
+    const double fm = p->inner_scale_conv == 1 ? 5.92 / (2.0 * kPi * p->l0) : 1.0 / p->l0;
+    fm2 = fm * fm;
+  }
+  const double f0 = (std::isfinite(p->L0) && p->L0 > 0) ? 1.0 / p->L0 : 0.0;
+  pl->df2 = static_cast<float>(df * df);
+  pl->inner = fm2 > 0 ? static_cast<float>(kLog2e / (2.0 * fm2)) : 0.0f;
+  pl->f02 = static_cast<float>(f0 * f0);
+  const double k = 2.0 * kPi * p->n0 / p->wavelength;
+  auto psd = [&](double f2, double r0inv53) {  // W(f^2) of Eq. S17
+    const double inner = fm2 > 0 ? std::exp(-f2 / fm2) : 1.0;
+    return 0.023 * r0inv53 * inner / std::pow(f2 + f0 * f0, 11.0 / 6.0);
+  };
+  std::vector<float> sh_amp(static_cast<size_t>(std::max(M, 1)) * 6, 0.0f);
+  for (int s = 0; s < M; ++s) {
+    // Eq. S18: r0 = (0.423 k^2 cn2dz)^(-3/5); r0^(-5/3) = 0.423 k^2 cn2dz
+    const double r0inv53 = 0.423 * k * k * p->cn2dz[s];
+    const double a = std::sqrt(0.023 * r0inv53) * df;  // sqrt(0.023) r0^(-5/6) df
+    pl->amp_rad.push_back(static_cast<float>(a));
+    pl->amp_rev.push_back(static_cast<float>(a / (2.0 * kPi)));
+    for (int lv = 0; lv < 3; ++lv) {
+      const double dfp = df / std::pow(3.0, lv + 1);
+      for (int d = 0; d < 2; ++d) {
+        const double f2 = (d + 1) * dfp * dfp;
+        sh_amp[(static_cast<size_t>(s) * 3 + lv) * 2 + d] =
+            static_cast<float>(std::sqrt(psd(f2, r0inv53)) * dfp / (2.0 * kPi));
+      }
+    }
+  }
+
+  // FP64-generated tables
+  std::vector<float2> tw(n), row(static_cast<size_t>(M + 1) * n), col(static_cast<size_t>(M + 1) * n),
+      shp(static_cast<size_t>(3) * n);
+  for (int i = 0; i < n; ++i) tw[i] = phasor(-static_cast<double>(i) / n);
+  for (int s = 0; s <= M; ++s) {
+    // h(k) = exp(-i pi (lambda/n0) dz f_k^2): revolutions -(lambda/n0) dz df^2 k^2 / 2
+    const double a = (p->wavelength / p->n0) * pl->dz[s] * df * df * 0.5;
+    for (int kk = 0; kk < n; ++kk) {
+      const double kh = signed_bin(kk, n);
+      const float2 h = phasor(-a * kh * kh);
+      row[static_cast<size_t>(s) * n + kk] = h;
+      col[static_cast<size_t>(s) * n + kk] = make_float2(h.x / n, h.y / n);
+    }
+  }
+  for (int lv = 0; lv < 3; ++lv) {
+    const double scale = 1.0 / (static_cast<double>(n) * std::pow(3.0, lv + 1));
+    double mr = 0, mi = 0;
+    for (int i = 0; i < n; ++i) {
+      const double rev = (i - n / 2) * scale;
+      shp[static_cast<size_t>(lv) * n + i] = phasor(rev);
+      mr += std::cos(2.0 * kPi * rev);
+      mi += std::sin(2.0 * kPi * rev);
+    }
+    pl->sh_mean_fac[lv] = make_float2(static_cast<float>(mr / n), static_cast<float>(mi / n));
+  }
+  auto upload = [&](auto** dst, const void* src, size_t bytes) -> hipError_t {
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(dst), bytes);
+    if (e != hipSuccess) return e;
+    return hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+  };
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = upload(&pl->d_tw, tw.data(), tw.size() * sizeof(float2));
+  if (e == hipSuccess) e = upload(&pl->d_row, row.data(), row.size() * sizeof(float2));
+  if (e == hipSuccess) e = upload(&pl->d_col, col.data(), col.size() * sizeof(float2));
+  if (e == hipSuccess) e = upload(&pl->d_sh_phasor, shp.data(), shp.size() * sizeof(float2));
+  if (e == hipSuccess) e = upload(&pl->d_sh_amp, sh_amp.data(), sh_amp.size() * sizeof(float));
+  std::vector<float> amp_rad = pl->amp_rad;
+  if (amp_rad.empty()) amp_rad.push_back(0.0f);
+  if (e == hipSuccess) e = upload(&pl->d_amp_rad, amp_rad.data(), amp_rad.size() * sizeof(float));
+  if (e != hipSuccess) {
+    turpy_plan_destroy(pl);
+    return hip_fail(e, "plan_create: table upload");
+  }
+  *out = pl;
+  return TURPY_OK;
+}
+
+turpy_status turpy_plan_destroy(turpy_plan* pl) {
+  if (!pl) return TURPY_OK;
+  (void)hipFree(pl->d_tw);
+  (void)hipFree(pl->d_row);
+  (void)hipFree(pl->d_col);
+  (void)hipFree(pl->d_sh_phasor);
+  (void)hipFree(pl->d_sh_amp);
+  (void)hipFree(pl->d_amp_rad);
+  delete pl;
+  return TURPY_OK;
+}
+
+turpy_status turpy_workspace_size(const turpy_plan* pl, int32_t op, size_t* bytes) {
+  if (!pl || !bytes) return fail(TURPY_E_INVALID, "workspace_size: NULL argument");
+  switch (op) {
+    case TURPY_OP_SCREEN_GENERATE:
+    case TURPY_OP_PROPAGATE: *bytes = pl->ws_forward(); return TURPY_OK;
+    case TURPY_OP_PROPAGATE_BACKWARD: *bytes = pl->ws_backward(); return TURPY_OK;
+    case TURPY_OP_EVOLVE: *bytes = 0; return TURPY_OK;
+    default: return fail(TURPY_E_INVALID, "workspace_size: unknown op %d", op);
+  }
+}
+
+}  // extern "C"
+
+namespace {
+
+struct Ws {
+  float2* scratch;
+  float2* sh;
+  float2* src;
+  float2* gbuf;
+};
+
+Ws carve(const turpy_plan* pl, void* ws) {
+  char* b = static_cast<char*>(ws);
+  return Ws{reinterpret_cast<float2*>(b), reinterpret_cast<float2*>(b + pl->off_sh()),
+            reinterpret_cast<float2*>(b + pl->off_src()), reinterpret_cast<float2*>(b + pl->off_gbuf())};
+}
+
+void key_of(uint64_t seed, uint32_t* k0, uint32_t* k1) {
+  *k0 = static_cast<uint32_t>(seed & 0xFFFFFFFFu);
+  *k1 = static_cast<uint32_t>(seed >> 32);
+}
+
+turpy_status check_t(int64_t t) {
+  if (t < 0 || t > 0xFFFFFFFFll) return fail(TURPY_E_INVALID, "time step t=%lld out of range", (long long)t);
+  return TURPY_OK;
+}
+
+RowArgs base_row(const turpy_plan* pl) {
+  RowArgs a{};
+  a.tw = pl->d_tw;
+  a.R = pl->R;
+  a.scale = 1.0f;
+  a.M = pl->M;
+  a.sh_phasor = pl->d_sh_phasor;
+  return a;
+}
+
+const char* row_family(const RowArgs& a) {
+  if (a.screen_mode == ROW_NO_SCREEN) return "row_plain";
+  return a.backward ? "row_bwd" : "row_fwd";
+}
+
+ColArgs col_args(const turpy_plan* pl, int step, const float2* in, int64_t in_stride, float2* out, int64_t R,
+                 bool adjoint) {
+  ColArgs c{};
+  c.tw = pl->d_tw;
+  c.in = in;
+  c.in_stride = in_stride;
+  c.out = out;
+  c.R = R;
+  c.table = pl->d_col + static_cast<size_t>(step) * pl->n;
+  c.conj_table = adjoint ? 1 : 0;
+  c.angular = pl->tf_kind == TURPY_TF_ANGULAR_SPECTRUM ? 1 : 0;
+  c.dz = pl->dz[step];
+  c.k = 2.0 * kPi * pl->n0 / pl->wavelength;
+  c.df = pl->df;
+  return c;
+}
+
+// Enqueue the column half of screen s into ws.scratch (noise or stored spectra).
+hipError_t enqueue_screen_col(const turpy_plan* pl, uint64_t seed, uint32_t t, int s, const float2* spectra,
+                              const Ws& w, hipStream_t st) {
+  SynthArgs a{};
+  a.tw = pl->d_tw;
+  a.scratch = w.scratch;
+  a.P = pl->P;
+  key_of(seed, &a.key0, &a.key1);
+  a.t = t;
+  a.screen = static_cast<uint32_t>(s);
+  a.tag = TAG_MAIN;
+  a.amp = pl->amp_rev[s];
+  a.df2 = pl->df2;
+  a.inner = pl->inner;
+  a.f02 = pl->f02;
+  a.spectra = spectra;
+  a.M = pl->M;
+  return timed("synth", st, [&] { return launch_synth(pl->n, a, st); });
+}
+
+hipError_t enqueue_sh(const turpy_plan* pl, uint64_t seed, uint32_t t, const Ws& w, hipStream_t st) {
+  ShArgs a{};
+  a.sh = w.sh;
+  a.P = pl->P;
+  a.M = pl->M;
+  a.levels = pl->sh_levels;
+  key_of(seed, &a.key0, &a.key1);
+  a.t = t;
+  a.amp = pl->d_sh_amp;
+  for (int i = 0; i < 3; ++i) a.mean_fac[i] = pl->sh_mean_fac[i];
+  return timed("sh", st, [&] { return launch_sh(a, st); });
+}
+
+// Fill the screen fields of a row pass for screen s.
+turpy_status screen_fields(const turpy_plan* pl, int32_t src, const void* screens_or_spectra, const Ws& w,
+                           int s, RowArgs* a) {
+  a->screen = s;
+  if (src == TURPY_SCREENS_MATERIALIZED) {
+    a->screen_mode = ROW_MATERIALIZED;
+    a->screens = static_cast<const float*>(screens_or_spectra);
+  } else {
+    a->screen_mode = ROW_SCRATCH;
+    a->scratch = w.scratch;
+    a->sh_levels = src == TURPY_SCREENS_SYNTH ? pl->sh_levels : 0;
+    a->sh = w.sh;
+  }
+  return TURPY_OK;
+}
+
+turpy_status check_src(const turpy_plan* pl, int32_t src, const void* screens_or_spectra) {
+  if (src != TURPY_SCREENS_SYNTH && src != TURPY_SCREENS_MATERIALIZED && src != TURPY_SCREENS_SPECTRA)
+    return fail(TURPY_E_INVALID, "unknown screen source %d", src);
+  if (src != TURPY_SCREENS_SYNTH && pl->M > 0 && !screens_or_spectra)
+    return fail(TURPY_E_INVALID, "screen source %d needs a screens/spectra pointer", src);
+  return TURPY_OK;
+}
+
+turpy_status check_device(const turpy_plan* pl) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != pl->device)
+    return fail(TURPY_E_INVALID, "plan was created on device %d but device %d is current", pl->device, dev);
+  return TURPY_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+turpy_status turpy_screen_generate(turpy_plan* pl, uint64_t seed, int64_t t, float* screens, void* ws,
+                                   size_t ws_bytes, void* stream) {
+  if (!pl || !screens) return fail(TURPY_E_INVALID, "screen_generate: NULL argument");
+  if (turpy_status st = check_t(t)) return st;
+  if (turpy_status st = check_device(pl)) return st;
+  if (pl->M == 0) return TURPY_OK;
+  if (!ws || ws_bytes < pl->ws_forward())
+    return fail(TURPY_E_WORKSPACE, "screen_generate: workspace %zu < %zu bytes", ws_bytes, pl->ws_forward());
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const Ws w = carve(pl, ws);
+  if (pl->sh_levels > 0) TURPY_HIP(enqueue_sh(pl, seed, static_cast<uint32_t>(t), w, st), "screen_generate: sh");
+  for (int s = 0; s < pl->M; ++s) {
+    TURPY_HIP(enqueue_screen_col(pl, seed, static_cast<uint32_t>(t), s, nullptr, w, st), "screen_generate: col");
+    RowArgs a = base_row(pl);
+    screen_fields(pl, TURPY_SCREENS_SYNTH, nullptr, w, s, &a);
+    a.screen_mode = ROW_SCRATCH;
+    a.in = nullptr;  // no field: the row kernel only emits the phases
+    a.phase_out = screens;
+    TURPY_HIP(timed(row_family(a), st, [&] { return launch_row(pl->n, a, pl->P, st); }), "screen_generate: row");
+  }
+  return TURPY_OK;
+}
+
+turpy_status turpy_propagate(turpy_plan* pl, uint64_t seed, int64_t t, const void* u_in, int64_t u_in_stride,
+                             int32_t src, const void* screens_or_spectra, void* u_out, void* checkpoints, void* ws,
+                             size_t ws_bytes, void* stream) {
+  if (!pl || !u_in || !u_out) return fail(TURPY_E_INVALID, "propagate: NULL argument");
+  if (turpy_status s_ = check_t(t)) return s_;
+  if (turpy_status s_ = check_device(pl)) return s_;
+  if (turpy_status s_ = check_src(pl, src, screens_or_spectra)) return s_;
+  const int64_t plane = static_cast<int64_t>(pl->n) * pl->n;
+  if (u_in_stride != 0 && u_in_stride != plane)
+    return fail(TURPY_E_INVALID, "propagate: u_in_stride must be 0 or N*N");
+  if (u_in_stride == 0 && u_in == u_out && pl->R > 1)
+    return fail(TURPY_E_INVALID, "propagate: a shared source cannot alias u_out");
+  if (!ws || ws_bytes < pl->ws_forward())
+    return fail(TURPY_E_WORKSPACE, "propagate: workspace %zu < %zu bytes", ws_bytes, pl->ws_forward());
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const Ws w = carve(pl, ws);
+  const int n = pl->n, M = pl->M;
+  const float inv_n = 1.0f / n;
+  const float2* uin = static_cast<const float2*>(u_in);
+  float2* uout = static_cast<float2*>(u_out);
+  const float2* spectra = src == TURPY_SCREENS_SPECTRA ? static_cast<const float2*>(screens_or_spectra) : nullptr;
+
+  if (src == TURPY_SCREENS_SYNTH && pl->sh_levels > 0 && M > 0)
+    TURPY_HIP(enqueue_sh(pl, seed, static_cast<uint32_t>(t), w, st), "propagate: sh");
+
+  const float2* cur = uin;
+  int64_t cur_stride = u_in_stride;
+  bool spectral = false;
+  if (pl->dz[0] > 0) {
+    // row transform of the source (x h_0(k1)), then the first column pass
+    RowArgs a = base_row(pl);
+    a.in = uin;
+    a.in_stride = u_in_stride;
+    a.out_spectral = 1;
+    a.post = pl->d_row;
+    float2* dst = uout;
+    int64_t rows_r = pl->R;
+    if (u_in_stride == 0) {
+      dst = w.src;
+      rows_r = 1;
+    }
+    a.out = dst;
+    a.R = rows_r;
+    TURPY_HIP(timed(row_family(a), st, [&] { return launch_row(n, a, (rows_r + 1) / 2, st); }), "propagate: source row transform");
+    ColArgs c = col_args(pl, 0, dst, u_in_stride == 0 ? 0 : plane, uout, pl->R, false);
+    TURPY_HIP(timed("col", st, [&] { return launch_col(n, c, st); }), "propagate: column pass 0");
+    cur = uout;
+    cur_stride = plane;
+    spectral = true;
+  }
+  for (int s = 0; s < M; ++s) {
+    if (src != TURPY_SCREENS_MATERIALIZED)
+      TURPY_HIP(enqueue_screen_col(pl, seed, static_cast<uint32_t>(t), s, spectra, w, st), "propagate: screen col");
+    const bool out_spec = pl->dz[s + 1] > 0;
+    RowArgs a = base_row(pl);
+    a.in = cur;
+    a.in_stride = cur_stride;
+    a.out = uout;
+    a.in_spectral = spectral ? 1 : 0;
+    a.out_spectral = out_spec ? 1 : 0;
+    a.post = out_spec ? pl->d_row + static_cast<size_t>(s + 1) * n : nullptr;
+    a.scale = spectral ? inv_n : 1.0f;
+    screen_fields(pl, src, screens_or_spectra, w, s, &a);
+    a.ckpt_out = static_cast<float2*>(checkpoints);
+    TURPY_HIP(timed(row_family(a), st, [&] { return launch_row(n, a, pl->P, st); }), "propagate: row pass");
+    cur = uout;
+    cur_stride = plane;
+    spectral = out_spec;
+    if (out_spec) {
+      ColArgs c = col_args(pl, s + 1, uout, plane, uout, pl->R, false);
+      TURPY_HIP(timed("col", st, [&] { return launch_col(n, c, st); }), "propagate: column pass");
+    }
+  }
+  if (spectral) {
+    RowArgs a = base_row(pl);
+    a.in = uout;
+    a.in_stride = plane;
+    a.out = uout;
+    a.in_spectral = 1;
+    a.scale = inv_n;
+    TURPY_HIP(timed(row_family(a), st, [&] { return launch_row(n, a, pl->P, st); }), "propagate: final row pass");
+  } else if (M == 0) {
+    TURPY_HIP(timed("copy", st, [&] { return launch_copy(uin, u_in_stride, uout, plane, pl->R, st); }), "propagate: copy");
+  }
+  return TURPY_OK;
+}
+
+turpy_status turpy_propagate_backward(turpy_plan* pl, uint64_t seed, int64_t t, const void* grad_u_out,
+                                      const void* checkpoints, int32_t src, const void* screens_or_spectra,
+                                      void* grad_u_in, float* grad_screens, void* ws, size_t ws_bytes,
+                                      void* stream) {
+  if (!pl || !grad_u_out) return fail(TURPY_E_INVALID, "propagate_backward: NULL argument");
+  if (turpy_status s_ = check_t(t)) return s_;
+  if (turpy_status s_ = check_device(pl)) return s_;
+  if (turpy_status s_ = check_src(pl, src, screens_or_spectra)) return s_;
+  if (pl->M > 0 && !checkpoints) return fail(TURPY_E_INVALID, "propagate_backward: checkpoints are required");
+  if (!ws || ws_bytes < pl->ws_backward())
+    return fail(TURPY_E_WORKSPACE, "propagate_backward: workspace %zu < %zu bytes", ws_bytes, pl->ws_backward());
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const Ws w = carve(pl, ws);
+  const int n = pl->n, M = pl->M;
+  const int64_t plane = static_cast<int64_t>(n) * n;
+  const float inv_n = 1.0f / n;
+  float2* g = grad_u_in ? static_cast<float2*>(grad_u_in) : w.gbuf;
+  const float2* gout = static_cast<const float2*>(grad_u_out);
+  const float2* spectra = src == TURPY_SCREENS_SPECTRA ? static_cast<const float2*>(screens_or_spectra) : nullptr;
+
+  if (src == TURPY_SCREENS_SYNTH && pl->sh_levels > 0 && M > 0)
+    TURPY_HIP(enqueue_sh(pl, seed, static_cast<uint32_t>(t), w, st), "propagate_backward: sh");
+
+  const float2* cur = gout;
+  bool spectral = false;
+  if (pl->dz[M] > 0) {
+    RowArgs a = base_row(pl);  // adjoint of the final (1/N) inverse row transform
+    a.in = gout;
+    a.in_stride = plane;
+    a.out = g;
+    a.out_spectral = 1;
+    a.scale = inv_n;
+    TURPY_HIP(timed(row_family(a), st, [&] { return launch_row(n, a, pl->P, st); }), "propagate_backward: first row pass");
+    ColArgs c = col_args(pl, M, g, plane, g, pl->R, true);
+    TURPY_HIP(timed("col", st, [&] { return launch_col(n, c, st); }), "propagate_backward: column pass");
+    cur = g;
+    spectral = true;
+  }
+  for (int s = M - 1; s >= 0; --s) {
+    if (src != TURPY_SCREENS_MATERIALIZED)
+      TURPY_HIP(enqueue_screen_col(pl, seed, static_cast<uint32_t>(t), s, spectra, w, st),
+                "propagate_backward: screen col");
+    const bool out_spec = pl->dz[s] > 0;
+    RowArgs a = base_row(pl);
+    a.in = cur;
+    a.in_stride = plane;
+    a.out = g;
+    a.in_spectral = spectral ? 1 : 0;
+    a.pre = spectral ? pl->d_row + static_cast<size_t>(s + 1) * n : nullptr;
+    a.conj_tables = 1;
+    a.out_spectral = out_spec ? 1 : 0;
+    a.scale = out_spec ? inv_n : 1.0f;
+    screen_fields(pl, src, screens_or_spectra, w, s, &a);
+    a.backward = 1;
+    a.ckpt_in = static_cast<const float2*>(checkpoints);
+    a.grad_screens = grad_screens;
+    TURPY_HIP(timed(row_family(a), st, [&] { return launch_row(n, a, pl->P, st); }), "propagate_backward: row pass");
+    cur = g;
+    spectral = out_spec;
+    if (out_spec) {
+      ColArgs c = col_args(pl, s, g, plane, g, pl->R, true);
+      TURPY_HIP(timed("col", st, [&] { return launch_col(n, c, st); }), "propagate_backward: column pass");
+    }
+  }
+  if (spectral) {
+    RowArgs a = base_row(pl);  // adjoint of the source row transform: conj h_0, unnormalised inverse
+    a.in = g;
+    a.in_stride = plane;
+    a.out = g;
+    a.in_spectral = 1;
+    a.pre = pl->d_row;
+    a.conj_tables = 1;
+    TURPY_HIP(timed(row_family(a), st, [&] { return launch_row(n, a, pl->P, st); }), "propagate_backward: last row pass");
+  } else if (M == 0) {
+    TURPY_HIP(timed("copy", st, [&] { return launch_copy(gout, plane, g, plane, pl->R, st); }), "propagate_backward: copy");
+  }
+  return TURPY_OK;
+}
+
+turpy_status turpy_evolve(turpy_plan* pl, uint64_t seed, int64_t t, double alpha, double shift_x, double shift_y,
+                          void* spectra, void* ws, size_t ws_bytes, void* stream) {
+  (void)ws;
+  (void)ws_bytes;
+  if (!pl || !spectra) return fail(TURPY_E_INVALID, "evolve: NULL argument");
+  if (turpy_status s_ = check_t(t)) return s_;
+  if (turpy_status s_ = check_device(pl)) return s_;
+  if (!(alpha >= 0.0 && alpha <= 1.0)) return fail(TURPY_E_INVALID, "evolve: alpha must be in [0, 1]");
+  if (!std::isfinite(shift_x) || !std::isfinite(shift_y)) return fail(TURPY_E_INVALID, "evolve: non-finite shift");
+  if (pl->M == 0) return TURPY_OK;
+  EvolveArgs a{};
+  a.spectra = static_cast<float2*>(spectra);
+  a.P = pl->P;
+  a.M = pl->M;
+  a.n = pl->n;
+  key_of(seed, &a.key0, &a.key1);
+  a.t = static_cast<uint32_t>(t);
+  a.init = t == 0 ? 1 : 0;
+  a.tag = t == 0 ? TAG_MAIN : TAG_AR;
+  a.alpha = alpha;
+  a.sx = shift_x;
+  a.sy = shift_y;
+  a.amp = pl->d_amp_rad;
+  a.df2 = pl->df2;
+  a.inner = pl->inner;
+  a.f02 = pl->f02;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  TURPY_HIP(timed("evolve", st, [&] { return launch_evolve(a, st); }), "evolve");
+  return TURPY_OK;
+}
+
+turpy_status turpy_stats(int32_t n, double dx, int64_t batch, const void* u, float* moments, int64_t count,
+                         int32_t finalize, float* si_map, double* summary, void* stream) {
+  if (n < 1 || n > 65536) return fail(TURPY_E_INVALID, "stats: n=%d out of range", n);
+  if (!moments) return fail(TURPY_E_INVALID, "stats: moments is NULL");
+  if (batch < 0) return fail(TURPY_E_INVALID, "stats: batch < 0");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (batch > 0) {
+    if (!u) return fail(TURPY_E_INVALID, "stats: u is NULL");
+    StatsArgs a{static_cast<const float2*>(u), batch, n, moments};
+    TURPY_HIP(timed("stats", st, [&] { return launch_stats(a, st); }), "stats: accumulate");
+  }
+  if (finalize) {
+    if (!summary) return fail(TURPY_E_INVALID, "stats: summary is NULL");
+    if (count < 1) return fail(TURPY_E_INVALID, "stats: count must be >= 1 to finalize");
+    if (!(dx > 0)) return fail(TURPY_E_INVALID, "stats: dx must be > 0");
+    FinalizeArgs a{moments, n, dx, static_cast<double>(count), si_map, summary};
+    TURPY_HIP(timed("finalize", st, [&] { return launch_finalize(a, st); }), "stats: finalize");
+  }
+  return TURPY_OK;
+}
+
+turpy_status turpy_profile(int32_t enable) {
+  g_prof.recycle();
+  g_prof.on = enable != 0;
+  return TURPY_OK;
+}
+
+turpy_status turpy_profile_read(const char* family, int64_t* launches, double* total_ms) {
+  if (!family || !launches || !total_ms) return fail(TURPY_E_INVALID, "profile_read: NULL argument");
+  *launches = 0;
+  *total_ms = 0.0;
+  auto it = g_prof.live.find(family);
+  if (it == g_prof.live.end()) return TURPY_OK;
+  for (auto& e : it->second) {
+    TURPY_HIP(hipEventSynchronize(e.stop), "profile_read");
+    float ms = 0.0f;
+    TURPY_HIP(hipEventElapsedTime(&ms, e.start, e.stop), "profile_read");
+    *total_ms += ms;
+    ++*launches;
+  }
+  return TURPY_OK;
+}
+
+turpy_status turpy_receiver_workspace_size(int32_t n, int64_t batch, size_t* bytes) {
+  (void)n;
+  (void)batch;
+  if (!bytes) return fail(TURPY_E_INVALID, "receiver_workspace_size: NULL argument");
+  *bytes = 0;
+  return fail(TURPY_E_UNSUPPORTED, "receiver: not built yet");
+}
+
+turpy_status turpy_receiver(int32_t, double, double, int64_t, const void*, const float*, const float*, void*, void*,
+                            size_t, void*) {
+  return fail(TURPY_E_UNSUPPORTED, "receiver: not built yet");
+}
+
+turpy_status turpy_receiver_backward(int32_t, double, double, int64_t, const void*, const float*, const float*,
+                                     const void*, void*, float*, float*, void*, size_t, void*) {
+  return fail(TURPY_E_UNSUPPORTED, "receiver_backward: not built yet");
+}
+
+}  // extern "C"

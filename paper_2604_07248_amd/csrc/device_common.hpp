@@ -1,0 +1,70 @@
+// Device helpers for gfx950: complex arithmetic, the Philox4x32-10 generator,
+// Box-Muller normals and revolution-based sine/cosine.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace turpy {
+
+__device__ __forceinline__ float2 c_add(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 c_sub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 c_mul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a * conj(b)
+__device__ __forceinline__ float2 c_mulc(float2 a, float2 b) {
+  return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+__device__ __forceinline__ float2 c_scale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64 products
+// with the multipliers 0xD2511F53 / 0xCD9E8D57, key advanced by the Weyl
+// constants 0x9E3779B9 / 0xBB67AE85 between rounds.
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int i = 0; i < 10; ++i) {
+    if (i > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint64_t p0 = static_cast<uint64_t>(0xD2511F53u) * c.x;
+    const uint64_t p1 = static_cast<uint64_t>(0xCD9E8D57u) * c.z;
+    c = make_uint4(static_cast<uint32_t>(p1 >> 32) ^ c.y ^ k0, static_cast<uint32_t>(p1),
+                   static_cast<uint32_t>(p0 >> 32) ^ c.w ^ k1, static_cast<uint32_t>(p0));
+  }
+  return c;
+}
+
+// Uniform in (0, 1): (floor(v / 512) + 1/2) * 2^-23, exact in FP32.
+__device__ __forceinline__ float u01(uint32_t v) {
+  return (static_cast<float>(v >> 9) + 0.5f) * 0x1p-23f;
+}
+
+// sin / cos of 2*pi*x for |x| <= 256 revolutions (hardware transcendental units
+// take their argument in revolutions).  The argument is first reduced to
+// [-1/2, 1/2] exactly.
+__device__ __forceinline__ void sincos_rev(float x, float* s, float* c) {
+  const float r = x - rintf(x);
+  *s = __builtin_amdgcn_sinf(r);
+  *c = __builtin_amdgcn_cosf(r);
+}
+
+// Complex unit-variance-per-component normal from two words:
+// rho = sqrt(-2 ln u(va)), theta = 2 pi u(vb).
+__device__ __forceinline__ float2 box_muller(uint32_t va, uint32_t vb) {
+  const float ua = u01(va);
+  const float ub = u01(vb);
+  const float rho = sqrtf(-2.0f * 0.69314718055994531f * __builtin_amdgcn_logf(ua));
+  float s, c;
+  sincos_rev(ub, &s, &c);
+  return make_float2(rho * c, rho * s);
+}
+
+// Counter words for the noise layout (e, t, pair, tag << 28 | screen).
+__device__ __forceinline__ uint4 noise_counter(uint32_t e, uint32_t t, uint32_t pair, uint32_t tag,
+                                               uint32_t screen) {
+  return make_uint4(e, t, pair, (tag << 28) | screen);
+}
+
+}  // namespace turpy

@@ -1,0 +1,601 @@
+// gfx950 kernels of the split-step turbulence path.
+//
+// Field layout: complex64 [R][N][N], row-major (i0 = y, i1 = x).  Between the
+// passes of a propagation the field lives in the "row-spectral" domain: each
+// row has been transformed along x.  One step of Eq. 1 is then two passes:
+//   column pass: FFT along y, multiply by the separable chirp h(k0)/N (and the
+//                angular-spectrum correction), inverse FFT along y;
+//   row pass:    inverse FFT along x (1/N folded into the next multiply),
+//                multiply by exp(i phi) of the screen, forward FFT along x and
+//                multiply by the next distance's chirp h(k1).
+// Each pass reads and writes the field once.  The screen of a realization pair
+// is synthesised in two halves that follow the same split: the column half
+// (noise, PSD weighting, inverse FFT along y) writes one complex scratch plane
+// per pair; the row pass finishes it (inverse FFT along x, subharmonics,
+// piston) right before the modulation, so the real screens never touch HBM.
+#include "fft.hpp"
+#include "kernels.hpp"
+
+namespace turpy {
+
+namespace {
+
+constexpr int kE = 16;  // elements per thread in every transform
+
+template <int N>
+constexpr int row_groups() {  // rows per block of the row kernels
+  return (256 / (N / kE)) < N ? (256 / (N / kE)) : N;
+}
+template <int N>
+constexpr int row_block() { return row_groups<N>() * (N / kE); }
+template <int N>
+constexpr int col_width() { return N >= 2048 ? 8 : (N < 16 ? N : 16); }
+template <int N>
+constexpr int col_block() { return col_width<N>() * (N / kE); }
+
+// Spread a 1-D block index so that consecutive logical tiles land on the same
+// XCD (blocks are dealt round-robin over the 8 XCDs, each with its own L2).
+__device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t nb) {
+  if (nb % 8u != 0u) return b;
+  return (b % 8u) * (nb / 8u) + b / 8u;
+}
+
+// PSD weighting of Eq. S16/S17 at integer radius^2 q (in bins):
+// amp * exp(-f^2/(2 fm^2)) * (f^2 + f0^2)^(-11/12), f^2 = q df^2; zero at DC.
+__device__ __forceinline__ float psd_amp(int q, float amp, float df2, float inner, float f02) {
+  if (q == 0) return 0.0f;
+  const float f2 = static_cast<float>(q) * df2;
+  const float l2 = -f2 * inner - (11.0f / 12.0f) * __builtin_amdgcn_logf(f2 + f02);
+  return amp * __builtin_amdgcn_exp2f(l2);
+}
+
+__device__ __forceinline__ int signed_bin(int k, int n) { return k < (n >> 1) ? k : k - n; }
+
+// ---------------------------------------------------------------------------
+// Row pass.
+// ---------------------------------------------------------------------------
+template <int N, int SCREEN, bool BWD>
+__global__ __launch_bounds__(row_block<N>()) void row_pass_kernel(RowArgs a) {
+  constexpr int T = N / kE;
+  constexpr int G = row_groups<N>();
+  __shared__ float2 smem[G * RowLds::words(N)];
+  const int g = threadIdx.x / T;
+  const int t = threadIdx.x % T;
+  const int i0 = blockIdx.x * G + g;
+  const int64_t j = blockIdx.y;
+  const RowLds lds{smem + g * RowLds::words(N)};
+  const float2* __restrict__ tw = a.tw;
+  const size_t plane = static_cast<size_t>(N) * N;
+  const size_t row_off = static_cast<size_t>(i0) * N;
+
+  float pa[kE], pb[kE];  // screen phase (revolutions) for realizations 2j and 2j+1
+  if constexpr (SCREEN == ROW_SCRATCH) {
+    float2 z[kE];
+    const float2* src = a.scratch + j * plane + row_off;
+#pragma unroll
+    for (int m = 0; m < kE; ++m) z[m] = src[t + T * m];
+    fft<N, kE, true>(z, lds, t, tw);
+    if (a.sh_levels > 0) {
+      const float2* c = a.sh + (static_cast<size_t>(j) * a.M + a.screen) * 32;
+      const float2 mean = c[24];
+#pragma unroll
+      for (int m = 0; m < kE; ++m) z[m] = c_sub(z[m], mean);
+      for (int p = 0; p < a.sh_levels; ++p) {
+        const float2* cp = c + 8 * p;
+        const float2* ph = a.sh_phasor + static_cast<size_t>(p) * N;
+        const float2 ey = ph[i0];
+        const float2 eyc = make_float2(ey.x, -ey.y);
+        // offsets (m, n): 0 (-1,-1) 1 (-1,0) 2 (-1,1) 3 (0,-1) 4 (0,1) 5 (1,-1) 6 (1,0) 7 (1,1)
+        const float2 dm = c_add(c_add(c_mul(cp[0], eyc), cp[3]), c_mul(cp[5], ey));
+        const float2 d0 = c_add(c_mul(cp[1], eyc), c_mul(cp[6], ey));
+        const float2 dp = c_add(c_add(c_mul(cp[2], eyc), cp[4]), c_mul(cp[7], ey));
+        const float2 sa = c_add(dp, dm);
+        const float2 sb = c_sub(dp, dm);
+#pragma unroll
+        for (int m = 0; m < kE; ++m) {
+          const float2 ex = ph[t + T * m];
+          z[m].x += d0.x + sa.x * ex.x - sb.y * ex.y;
+          z[m].y += d0.y + sa.y * ex.x + sb.x * ex.y;
+        }
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < kE; ++m) {
+      pa[m] = z[m].x;
+      pb[m] = z[m].y;
+    }
+  } else if constexpr (SCREEN == ROW_MATERIALIZED) {
+    constexpr float inv2pi = 0.15915494309189535f;
+    const int64_t ra = 2 * j, rb = 2 * j + 1;
+    const float* sa = a.screens + (static_cast<size_t>(ra) * a.M + a.screen) * plane + row_off;
+#pragma unroll
+    for (int m = 0; m < kE; ++m) pa[m] = sa[t + T * m] * inv2pi;
+    if (rb < a.R) {
+      const float* sb = a.screens + (static_cast<size_t>(rb) * a.M + a.screen) * plane + row_off;
+#pragma unroll
+      for (int m = 0; m < kE; ++m) pb[m] = sb[t + T * m] * inv2pi;
+    }
+  }
+
+  if (SCREEN != ROW_NO_SCREEN && a.phase_out) {
+    constexpr float two_pi = 6.283185307179586f;
+    for (int b = 0; b < 2; ++b) {
+      const int64_t r = 2 * j + b;
+      if (r >= a.R) break;
+      float* dst = a.phase_out + (static_cast<size_t>(r) * a.M + a.screen) * plane + row_off;
+      const float* ph = b ? pb : pa;
+#pragma unroll
+      for (int m = 0; m < kE; ++m) dst[t + T * m] = ph[m] * two_pi;
+    }
+  }
+  if (!a.in) return;  // uniform over the block
+
+  for (int b = 0; b < 2; ++b) {
+    const int64_t r = 2 * j + b;
+    if (r >= a.R) break;  // uniform over the block
+    float2 x[kE];
+    const float2* src = a.in + r * a.in_stride + row_off;
+#pragma unroll
+    for (int m = 0; m < kE; ++m) x[m] = src[t + T * m];
+    if (a.in_spectral) {
+      if (a.pre) {
+#pragma unroll
+        for (int m = 0; m < kE; ++m) {
+          const float2 h = a.pre[t + T * m];
+          x[m] = a.conj_tables ? c_mulc(x[m], h) : c_mul(x[m], h);
+        }
+      }
+      fft<N, kE, true>(x, lds, t, tw);
+    }
+    const float* ph = b ? pb : pa;
+    if constexpr (SCREEN != ROW_NO_SCREEN) {
+      const size_t ck = (static_cast<size_t>(r) * a.M + a.screen) * plane + row_off;
+      if constexpr (!BWD) {
+#pragma unroll
+        for (int m = 0; m < kE; ++m) {
+          float s, c;
+          sincos_rev(ph[m], &s, &c);
+          x[m] = c_mul(x[m], make_float2(c * a.scale, s * a.scale));
+        }
+        if (a.ckpt_out) {
+#pragma unroll
+          for (int m = 0; m < kE; ++m) a.ckpt_out[ck + t + T * m] = x[m];
+        }
+      } else {
+        if (a.grad_screens) {
+#pragma unroll
+          for (int m = 0; m < kE; ++m) {
+            const float2 w = a.ckpt_in[ck + t + T * m];
+            a.grad_screens[ck + t + T * m] = w.x * x[m].y - w.y * x[m].x;  // Im(conj(W) g)
+          }
+        }
+#pragma unroll
+        for (int m = 0; m < kE; ++m) {
+          float s, c;
+          sincos_rev(ph[m], &s, &c);
+          x[m] = c_mul(x[m], make_float2(c * a.scale, -s * a.scale));
+        }
+      }
+    } else {
+      if (a.scale != 1.0f) {
+#pragma unroll
+        for (int m = 0; m < kE; ++m) x[m] = c_scale(x[m], a.scale);
+      }
+    }
+    if (a.out_spectral) {
+      fft<N, kE, false>(x, lds, t, tw);
+      if (a.post) {
+#pragma unroll
+        for (int m = 0; m < kE; ++m) {
+          const float2 h = a.post[t + T * m];
+          x[m] = a.conj_tables ? c_mulc(x[m], h) : c_mul(x[m], h);
+        }
+      }
+    }
+    float2* dst = a.out + r * plane + row_off;
+#pragma unroll
+    for (int m = 0; m < kE; ++m) dst[t + T * m] = x[m];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Column pass: FFT along y, x h(k0)/N (x angular-spectrum correction), IFFT.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float2 angular_correction(int k0, int k1, int n, double dz, double k,
+                                                     double df) {
+  // H_as / H_fresnel = exp(i dz (s - k + kappa^2/(2k))) = exp(-i dz kappa^4 / (2k (s+k)^2))
+  // for kappa < k (s = sqrt(k^2 - kappa^2)); evanescent bins decay as exp(-dz sqrt(kappa^2 - k^2)).
+  const double kx = signed_bin(k1, n), ky = signed_bin(k0, n);
+  const double kap2 = 4.0 * 3.14159265358979323846 * 3.14159265358979323846 * (kx * kx + ky * ky) * df * df;
+  const double k2 = k * k;
+  if (kap2 < k2) {
+    const double s = sqrt(k2 - kap2);
+    const double d = -dz * kap2 * kap2 / (2.0 * k * (s + k) * (s + k));
+    double rev = d * 0.15915494309189535;
+    rev -= rint(rev);
+    float sn, cs;
+    sincos_rev(static_cast<float>(rev), &sn, &cs);
+    return make_float2(cs, sn);
+  }
+  // exp(-dz sqrt(kappa^2 - k^2)) exp(-i k dz) / exp(-i dz kappa^2 / (2k))
+  const double mag = exp(-dz * sqrt(kap2 - k2));
+  double rev = (-k * dz + dz * kap2 / (2.0 * k)) * 0.15915494309189535;
+  rev -= rint(rev);
+  float sn, cs;
+  sincos_rev(static_cast<float>(rev), &sn, &cs);
+  return make_float2(static_cast<float>(mag) * cs, static_cast<float>(mag) * sn);
+}
+
+template <int N, bool ANGULAR>
+__global__ __launch_bounds__(col_block<N>()) void col_pass_kernel(ColArgs a) {
+  constexpr int T = N / kE;
+  constexpr int K = col_width<N>();
+  constexpr int STRIPS = N / K;
+  __shared__ float2 smem[N * K];
+  const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
+  const int strip = b % STRIPS;
+  const int64_t r = b / STRIPS;
+  const int c = threadIdx.x % K;
+  const int t = threadIdx.x / K;
+  const int k1 = strip * K + c;
+  const ColLds<K> lds{smem, c};
+  const float2* __restrict__ tw = a.tw;
+  const float2* src = a.in + r * a.in_stride + k1;
+  float2 x[kE];
+#pragma unroll
+  for (int m = 0; m < kE; ++m) x[m] = src[static_cast<size_t>(t + T * m) * N];
+  fft<N, kE, false>(x, lds, t, tw);
+#pragma unroll
+  for (int m = 0; m < kE; ++m) {
+    const int k0 = t + T * m;
+    float2 h = a.table[k0];
+    if constexpr (ANGULAR) h = c_mul(h, angular_correction(k0, k1, N, a.dz, a.k, a.df));
+    x[m] = a.conj_table ? c_mulc(x[m], h) : c_mul(x[m], h);
+  }
+  fft<N, kE, true>(x, lds, t, tw);
+  float2* dst = a.out + r * static_cast<int64_t>(N) * N + k1;
+#pragma unroll
+  for (int m = 0; m < kE; ++m) dst[static_cast<size_t>(t + T * m) * N] = x[m];
+}
+
+// ---------------------------------------------------------------------------
+// Column half of the screen synthesis: noise x PSD weight (Eq. S16/S17), or a
+// stored spectrum, then the unnormalised inverse transform along y.
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ __launch_bounds__(col_block<N>()) void synth_col_kernel(SynthArgs a) {
+  constexpr int T = N / kE;
+  constexpr int K = col_width<N>();
+  constexpr int STRIPS = N / K;
+  __shared__ float2 smem[N * K];
+  const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
+  const int strip = b % STRIPS;
+  const int64_t j = b / STRIPS;
+  const int c = threadIdx.x % K;
+  const int t = threadIdx.x / K;
+  const int k1 = strip * K + c;
+  const ColLds<K> lds{smem, c};
+  float2 x[kE];
+  if (a.spectra) {
+    constexpr float inv2pi = 0.15915494309189535f;
+    const float2* src = a.spectra + (static_cast<size_t>(j) * a.M + a.screen) * N * N + k1;
+#pragma unroll
+    for (int m = 0; m < kE; ++m) x[m] = c_scale(src[static_cast<size_t>(t + T * m) * N], inv2pi);
+  } else {
+    const int kx = signed_bin(k1, N);
+#pragma unroll
+    for (int m = 0; m < kE / 2; ++m) {
+      const int k0 = t + T * m;  // < N/2
+      const uint32_t e = static_cast<uint32_t>(k0) * N + k1;
+      const uint4 v = philox4x32_10(noise_counter(e, a.t, static_cast<uint32_t>(j), a.tag, a.screen), a.key0,
+                                    a.key1);
+      const int ky_lo = k0;             // signed bin of k0 (< N/2)
+      const int ky_hi = k0 - N / 2;     // signed bin of k0 + N/2
+      const float w_lo = psd_amp(ky_lo * ky_lo + kx * kx, a.amp, a.df2, a.inner, a.f02);
+      const float w_hi = psd_amp(ky_hi * ky_hi + kx * kx, a.amp, a.df2, a.inner, a.f02);
+      x[m] = c_scale(box_muller(v.x, v.y), w_lo);
+      x[m + kE / 2] = c_scale(box_muller(v.z, v.w), w_hi);
+    }
+  }
+  fft<N, kE, true>(x, lds, t, a.tw);
+  float2* dst = a.scratch + j * static_cast<int64_t>(N) * N + k1;
+#pragma unroll
+  for (int m = 0; m < kE; ++m) dst[static_cast<size_t>(t + T * m) * N] = x[m];
+}
+
+// ---------------------------------------------------------------------------
+// Subharmonic coefficients of Eq. 2 for every (pair, screen), and their mean.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void sh_kernel(ShArgs a) {
+  __shared__ float2 coef[24];
+  const int64_t j = blockIdx.x;
+  const int s = blockIdx.y;
+  const int l = threadIdx.x;
+  if (l < 4 * a.levels) {
+    const int p = l / 4;
+    const uint4 v = philox4x32_10(noise_counter(static_cast<uint32_t>(l), a.t, static_cast<uint32_t>(j), TAG_SH,
+                                                static_cast<uint32_t>(s)),
+                                  a.key0, a.key1);
+    const int q0 = 2 * (l % 4), q1 = q0 + 1;
+    // offsets with |m| + |n| = 2 (diagonal) are q = 0, 2, 5, 7
+    const bool diag0 = (q0 == 0 || q0 == 2 || q0 == 5 || q0 == 7);
+    const bool diag1 = (q1 == 0 || q1 == 2 || q1 == 5 || q1 == 7);
+    const float* amp = a.amp + (static_cast<size_t>(s) * 3 + p) * 2;
+    coef[8 * p + q0] = c_scale(box_muller(v.x, v.y), amp[diag0 ? 1 : 0]);
+    coef[8 * p + q1] = c_scale(box_muller(v.z, v.w), amp[diag1 ? 1 : 0]);
+  }
+  __syncthreads();
+  float2* out = a.sh + (static_cast<size_t>(j) * a.M + s) * 32;
+  if (l < 24) out[l] = l < 8 * a.levels ? coef[l] : make_float2(0.0f, 0.0f);
+  if (l == 0) {
+    float2 mean = make_float2(0.0f, 0.0f);
+    for (int p = 0; p < a.levels; ++p) {
+      const float2 e1 = a.mean_fac[p];
+      const float2 em = make_float2(e1.x, -e1.y);
+      const float2 one = make_float2(1.0f, 0.0f);
+      int q = 0;
+      for (int mm = -1; mm <= 1; ++mm)
+        for (int nn = -1; nn <= 1; ++nn) {
+          if (mm == 0 && nn == 0) continue;
+          const float2 fy = mm < 0 ? em : (mm > 0 ? e1 : one);
+          const float2 fx = nn < 0 ? em : (nn > 0 ? e1 : one);
+          mean = c_add(mean, c_mul(coef[8 * p + q], c_mul(fy, fx)));
+          ++q;
+        }
+    }
+    out[24] = mean;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Spectrum evolution (Eq. 4 then Eq. 5), elementwise on bin pairs (k0, k1),
+// (k0 + N/2, k1) that share one Philox block.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void evolve_kernel(EvolveArgs a) {
+  const int n = a.n;
+  const int64_t half = static_cast<int64_t>(n / 2) * n;
+  const int64_t total = a.P * a.M * half;
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int64_t js = idx / half;
+  const int64_t rem = idx % half;
+  const int k0 = static_cast<int>(rem / n);
+  const int k1 = static_cast<int>(rem % n);
+  const int64_t j = js / a.M;
+  const int s = static_cast<int>(js % a.M);
+  const uint4 v = philox4x32_10(
+      noise_counter(static_cast<uint32_t>(rem), a.t, static_cast<uint32_t>(j), a.tag, static_cast<uint32_t>(s)),
+      a.key0, a.key1);
+  float2* base = a.spectra + js * static_cast<int64_t>(n) * n;
+  const float amp = a.amp[s];
+  const int kx = signed_bin(k1, n);
+  const float blend = static_cast<float>(sqrt(1.0 - a.alpha * a.alpha));
+  for (int h = 0; h < 2; ++h) {
+    const int kk0 = k0 + h * (n / 2);
+    const int ky = signed_bin(kk0, n);
+    const float w = psd_amp(ky * ky + kx * kx, amp, a.df2, a.inner, a.f02);
+    const float2 nc = h == 0 ? box_muller(v.x, v.y) : box_muller(v.z, v.w);
+    float2* p = base + static_cast<int64_t>(kk0) * n + k1;
+    float2 out;
+    if (a.init) {
+      out = c_scale(nc, w);
+    } else {
+      double rev = -(static_cast<double>(kx) * a.sx + static_cast<double>(ky) * a.sy) / n;
+      rev -= rint(rev);
+      float sn, cs;
+      sincos_rev(static_cast<float>(rev), &sn, &cs);
+      const float al = static_cast<float>(a.alpha);
+      out = c_add(c_scale(c_mul(*p, make_float2(cs, sn)), al), c_scale(nc, blend * w));
+    }
+    if (kk0 == 0 && k1 == 0) out = make_float2(0.0f, 0.0f);
+    *p = out;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Ensemble moments: Kahan-compensated sums of I and I^2 per pixel.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void stats_kernel(StatsArgs a) {
+  const int64_t np = static_cast<int64_t>(a.n) * a.n;
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= np) return;
+  float s1 = a.moments[p], c1 = a.moments[np + p];
+  float s2 = a.moments[2 * np + p], c2 = a.moments[3 * np + p];
+  for (int64_t b = 0; b < a.batch; ++b) {
+    const float2 u = a.u[b * np + p];
+    const float i = u.x * u.x + u.y * u.y;
+    float y = i - c1;
+    float tt = s1 + y;
+    c1 = (tt - s1) - y;
+    s1 = tt;
+    y = i * i - c2;
+    tt = s2 + y;
+    c2 = (tt - s2) - y;
+    s2 = tt;
+  }
+  a.moments[p] = s1;
+  a.moments[np + p] = c1;
+  a.moments[2 * np + p] = s2;
+  a.moments[3 * np + p] = c2;
+}
+
+template <int NT>
+__device__ double block_sum(double v, double* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = NT / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+template <int NT>
+__device__ double block_max(double v, double* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = NT / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(1024) void finalize_kernel(FinalizeArgs a) {
+  constexpr int NT = 1024;
+  __shared__ double red[NT];
+  const int n = a.n;
+  const int64_t np = static_cast<int64_t>(n) * n;
+  double si_sum = 0, si_cnt = 0, m1_sum = 0, r2m1 = 0, m1_max = 0;
+  for (int64_t p = threadIdx.x; p < np; p += NT) {
+    const int i0 = static_cast<int>(p / n), i1 = static_cast<int>(p % n);
+    const double m1 = (static_cast<double>(a.moments[p]) - a.moments[np + p]) / a.count;
+    const double m2 = (static_cast<double>(a.moments[2 * np + p]) - a.moments[3 * np + p]) / a.count;
+    const double si = m2 / (m1 * m1) - 1.0;
+    if (a.si_map) a.si_map[p] = static_cast<float>(si);
+    const int d0 = abs(i0 - n / 2), d1 = abs(i1 - n / 2);
+    if (d0 < n / 4 && d1 < n / 4) {
+      si_sum += si;
+      si_cnt += 1.0;
+    }
+    const double x = (i1 - n / 2) * a.dx, y = (i0 - n / 2) * a.dx;
+    m1_sum += m1;
+    r2m1 += (x * x + y * y) * m1;
+    m1_max = fmax(m1_max, m1);
+  }
+  si_sum = block_sum<NT>(si_sum, red);
+  si_cnt = block_sum<NT>(si_cnt, red);
+  m1_sum = block_sum<NT>(m1_sum, red);
+  r2m1 = block_sum<NT>(r2m1, red);
+  m1_max = block_max<NT>(m1_max, red);
+  const double thr = exp(-2.0) * m1_max;
+  double s0 = 0, sx = 0, sxx = 0, sy = 0, sxy = 0;
+  for (int64_t p = threadIdx.x; p < np; p += NT) {
+    const double m1 = (static_cast<double>(a.moments[p]) - a.moments[np + p]) / a.count;
+    if (m1 >= thr && m1 > 0) {
+      const int i0 = static_cast<int>(p / n), i1 = static_cast<int>(p % n);
+      const double x = (i1 - n / 2) * a.dx, y = (i0 - n / 2) * a.dx;
+      const double r2 = x * x + y * y, l = log(m1);
+      s0 += 1;
+      sx += r2;
+      sxx += r2 * r2;
+      sy += l;
+      sxy += r2 * l;
+    }
+  }
+  s0 = block_sum<NT>(s0, red);
+  sx = block_sum<NT>(sx, red);
+  sxx = block_sum<NT>(sxx, red);
+  sy = block_sum<NT>(sy, red);
+  sxy = block_sum<NT>(sxy, red);
+  if (threadIdx.x == 0) {
+    const double den = s0 * sxx - sx * sx;
+    const double slope = den != 0 ? (s0 * sxy - sx * sy) / den : 0.0;
+    a.summary[0] = si_cnt > 0 ? si_sum / si_cnt : 0.0;
+    a.summary[1] = m1_sum > 0 ? sqrt(2.0 * r2m1 / m1_sum) : 0.0;
+    a.summary[2] = slope < 0 ? sqrt(-2.0 / slope) : __builtin_huge_val();
+    a.summary[3] = a.count;
+  }
+}
+
+__global__ __launch_bounds__(256) void copy_kernel(const float2* in, int64_t in_stride, float2* out,
+                                                   int64_t count, int64_t R) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= count * R) return;
+  const int64_t r = idx / count, p = idx % count;
+  out[idx] = in[r * in_stride + p];
+}
+
+template <int N>
+hipError_t row_launch(const RowArgs& a, int64_t pairs, hipStream_t s) {
+  constexpr int G = row_groups<N>();
+  dim3 grid(N / G, static_cast<uint32_t>(pairs));
+  dim3 block(row_block<N>());
+  if (a.screen_mode == ROW_NO_SCREEN)
+    hipLaunchKernelGGL((row_pass_kernel<N, ROW_NO_SCREEN, false>), grid, block, 0, s, a);
+  else if (a.screen_mode == ROW_SCRATCH && !a.backward)
+    hipLaunchKernelGGL((row_pass_kernel<N, ROW_SCRATCH, false>), grid, block, 0, s, a);
+  else if (a.screen_mode == ROW_SCRATCH)
+    hipLaunchKernelGGL((row_pass_kernel<N, ROW_SCRATCH, true>), grid, block, 0, s, a);
+  else if (!a.backward)
+    hipLaunchKernelGGL((row_pass_kernel<N, ROW_MATERIALIZED, false>), grid, block, 0, s, a);
+  else
+    hipLaunchKernelGGL((row_pass_kernel<N, ROW_MATERIALIZED, true>), grid, block, 0, s, a);
+  return hipGetLastError();
+}
+
+template <int N>
+hipError_t col_launch(const ColArgs& a, hipStream_t s) {
+  constexpr int K = col_width<N>();
+  const uint64_t blocks = static_cast<uint64_t>(N / K) * a.R;
+  if (a.angular)
+    hipLaunchKernelGGL((col_pass_kernel<N, true>), dim3(static_cast<uint32_t>(blocks)), dim3(col_block<N>()), 0, s, a);
+  else
+    hipLaunchKernelGGL((col_pass_kernel<N, false>), dim3(static_cast<uint32_t>(blocks)), dim3(col_block<N>()), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int N>
+hipError_t synth_launch(const SynthArgs& a, hipStream_t s) {
+  constexpr int K = col_width<N>();
+  const uint64_t blocks = static_cast<uint64_t>(N / K) * a.P;
+  hipLaunchKernelGGL(synth_col_kernel<N>, dim3(static_cast<uint32_t>(blocks)), dim3(col_block<N>()), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+#define TURPY_DISPATCH_N(n, FN, ...)            \
+  switch (n) {                                  \
+    case 16: return FN<16>(__VA_ARGS__);        \
+    case 32: return FN<32>(__VA_ARGS__);        \
+    case 64: return FN<64>(__VA_ARGS__);        \
+    case 128: return FN<128>(__VA_ARGS__);      \
+    case 256: return FN<256>(__VA_ARGS__);      \
+    case 512: return FN<512>(__VA_ARGS__);      \
+    case 1024: return FN<1024>(__VA_ARGS__);    \
+    case 2048: return FN<2048>(__VA_ARGS__);    \
+    default: return hipErrorInvalidValue;       \
+  }
+
+hipError_t launch_row(int n, const RowArgs& a, int64_t pairs, hipStream_t s) {
+  TURPY_DISPATCH_N(n, row_launch, a, pairs, s)
+}
+hipError_t launch_col(int n, const ColArgs& a, hipStream_t s) { TURPY_DISPATCH_N(n, col_launch, a, s) }
+hipError_t launch_synth(int n, const SynthArgs& a, hipStream_t s) { TURPY_DISPATCH_N(n, synth_launch, a, s) }
+
+hipError_t launch_sh(const ShArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(sh_kernel, dim3(static_cast<uint32_t>(a.P), a.M), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_evolve(const EvolveArgs& a, hipStream_t s) {
+  const int64_t total = a.P * a.M * static_cast<int64_t>(a.n / 2) * a.n;
+  hipLaunchKernelGGL(evolve_kernel, dim3(static_cast<uint32_t>((total + 255) / 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_stats(const StatsArgs& a, hipStream_t s) {
+  const int64_t np = static_cast<int64_t>(a.n) * a.n;
+  hipLaunchKernelGGL(stats_kernel, dim3(static_cast<uint32_t>((np + 255) / 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(1024), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(const float2* in, int64_t in_stride, float2* out, int64_t count, int64_t R,
+                       hipStream_t s) {
+  const int64_t total = count * R;
+  hipLaunchKernelGGL(copy_kernel, dim3(static_cast<uint32_t>((total + 255) / 256)), dim3(256), 0, s, in,
+                     in_stride, out, count, R);
+  return hipGetLastError();
+}
+
+}  // namespace turpy

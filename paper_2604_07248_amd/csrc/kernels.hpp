@@ -1,0 +1,140 @@
+// Launch interface between the host runtime (api.hip) and the gfx950 kernels
+// (kernels.hip).  Plain structs of device pointers and scalars.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace turpy {
+
+// Philox counter tags of the noise layout.
+constexpr uint32_t TAG_MAIN = 1;
+constexpr uint32_t TAG_SH = 2;
+constexpr uint32_t TAG_AR = 3;
+
+// Screen source inside a row pass.
+enum RowScreen : int { ROW_NO_SCREEN = 0, ROW_SCRATCH = 1, ROW_MATERIALIZED = 2 };
+
+struct RowArgs {
+  const float2* tw;         // twiddles exp(-2 pi i k / N), [N]
+  const float2* in;         // field rows, realization r at in + r * in_stride
+  int64_t in_stride;        // elements between realizations (0: shared source)
+  float2* out;              // [R][N][N]
+  int64_t R;                // realizations
+  int in_spectral;          // input rows in the row-spectral domain: inverse row transform first
+  int out_spectral;         // forward row transform at the end
+  const float2* pre;        // per-column factor before the inverse transform, or NULL
+  const float2* post;       // per-column factor after the forward transform, or NULL
+  int conj_tables;          // use conj(pre), conj(post)
+  float scale;              // normalisation folded into the pointwise step
+  int screen_mode;          // RowScreen
+  const float2* scratch;    // [P][N][N] column-transformed complex screen, revolutions
+  const float* screens;     // [R][M][N][N] radians (materialised)
+  int screen;               // screen index s
+  int M;                    // screens per path
+  int sh_levels;            // 0..3
+  const float2* sh;         // [P][M][32] subharmonic coefficients (revolutions), [24] = mean
+  const float2* sh_phasor;  // [3][N] exp(2 pi i (i - N/2) / (N 3^p))
+  int backward;             // 0: W = U e^{i phi}; 1: adjoint (read checkpoint, write dL/dphi, e^{-i phi})
+  float2* ckpt_out;         // forward: [R][M][N][N] field after the screen, or NULL
+  const float2* ckpt_in;    // backward: same layout
+  float* grad_screens;      // backward: [R][M][N][N] dL/dphi, or NULL
+  float* phase_out;         // [R][M][N][N] radians: write the screens themselves, or NULL
+};
+
+struct ColArgs {
+  const float2* tw;
+  const float2* in;         // realization r at in + r * in_stride
+  int64_t in_stride;
+  float2* out;              // [R][N][N]
+  int64_t R;
+  const float2* table;      // h[k0] / N for this distance, [N]
+  int conj_table;
+  int angular;              // angular-spectrum correction on top of the separable Fresnel chirp
+  double dz;                // distance (for the angular-spectrum correction)
+  double k;                 // 2 pi n0 / lambda
+  double df;                // 1 / (N dx)
+};
+
+struct SynthArgs {
+  const float2* tw;
+  float2* scratch;          // [P][N][N]
+  int64_t P;                // realization pairs
+  uint32_t key0, key1;      // Philox key (seed)
+  uint32_t t;               // time step
+  uint32_t screen;
+  uint32_t tag;
+  float amp;                // sqrt(0.023) r0^(-5/6) df / (2 pi): revolutions
+  float df2;                // df^2
+  float inner;              // log2(e) / (2 fm^2), 0 when no inner-scale cutoff
+  float f02;                // f0^2
+  // spectra source (ROW_SCRATCH from stored spectra) instead of noise
+  const float2* spectra;    // [P][M][N][N] radians, or NULL for synthesis
+  int M;
+};
+
+struct ShArgs {
+  float2* sh;               // [P][M][32]
+  int64_t P;
+  int M;
+  int levels;
+  uint32_t key0, key1, t;
+  const float* amp;         // [M][3][2] amplitude (revolutions) for |offset|^2 = 1, 2
+  float2 mean_fac[3];       // mean over the grid of exp(2 pi i (i - N/2)/(N 3^p))
+};
+
+struct EvolveArgs {
+  float2* spectra;          // [P][M][N][N] radians, in place
+  int64_t P;
+  int M;
+  int n;
+  uint32_t key0, key1, t, tag;
+  double alpha;
+  double sx, sy;            // shift in pixels
+  int init;                 // 1: overwrite with fresh spectra (t = 0)
+  const float* amp;         // [M] sqrt(0.023) r0^(-5/6) df: radians
+  float df2, inner, f02;
+};
+
+struct StatsArgs {
+  const float2* u;
+  int64_t batch;
+  int n;
+  float* moments;           // [4][n][n]
+};
+
+struct FinalizeArgs {
+  const float* moments;
+  int n;
+  double dx;
+  double count;
+  float* si_map;
+  double* summary;
+};
+
+struct RecvArgs {
+  const float2* tw;
+  const float2* in;
+  float2* out;
+  int64_t batch;
+  double dx;
+  double radius2;           // (aperture diameter / 2)^2
+  const float* theta1;
+  const float* theta2;      // centred order
+  int mode;                 // see kernels.hip
+  const float2* aux;        // second input (backward)
+  float* partial;           // [chunks][n][n] partial mask gradients
+  int chunk;                // batch elements per chunk
+};
+
+hipError_t launch_row(int n, const RowArgs& a, int64_t pairs, hipStream_t s);
+hipError_t launch_col(int n, const ColArgs& a, hipStream_t s);
+hipError_t launch_synth(int n, const SynthArgs& a, hipStream_t s);
+hipError_t launch_sh(const ShArgs& a, hipStream_t s);
+hipError_t launch_evolve(const EvolveArgs& a, hipStream_t s);
+hipError_t launch_stats(const StatsArgs& a, hipStream_t s);
+hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s);
+hipError_t launch_copy(const float2* in, int64_t in_stride, float2* out, int64_t count, int64_t R,
+                       hipStream_t s);
+
+}  // namespace turpy

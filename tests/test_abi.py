@@ -1,0 +1,87 @@
+"""CPU checks of the C-ABI library: it loads, exports every symbol the header
+declares, and rejects invalid descriptors before touching the GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2604_07248_amd import binding as B
+from paper_2604_07248_amd import workloads
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_symbols():
+    text = open(os.path.join(ROOT, "include", "turpy.h")).read()
+    decl = re.findall(r"^\s*(?:turpy_status|const char\*)\s+(turpy_[a-z_]+)\s*\(", text, re.M)
+    return sorted(set(decl))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(B.LIB_PATH):
+        pytest.fail("libturpy.so is not built (run __graft_entry__.build())")
+    return B.lib()
+
+
+def test_exports_every_declared_symbol(L):
+    declared = header_symbols()
+    assert len(declared) >= 13
+    assert sorted(B.EXPORTS) == declared
+    for name in declared:
+        assert getattr(L, name) is not None
+
+
+def test_version_and_error_strings(L):
+    assert b"gfx950" in L.turpy_version()
+    assert isinstance(L.turpy_last_error(), bytes)
+
+
+def _status(path, flags=0):
+    cp = B.make_cpath(path)
+    h = ctypes.c_void_p()
+    st = B.lib().turpy_plan_create(ctypes.byref(h), ctypes.byref(cp), flags)
+    return st, B.last_error()
+
+
+@pytest.mark.parametrize("change,status,needle", [
+    (dict(n=100), B.E_INVALID, "power of two"),
+    (dict(n=4096), B.E_UNSUPPORTED, "outside"),
+    (dict(n=8), B.E_UNSUPPORTED, "outside"),
+    (dict(dx=0.0), B.E_INVALID, "dx"),
+    (dict(wavelength=-1.0), B.E_INVALID, "wavelength"),
+    (dict(sh_levels=4), B.E_UNSUPPORTED, "sh_levels"),
+    (dict(tf_kind=7), B.E_INVALID, "tf_kind"),
+    (dict(realizations=0), B.E_INVALID, "realizations"),
+    (dict(inner_scale_conv=3), B.E_INVALID, "inner_scale_conv"),
+])
+def test_invalid_descriptors_rejected(L, change, status, needle):
+    p = workloads.config1().path.with_(**change)
+    st, msg = _status(p)
+    assert st == status and needle in msg, (st, msg)
+
+
+def test_negative_and_interior_zero_distances(L):
+    p = workloads.config1().path
+    st, msg = _status(p.with_(dz=(100.0, -1.0, 200.0, 200.0, 200.0, 100.0)))
+    assert st == B.E_INVALID and "dz[1]" in msg
+    st, msg = _status(p.with_(dz=(100.0, 0.0, 200.0, 200.0, 200.0, 100.0)))
+    assert st == B.E_UNSUPPORTED and "merge" in msg
+    st, msg = _status(p.with_(cn2dz=(1e-12, -1e-12, 1e-12, 1e-12, 1e-12)))
+    assert st == B.E_INVALID and "cn2dz[1]" in msg
+
+
+def test_aliasing_limit(L):
+    """A step beyond N dx^2 n0 / lambda (Sec. 2.4, Eq. 7 at the Nyquist frequency) is refused."""
+    p = workloads.config1().path
+    limit = p.n * p.dx ** 2 / p.wavelength
+    st, msg = _status(p.with_(dz=(100.0, 200.0, 200.0, 200.0, limit * 1.01, 100.0)))
+    assert st == B.E_ALIASING and "sampling limit" in msg
+
+
+def test_stats_argument_errors(L):
+    st = L.turpy_stats(64, 0.01, 1, None, None, 0, 0, None, None, None)
+    assert st == B.E_INVALID and "moments" in B.last_error()
+    st = L.turpy_stats(0, 0.01, 0, None, None, 0, 0, None, None, None)
+    assert st == B.E_INVALID

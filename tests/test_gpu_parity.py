@@ -1,0 +1,231 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle, element by
+element on the same seeded inputs (field relative-L2 <= 1e-4 in complex64)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import evolve as oev
+from oracle import propagate as opr
+from oracle import stats as ost
+from paper_2604_07248_amd import workloads
+
+from gpu_helpers import TOL, oracle_propagate, oracle_screens, rel_l2, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def api(gpu_lib):
+    from paper_2604_07248_amd import api as _api
+    return _api
+
+
+def c64(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.complex64)).cuda()
+
+
+def sized_path(n, realizations=3, m=2, sh=0, **kw):
+    """A path on an N-point grid whose steps sit below the sampling limit."""
+    lam = 1e-6
+    dx = 2e-3 if n >= 128 else 4e-3
+    limit = n * dx * dx / lam
+    length = min(0.8 * limit * m, 2000.0) if m > 0 else 0.5 * limit
+    side = n * dx
+    if m == 0:
+        return workloads.Path(n=n, dx=dx, wavelength=lam, dz=(length,), cn2dz=(), l0=0.005, L0=20.0,
+                              sh_levels=sh, realizations=realizations, **kw)
+    return workloads.uniform_path(n, side, lam, length, m, 1e-15, 0.005, 20.0, sh, realizations=realizations).with_(**kw)
+
+
+def gaussian(path, w0_frac=0.1):
+    return workloads.gaussian_source(path.n, path.dx, w0_frac * path.n * path.dx)
+
+
+@pytest.mark.parametrize("n", [16, 32, 64, 128, 256, 512, 1024, 2048])
+def test_screens_match_oracle(api, n):
+    path = sized_path(n, realizations=3, m=2, sh=3 if n in (64, 512) else 0)
+    say(f"[screens] n={n} sh={path.sh_levels}")
+    plan = api.Plan(path)
+    got = plan.screens(seed=7).cpu().numpy()
+    ref = oracle_screens(path, 7, range(3))
+    err = rel_l2(got, ref)
+    say(f"[screens] n={n} rel-L2 {err:.2e}")
+    assert err < TOL
+
+
+@pytest.mark.parametrize("n", [16, 32, 64, 128, 256, 512, 1024, 2048])
+def test_propagate_sizes(api, n):
+    path = sized_path(n)
+    say(f"[propagate] n={n}")
+    u0 = gaussian(path)
+    plan = api.Plan(path)
+    out, ck = plan.propagate(c64(u0), seed=11, checkpoints=True)
+    ref, ref_ck = oracle_propagate(path, 11, u0.astype(np.complex64))
+    err = rel_l2(out.cpu().numpy(), ref)
+    cerr = rel_l2(ck.cpu().numpy(), ref_ck)
+    say(f"[propagate] n={n} field {err:.2e} checkpoints {cerr:.2e}")
+    assert err < TOL and cerr < TOL
+
+
+def test_config1_full(api):
+    w = workloads.config1()
+    say("[config1] N=128 R=16 M=5")
+    u0 = w.source_field().astype(np.complex64)
+    plan = api.Plan(w.path)
+    out = plan.propagate(c64(u0), seed=w.seed).cpu().numpy()
+    ref, _ = oracle_propagate(w.path, w.seed, u0)
+    per = [rel_l2(out[r], ref[r]) for r in range(w.path.realizations)]
+    say(f"[config1] worst per-realization rel-L2 {max(per):.2e}")
+    assert max(per) < TOL
+    # statistics of the batch against the oracle's
+    m = api.Moments(w.path.n, w.path.dx)
+    m.add(torch.from_numpy(out).cuda())
+    _, s = m.finalize()
+    so = ost.summary(ref, w.path.dx)
+    for key, tol in (("si_plane", 1e-3), ("w_2nd", 1e-4), ("w_fit", 1e-2)):
+        assert abs(s[key] - so[key]) <= tol * abs(so[key]), (key, s[key], so[key])
+
+
+@pytest.mark.parametrize("case", ["angular", "first_zero", "last_zero", "no_screens", "per_realization_source",
+                                  "subharmonics", "inner_conv", "kolmogorov", "single", "odd_pairs"])
+def test_propagate_options(api, case):
+    path = sized_path(256, realizations=4, m=3)
+    if case == "angular":
+        path = path.with_(tf_kind=1)
+    elif case == "first_zero":
+        path = path.with_(dz=(0.0,) + path.dz[1:])
+    elif case == "last_zero":
+        path = path.with_(dz=path.dz[:-1] + (0.0,))
+    elif case == "no_screens":
+        path = sized_path(256, realizations=2, m=0)
+    elif case == "subharmonics":
+        path = path.with_(sh_levels=3)
+    elif case == "inner_conv":
+        path = path.with_(inner_scale_conv=1)
+    elif case == "kolmogorov":
+        path = path.with_(l0=0.0, L0=float("inf"), sh_levels=2)
+    elif case == "single":
+        path = path.with_(realizations=1)
+    elif case == "odd_pairs":
+        path = path.with_(realizations=5)
+    say(f"[options] {case}")
+    u0 = gaussian(path)
+    if case == "per_realization_source":
+        rng = np.random.default_rng(3)
+        u0 = u0[None] * np.exp(1j * 0.3 * rng.standard_normal((path.realizations, path.n, path.n)))
+    u0 = u0.astype(np.complex64)
+    plan = api.Plan(path)
+    out = plan.propagate(c64(u0), seed=5).cpu().numpy()
+    ref, _ = oracle_propagate(path, 5, u0)
+    err = rel_l2(out, ref)
+    say(f"[options] {case} rel-L2 {err:.2e}")
+    assert err < TOL
+
+
+def test_materialized_equals_synthesised(api):
+    path = sized_path(512, realizations=4, m=3, sh=3)
+    say("[materialized] n=512")
+    plan = api.Plan(path)
+    u0 = c64(gaussian(path))
+    phi = plan.screens(seed=9)
+    a = plan.propagate(u0, seed=9)
+    b = plan.propagate(u0, seed=0, screens=phi)
+    err = rel_l2(b.cpu().numpy(), a.cpu().numpy())
+    say(f"[materialized] rel diff {err:.2e}")
+    assert err < 1e-5
+
+
+@pytest.mark.parametrize("case", ["synth", "materialized", "angular_edges"])
+def test_backward_matches_oracle_adjoint(api, case):
+    path = sized_path(256, realizations=3, m=3, sh=3 if case == "synth" else 0)
+    if case == "angular_edges":
+        path = path.with_(tf_kind=1, dz=(0.0,) + path.dz[1:-1] + (0.0,))
+    say(f"[backward] {case}")
+    plan = api.Plan(path)
+    u0 = gaussian(path).astype(np.complex64)
+    rng = np.random.default_rng(4)
+    g_out = (rng.standard_normal((3, path.n, path.n)) + 1j * rng.standard_normal((3, path.n, path.n))).astype(np.complex64)
+    screens = plan.screens(seed=13) if case != "synth" else None
+    out, ck = plan.propagate(c64(u0), seed=13, screens=screens, checkpoints=True)
+    g_in, g_phi = plan.propagate_backward(c64(g_out), ck, seed=13, screens=screens)
+    phi = oracle_screens(path, 13, range(3))
+    ref_out, ref_ck = opr.propagate(u0.astype(np.complex128), path, phi)
+    ref_gin, ref_gphi = opr.propagate_adjoint(g_out.astype(np.complex128), path, phi, ref_ck)
+    e_in = rel_l2(g_in.cpu().numpy(), ref_gin)
+    e_phi = rel_l2(g_phi.cpu().numpy(), ref_gphi)
+    say(f"[backward] {case} grad_u_in {e_in:.2e} grad_phi {e_phi:.2e}")
+    assert e_in < TOL and e_phi < TOL
+
+
+def test_evolve_and_spectra_propagation(api):
+    path = sized_path(256, realizations=4, m=2)
+    say("[evolve] n=256")
+    plan = api.Plan(path)
+    spec = plan.init_spectra(seed=3)
+    ref = oev.initial_spectra(path, 3)
+    assert rel_l2(spec.cpu().numpy(), ref) < TOL
+    for t in (1, 2, 3):
+        plan.evolve(spec, seed=3, t=t, alpha=0.9, shift_x=0.5, shift_y=-0.25)
+        ref = oev.evolve(ref, path, 3, t, 0.9, 0.5, -0.25)
+    e_spec = rel_l2(spec.cpu().numpy(), ref)
+    u0 = gaussian(path).astype(np.complex64)
+    out = plan.propagate(c64(u0), spectra=spec).cpu().numpy()
+    phi = oev.screens_from_spectra(ref, path.realizations)
+    ref_out, _ = opr.propagate(u0.astype(np.complex128), path, phi)
+    e_out = rel_l2(out, ref_out)
+    say(f"[evolve] spectra {e_spec:.2e} field {e_out:.2e}")
+    assert e_spec < TOL and e_out < TOL
+
+
+def test_stats_match_oracle(api):
+    rng = np.random.default_rng(8)
+    n, dx = 128, 0.004
+    # a wide beam: FP32 moments hold I^2 only above ~1e-38 (the FP64 oracle has no such floor)
+    u = workloads.gaussian_source(n, dx, 0.15)[None] * (1 + 0.3 * rng.standard_normal((40, n, n)))
+    u = u.astype(np.complex64)
+    m = api.Moments(n, dx)
+    m.add(torch.from_numpy(u[:25]).cuda())
+    m.add(torch.from_numpy(u[25:]).cuda())
+    si, s = m.finalize()
+    so = ost.summary(u.astype(np.complex128), dx)
+    m1, m2 = ost.moments(u.astype(np.complex128))
+    si_ref = ost.si_map(m1, m2)
+    assert s["count"] == 40
+    assert np.max(np.abs(si.cpu().numpy() - si_ref)) < 1e-4 * np.max(np.abs(si_ref)) + 1e-5
+    for key in ("si_plane", "w_2nd", "w_fit"):
+        assert abs(s[key] - so[key]) <= 1e-4 * abs(so[key]), (key, s[key], so[key])
+
+
+def test_determinism(api):
+    path = sized_path(512, realizations=4, m=3, sh=3)
+    plan = api.Plan(path)
+    u0 = c64(gaussian(path))
+    a = plan.propagate(u0, seed=21).cpu().numpy()
+    b = plan.propagate(u0, seed=21).cpu().numpy()
+    assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+
+
+def test_headline_full_size_sampled(api):
+    """Full headline workload (N=1024, R=64, M=8) in the benchmark's launch
+    configuration; sampled realizations checked one by one against the oracle."""
+    w = workloads.headline()
+    say("[headline] N=1024 R=64 M=8")
+    plan = api.Plan(w.path)
+    u0 = w.source_field().astype(np.complex64)
+    out, ck = plan.propagate(c64(u0), seed=w.seed, checkpoints=True)
+    g = torch.ones_like(out) * (1.0 / 1024)
+    g_in, g_phi = plan.propagate_backward(g, ck, seed=w.seed)
+    out = out.cpu().numpy()
+    sample = [0, 1, 37, 63]
+    phi = oracle_screens(w.path, w.seed, sample)
+    ref, ref_ck = opr.propagate(u0.astype(np.complex128), w.path, phi)
+    ref_gin, ref_gphi = opr.propagate_adjoint(np.ones_like(ref) / 1024, w.path, phi, ref_ck)
+    for i, r in enumerate(sample):
+        e = rel_l2(out[r], ref[i])
+        eg = rel_l2(g_in[r].cpu().numpy(), ref_gin[i])
+        ep = rel_l2(g_phi[r].cpu().numpy(), ref_gphi[i])
+        say(f"[headline] r={r} field {e:.2e} grad_in {eg:.2e} grad_phi {ep:.2e}")
+        assert e < TOL and eg < TOL and ep < TOL
+    # energy is conserved by every realization (unitary steps)
+    e0 = np.sum(np.abs(u0.astype(np.complex128)) ** 2)
+    assert np.max(np.abs(np.sum(np.abs(out.astype(np.complex128)) ** 2, axis=(1, 2)) / e0 - 1)) < 1e-4
