@@ -167,16 +167,19 @@ turpy_status turpy_stats(int32_t n, double dx, int64_t batch, const void* u, flo
  *  U1 = A u exp(i theta1) (A: disc of `aperture_diameter` metres centred on
  *  pixel (n/2, n/2)); Z = DFT{U1} exp(i theta2') with theta2' the natural-order
  *  view of theta2 (theta2 stored centred, fftshift order);
- *  u_out = IDFT{Z} (1/n^2 inverse).  u, u_out complex64 [batch][n][n];
- *  theta1, theta2 float [n][n].  ws: turpy_receiver_workspace_size bytes. */
+ *  u_out = IDFT{Z} (1/n^2 inverse).  u, u_out complex64 [batch][n][n] (must
+ *  not alias); theta1, theta2 float [n][n] radians.  The forward pass needs no
+ *  workspace (ws may be NULL).  n: power of two 16..2048. */
 turpy_status turpy_receiver_workspace_size(int32_t n, int64_t batch, size_t* bytes);
 turpy_status turpy_receiver(int32_t n, double dx, double aperture_diameter, int64_t batch, const void* u,
                             const float* theta1, const float* theta2, void* u_out, void* ws,
                             size_t ws_bytes, void* stream);
 
 /* Adjoint of turpy_receiver: given grad_out [batch][n][n] returns
- * grad_u [batch][n][n] (or NULL), and dL/dtheta1, dL/dtheta2 [n][n] summed
- * over the batch (theta2 gradient in centred order; either may be NULL). */
+ * grad_u [batch][n][n] (or NULL), and dL/dtheta1, dL/dtheta2 float [n][n]
+ * summed over the batch (theta2 gradient in centred order; either may be
+ * NULL).  The batch sums are taken in a fixed order (bitwise reproducible).
+ * ws: turpy_receiver_workspace_size(n, batch) bytes. */
 turpy_status turpy_receiver_backward(int32_t n, double dx, double aperture_diameter, int64_t batch,
                                      const void* u, const float* theta1, const float* theta2,
                                      const void* grad_out, void* grad_u, float* grad_theta1,
@@ -186,7 +189,8 @@ turpy_status turpy_receiver_backward(int32_t n, double dx, double aperture_diame
  * starts bracketing every kernel the library enqueues with a pair of HIP events
  * on that kernel's stream; turpy_profile(0) stops recording.  Kernel families:
  * "row_fwd", "row_bwd", "row_plain", "col", "synth", "sh", "evolve", "stats",
- * "finalize", "copy".  turpy_profile_read waits for the recorded events and
+ * "finalize", "copy", "recv_row", "recv_col", "recv_col_grad", "recv_row_grad",
+ * "recv_reduce".  turpy_profile_read waits for the recorded events and
  * returns the launch count and summed duration (ms) of one family (zero when it
  * never ran).  Host-side state, process-wide; not thread-safe. */
 turpy_status turpy_profile(int32_t enable);

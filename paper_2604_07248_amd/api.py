@@ -158,6 +158,55 @@ class Moments:
         return si, {"si_plane": s[0], "w_2nd": s[1], "w_fit": s[2], "count": int(s[3])}
 
 
+class Receiver:
+    """Dual-domain two-mask receiver on an N x N grid (turpy_receiver)."""
+
+    def __init__(self, n, dx, aperture_diameter=0.3048, device=None):
+        self.n, self.dx, self.diameter = n, dx, aperture_diameter
+        self.device = torch.device(device) if device is not None else torch.device("cuda")
+        self._ws = None
+
+    def forward(self, u, theta1, theta2, out=None):
+        b = u.shape[0]
+        _need(u, torch.complex64, (b, self.n, self.n), "u")
+        _need(theta1, torch.float32, (self.n, self.n), "theta1")
+        _need(theta2, torch.float32, (self.n, self.n), "theta2")
+        out = torch.empty_like(u) if out is None else out
+        B.receiver(self.n, self.dx, self.diameter, b, _ptr(u), _ptr(theta1), _ptr(theta2), _ptr(out), None, 0,
+                   _stream())
+        return out
+
+    def backward(self, u, theta1, theta2, grad_out, want_u=True):
+        b = u.shape[0]
+        _need(grad_out, torch.complex64, (b, self.n, self.n), "grad_out")
+        size = B.receiver_workspace_size(self.n, b)
+        if self._ws is None or self._ws.numel() < size:
+            self._ws = torch.empty(size, dtype=torch.uint8, device=self.device)
+        g_u = torch.empty_like(u) if want_u else None
+        g1 = torch.empty((self.n, self.n), dtype=torch.float32, device=self.device)
+        g2 = torch.empty((self.n, self.n), dtype=torch.float32, device=self.device)
+        B.receiver_backward(self.n, self.dx, self.diameter, b, _ptr(u), _ptr(theta1), _ptr(theta2), _ptr(grad_out),
+                            _ptr(g_u), _ptr(g1), _ptr(g2), _ptr(self._ws), size, _stream())
+        return g_u, g1, g2
+
+
+class ReceiverFn(torch.autograd.Function):
+    """u_out = receiver(u, theta1, theta2) with the hand-written adjoint."""
+
+    @staticmethod
+    def forward(ctx, u, theta1, theta2, rx):
+        u, theta1, theta2 = u.contiguous(), theta1.contiguous(), theta2.contiguous()
+        ctx.rx = rx
+        ctx.save_for_backward(u, theta1, theta2)
+        return rx.forward(u, theta1, theta2)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        u, theta1, theta2 = ctx.saved_tensors
+        g_u, g1, g2 = ctx.rx.backward(u, theta1, theta2, grad_out.contiguous(), want_u=ctx.needs_input_grad[0])
+        return g_u, g1, g2, None
+
+
 class Propagate(torch.autograd.Function):
     """u_out = propagate(u_in, phi) with the hand-written adjoint as backward.
 

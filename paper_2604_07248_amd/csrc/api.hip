@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -413,6 +414,44 @@ turpy_status check_device(const turpy_plan* pl) {
   return TURPY_OK;
 }
 
+constexpr int64_t kRecvChunks = 16;
+
+turpy_status check_receiver_shape(int32_t n, int64_t batch) {
+  if (!pow2(n)) return fail(TURPY_E_INVALID, "receiver: n=%d is not a power of two", n);
+  if (n < 16 || n > 2048) return fail(TURPY_E_UNSUPPORTED, "receiver: n=%d outside 16..2048", n);
+  if (batch < 1 || batch > (int64_t(1) << 31)) return fail(TURPY_E_INVALID, "receiver: batch out of range");
+  return TURPY_OK;
+}
+
+size_t receiver_ws(int32_t n, int64_t batch) {
+  const size_t plane = static_cast<size_t>(n) * n;
+  const int64_t chunks = batch < kRecvChunks ? batch : kRecvChunks;
+  return 2 * align_up(batch * plane * sizeof(float2)) + align_up(chunks * plane * sizeof(float));
+}
+
+// Process-wide FP64-generated twiddle tables per (device, N) for plan-less calls.
+std::mutex g_tw_mutex;
+std::map<std::pair<int, int>, float2*> g_tw_cache;
+
+turpy_status twiddles_for(int n, const float2** out) {
+  int dev = 0;
+  TURPY_HIP(hipGetDevice(&dev), "twiddle table");
+  std::lock_guard<std::mutex> lock(g_tw_mutex);
+  auto it = g_tw_cache.find({dev, n});
+  if (it != g_tw_cache.end()) {
+    *out = it->second;
+    return TURPY_OK;
+  }
+  std::vector<float2> tw(n);
+  for (int i = 0; i < n; ++i) tw[i] = phasor(-static_cast<double>(i) / n);
+  float2* d = nullptr;
+  TURPY_HIP(hipMalloc(&d, n * sizeof(float2)), "twiddle table");
+  TURPY_HIP(hipMemcpy(d, tw.data(), n * sizeof(float2), hipMemcpyHostToDevice), "twiddle table");
+  g_tw_cache[{dev, n}] = d;
+  *out = d;
+  return TURPY_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -681,21 +720,107 @@ turpy_status turpy_profile_read(const char* family, int64_t* launches, double* t
 }
 
 turpy_status turpy_receiver_workspace_size(int32_t n, int64_t batch, size_t* bytes) {
-  (void)n;
-  (void)batch;
   if (!bytes) return fail(TURPY_E_INVALID, "receiver_workspace_size: NULL argument");
-  *bytes = 0;
-  return fail(TURPY_E_UNSUPPORTED, "receiver: not built yet");
+  if (turpy_status st = check_receiver_shape(n, batch)) return st;
+  *bytes = receiver_ws(n, batch);
+  return TURPY_OK;
 }
 
-turpy_status turpy_receiver(int32_t, double, double, int64_t, const void*, const float*, const float*, void*, void*,
-                            size_t, void*) {
-  return fail(TURPY_E_UNSUPPORTED, "receiver: not built yet");
+turpy_status turpy_receiver(int32_t n, double dx, double aperture_diameter, int64_t batch, const void* u,
+                            const float* theta1, const float* theta2, void* u_out, void* ws, size_t ws_bytes,
+                            void* stream) {
+  (void)ws;
+  (void)ws_bytes;
+  if (turpy_status st = check_receiver_shape(n, batch)) return st;
+  if (!u || !theta1 || !theta2 || !u_out) return fail(TURPY_E_INVALID, "receiver: NULL argument");
+  if (!(dx > 0) || !(aperture_diameter > 0)) return fail(TURPY_E_INVALID, "receiver: dx and diameter must be > 0");
+  if (u == u_out) return fail(TURPY_E_INVALID, "receiver: u and u_out must not alias");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const float2* tw = nullptr;
+  if (turpy_status e = twiddles_for(n, &tw)) return e;
+  RecvArgs a{};
+  a.tw = tw;
+  a.n = n;
+  a.batch = batch;
+  a.dx = dx;
+  a.radius2 = 0.25 * aperture_diameter * aperture_diameter;
+  a.theta1 = theta1;
+  a.theta2 = theta2;
+  a.u = static_cast<const float2*>(u);
+  a.out = static_cast<float2*>(u_out);
+  TURPY_HIP(timed("recv_row", st, [&] { return launch_recv_row_in(a, st); }), "receiver: row pass");
+  a.in = a.out;
+  TURPY_HIP(timed("recv_col", st, [&] { return launch_recv_col(a, st); }), "receiver: column pass");
+  RowArgs r{};
+  r.tw = tw;
+  r.in = a.out;
+  r.in_stride = static_cast<int64_t>(n) * n;
+  r.out = a.out;
+  r.R = batch;
+  r.in_spectral = 1;
+  r.scale = 1.0f / n;
+  TURPY_HIP(timed("row_plain", st, [&] { return launch_row(n, r, (batch + 1) / 2, st); }), "receiver: last row pass");
+  return TURPY_OK;
 }
 
-turpy_status turpy_receiver_backward(int32_t, double, double, int64_t, const void*, const float*, const float*,
-                                     const void*, void*, float*, float*, void*, size_t, void*) {
-  return fail(TURPY_E_UNSUPPORTED, "receiver_backward: not built yet");
+turpy_status turpy_receiver_backward(int32_t n, double dx, double aperture_diameter, int64_t batch, const void* u,
+                                     const float* theta1, const float* theta2, const void* grad_out, void* grad_u,
+                                     float* grad_theta1, float* grad_theta2, void* ws, size_t ws_bytes,
+                                     void* stream) {
+  if (turpy_status st = check_receiver_shape(n, batch)) return st;
+  if (!u || !theta1 || !theta2 || !grad_out) return fail(TURPY_E_INVALID, "receiver_backward: NULL argument");
+  if (!(dx > 0) || !(aperture_diameter > 0))
+    return fail(TURPY_E_INVALID, "receiver_backward: dx and diameter must be > 0");
+  const size_t need = receiver_ws(n, batch);
+  if (!ws || ws_bytes < need)
+    return fail(TURPY_E_WORKSPACE, "receiver_backward: workspace %zu < %zu bytes", ws_bytes, need);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const float2* tw = nullptr;
+  if (turpy_status e = twiddles_for(n, &tw)) return e;
+  const size_t plane = static_cast<size_t>(n) * n;
+  char* base = static_cast<char*>(ws);
+  float2* gbuf = reinterpret_cast<float2*>(base);
+  float2* xbuf = reinterpret_cast<float2*>(base + align_up(batch * plane * sizeof(float2)));
+  float* part = reinterpret_cast<float*>(base + 2 * align_up(batch * plane * sizeof(float2)));
+  // G = row FFT of grad_out
+  RowArgs r{};
+  r.tw = tw;
+  r.in = static_cast<const float2*>(grad_out);
+  r.in_stride = static_cast<int64_t>(plane);
+  r.out = gbuf;
+  r.R = batch;
+  r.out_spectral = 1;
+  r.scale = 1.0f;
+  TURPY_HIP(timed("row_plain", st, [&] { return launch_row(n, r, (batch + 1) / 2, st); }),
+            "receiver_backward: row FFT of the gradient");
+  RecvArgs a{};
+  a.tw = tw;
+  a.n = n;
+  a.batch = batch;
+  a.dx = dx;
+  a.radius2 = 0.25 * aperture_diameter * aperture_diameter;
+  a.theta1 = theta1;
+  a.theta2 = theta2;
+  a.u = static_cast<const float2*>(u);
+  a.out = xbuf;
+  a.chunks = static_cast<int>(batch < kRecvChunks ? batch : kRecvChunks);
+  a.partial = part;
+  TURPY_HIP(timed("recv_row", st, [&] { return launch_recv_row_in(a, st); }), "receiver_backward: U1 row FFT");
+  a.in = xbuf;
+  a.in2 = gbuf;
+  a.out = gbuf;
+  TURPY_HIP(timed("recv_col_grad", st, [&] { return launch_recv_col_grad(a, st); }),
+            "receiver_backward: column pass");
+  if (grad_theta2)
+    TURPY_HIP(timed("recv_reduce", st, [&] { return launch_recv_reduce(a, grad_theta2, 1, st); }),
+              "receiver_backward: theta2 reduce");
+  a.in = gbuf;
+  a.out = static_cast<float2*>(grad_u);
+  TURPY_HIP(timed("recv_row_grad", st, [&] { return launch_recv_row_grad(a, st); }), "receiver_backward: row pass");
+  if (grad_theta1)
+    TURPY_HIP(timed("recv_reduce", st, [&] { return launch_recv_reduce(a, grad_theta1, 0, st); }),
+              "receiver_backward: theta1 reduce");
+  return TURPY_OK;
 }
 
 }  // extern "C"

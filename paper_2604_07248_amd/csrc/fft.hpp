@@ -176,4 +176,14 @@ __device__ __forceinline__ void fft(float2 (&x)[E], const Lds& lds, int t, const
   }
 }
 
+// Barriers executed by fft<N, 16, ...>: a group with no transform to do calls
+// this so that every thread of a block passes the same barrier sequence.
+template <int N>
+__device__ __forceinline__ void idle_fft() {
+  constexpr int REM1 = N / 16;
+  constexpr int PASSES = REM1 == 1 ? 1 : (REM1 <= 16 ? 2 : 3);
+#pragma unroll
+  for (int i = 0; i < 2 * (PASSES - 1); ++i) __syncthreads();
+}
+
 }  // namespace turpy

@@ -15,30 +15,11 @@
 // piston) right before the modulation, so the real screens never touch HBM.
 #include "fft.hpp"
 #include "kernels.hpp"
+#include "layout.hpp"
 
 namespace turpy {
 
 namespace {
-
-constexpr int kE = 16;  // elements per thread in every transform
-
-template <int N>
-constexpr int row_groups() {  // rows per block of the row kernels
-  return (256 / (N / kE)) < N ? (256 / (N / kE)) : N;
-}
-template <int N>
-constexpr int row_block() { return row_groups<N>() * (N / kE); }
-template <int N>
-constexpr int col_width() { return N >= 2048 ? 8 : (N < 16 ? N : 16); }
-template <int N>
-constexpr int col_block() { return col_width<N>() * (N / kE); }
-
-// Spread a 1-D block index so that consecutive logical tiles land on the same
-// XCD (blocks are dealt round-robin over the 8 XCDs, each with its own L2).
-__device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t nb) {
-  if (nb % 8u != 0u) return b;
-  return (b % 8u) * (nb / 8u) + b / 8u;
-}
 
 // PSD weighting of Eq. S16/S17 at integer radius^2 q (in bins):
 // amp * exp(-f^2/(2 fm^2)) * (f^2 + f0^2)^(-11/12), f^2 = q df^2; zero at DC.
@@ -55,7 +36,8 @@ __device__ __forceinline__ int signed_bin(int k, int n) { return k < (n >> 1) ? 
 // Row pass.
 // ---------------------------------------------------------------------------
 template <int N, int SCREEN, bool BWD>
-__global__ __launch_bounds__(row_block<N>()) void row_pass_kernel(RowArgs a) {
+__global__ __launch_bounds__(row_block<N>()) __attribute__((amdgpu_waves_per_eu(TURPY_ROW_WAVES, 0)))
+void row_pass_kernel(RowArgs a) {
   constexpr int T = N / kE;
   constexpr int G = row_groups<N>();
   __shared__ float2 smem[G * RowLds::words(N)];
@@ -199,6 +181,193 @@ __global__ __launch_bounds__(row_block<N>()) void row_pass_kernel(RowArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Row pass with a screen, split over the two realizations of a pair.  Half A
+// (realization 2j) finishes the screen row: inverse FFT of the scratch row,
+// subharmonics and piston, keeps Re z and hands Im z to half B through LDS.
+// Half B (realization 2j+1) meanwhile loads and inverse-transforms its own
+// field row.  Then both modulate (or, backward, form dL/dphi and apply the
+// conjugate phase) and transform forward.  Both halves pass the same barrier
+// sequence: a half with no transform at a stage runs idle_fft.
+// ---------------------------------------------------------------------------
+template <int N, int SCREEN, bool BWD>
+__global__ __launch_bounds__(pair_block<N>()) __attribute__((amdgpu_waves_per_eu(TURPY_PAIR_WAVES, 0)))
+void row_pair_kernel(RowArgs a) {
+  constexpr int T = N / kE;
+  constexpr int G = pair_rows<N>();
+  constexpr int HALF = G * T;
+  __shared__ float2 smem[2 * G * RowLds::words(N)];
+  const int role = threadIdx.x / HALF;
+  const int g = (threadIdx.x % HALF) / T;
+  const int t = threadIdx.x % T;
+  const int i0 = blockIdx.x * G + g;
+  const int64_t j = blockIdx.y;
+  const bool has_b = 2 * j + 1 < a.R;
+  const int64_t r = (role == 1 && has_b) ? 2 * j + 1 : 2 * j;
+  const bool writes = role == 0 || has_b;
+  const RowLds lds{smem + (role * G + g) * RowLds::words(N)};
+  float* handoff = reinterpret_cast<float*>(smem + (G + g) * RowLds::words(N));  // half B's buffer
+  const float2* __restrict__ tw = a.tw;
+  const size_t plane = static_cast<size_t>(N) * N;
+  const size_t row_off = static_cast<size_t>(i0) * N;
+  const bool in_spec = a.in_spectral != 0, out_spec = a.out_spectral != 0;
+
+  float ph[kE];
+  float2 x[kE];
+  // stage 1: A -> screen row (scratch) or its phases (materialised); B -> its field row
+  if (role == 0) {
+    if constexpr (SCREEN == ROW_SCRATCH) {
+      const float2* src = a.scratch + j * plane + row_off;
+#pragma unroll
+      for (int m = 0; m < kE; ++m) x[m] = src[t + T * m];
+      fft<N, kE, true>(x, lds, t, tw);
+    } else {
+      constexpr float inv2pi = 0.15915494309189535f;
+      const float* sa = a.screens + (static_cast<size_t>(r) * a.M + a.screen) * plane + row_off;
+#pragma unroll
+      for (int m = 0; m < kE; ++m) ph[m] = sa[t + T * m] * inv2pi;
+      if (in_spec) idle_fft<N>();
+    }
+  } else {
+    const float2* src = a.in + r * a.in_stride + row_off;
+#pragma unroll
+    for (int m = 0; m < kE; ++m) x[m] = src[t + T * m];
+    if (in_spec) {
+      if (a.pre) {
+#pragma unroll
+        for (int m = 0; m < kE; ++m) {
+          const float2 h = a.pre[t + T * m];
+          x[m] = a.conj_tables ? c_mulc(x[m], h) : c_mul(x[m], h);
+        }
+      }
+      fft<N, kE, true>(x, lds, t, tw);
+    } else if (SCREEN == ROW_SCRATCH) {
+      idle_fft<N>();
+    }
+  }
+  // stage 2: phases of both halves
+  if constexpr (SCREEN == ROW_SCRATCH) {
+    if (role == 0) {
+      if (a.sh_levels > 0) {
+        const float2* c = a.sh + (static_cast<size_t>(j) * a.M + a.screen) * 32;
+        const float2 mean = c[24];
+#pragma unroll
+        for (int m = 0; m < kE; ++m) x[m] = c_sub(x[m], mean);
+        for (int p = 0; p < a.sh_levels; ++p) {
+          const float2* cp = c + 8 * p;
+          const float2* phs = a.sh_phasor + static_cast<size_t>(p) * N;
+          const float2 ey = phs[i0];
+          const float2 eyc = make_float2(ey.x, -ey.y);
+          // offsets (m, n): 0 (-1,-1) 1 (-1,0) 2 (-1,1) 3 (0,-1) 4 (0,1) 5 (1,-1) 6 (1,0) 7 (1,1)
+          const float2 dm = c_add(c_add(c_mul(cp[0], eyc), cp[3]), c_mul(cp[5], ey));
+          const float2 d0 = c_add(c_mul(cp[1], eyc), c_mul(cp[6], ey));
+          const float2 dp = c_add(c_add(c_mul(cp[2], eyc), cp[4]), c_mul(cp[7], ey));
+          const float2 sa = c_add(dp, dm);
+          const float2 sb = c_sub(dp, dm);
+#pragma unroll
+          for (int m = 0; m < kE; ++m) {
+            const float2 ex = phs[t + T * m];
+            x[m].x += d0.x + sa.x * ex.x - sb.y * ex.y;
+            x[m].y += d0.y + sa.y * ex.x + sb.x * ex.y;
+          }
+        }
+      }
+#pragma unroll
+      for (int m = 0; m < kE; ++m) {
+        ph[m] = x[m].x;
+        handoff[t + T * m] = x[m].y;
+      }
+    }
+    __syncthreads();
+    if (role == 1) {
+#pragma unroll
+      for (int m = 0; m < kE; ++m) ph[m] = handoff[t + T * m];
+    }
+    __syncthreads();
+  } else {
+    if (role == 1) {
+      constexpr float inv2pi = 0.15915494309189535f;
+      const float* sb = a.screens + (static_cast<size_t>(r) * a.M + a.screen) * plane + row_off;
+#pragma unroll
+      for (int m = 0; m < kE; ++m) ph[m] = sb[t + T * m] * inv2pi;
+    }
+  }
+
+  // the pointwise step of Eq. 1 (or its adjoint) and the forward transform
+  auto finish = [&]() {
+    const size_t ck = (static_cast<size_t>(r) * a.M + a.screen) * plane + row_off;
+    if constexpr (!BWD) {
+#pragma unroll
+      for (int m = 0; m < kE; ++m) {
+        float s, c;
+        sincos_rev(ph[m], &s, &c);
+        x[m] = c_mul(x[m], make_float2(c * a.scale, s * a.scale));
+      }
+      if (a.ckpt_out && writes) {
+#pragma unroll
+        for (int m = 0; m < kE; ++m) a.ckpt_out[ck + t + T * m] = x[m];
+      }
+    } else {
+      if (a.grad_screens && writes) {
+#pragma unroll
+        for (int m = 0; m < kE; ++m) {
+          const float2 w = a.ckpt_in[ck + t + T * m];
+          a.grad_screens[ck + t + T * m] = w.x * x[m].y - w.y * x[m].x;  // Im(conj(W) g)
+        }
+      }
+#pragma unroll
+      for (int m = 0; m < kE; ++m) {
+        float s, c;
+        sincos_rev(ph[m], &s, &c);
+        x[m] = c_mul(x[m], make_float2(c * a.scale, -s * a.scale));
+      }
+    }
+    if (out_spec) {
+      fft<N, kE, false>(x, lds, t, tw);
+      if (a.post) {
+#pragma unroll
+        for (int m = 0; m < kE; ++m) {
+          const float2 h = a.post[t + T * m];
+          x[m] = a.conj_tables ? c_mulc(x[m], h) : c_mul(x[m], h);
+        }
+      }
+    }
+    if (writes) {
+      float2* dst = a.out + r * static_cast<int64_t>(plane) + row_off;
+#pragma unroll
+      for (int m = 0; m < kE; ++m) dst[t + T * m] = x[m];
+    }
+  };
+
+  // stage 3: A loads / inverse-transforms its field; B finishes
+  if (role == 0) {
+    const float2* src = a.in + r * a.in_stride + row_off;
+#pragma unroll
+    for (int m = 0; m < kE; ++m) x[m] = src[t + T * m];
+    if (in_spec) {
+      if (a.pre) {
+#pragma unroll
+        for (int m = 0; m < kE; ++m) {
+          const float2 h = a.pre[t + T * m];
+          x[m] = a.conj_tables ? c_mulc(x[m], h) : c_mul(x[m], h);
+        }
+      }
+      fft<N, kE, true>(x, lds, t, tw);
+    } else if (out_spec) {
+      idle_fft<N>();
+    }
+  } else {
+    finish();
+    if (in_spec && !out_spec) idle_fft<N>();
+  }
+  // stage 4: A finishes
+  if (role == 0) {
+    finish();
+  } else if (out_spec) {
+    idle_fft<N>();
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Column pass: FFT along y, x h(k0)/N (x angular-spectrum correction), IFFT.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ float2 angular_correction(int k0, int k1, int n, double dz, double k,
@@ -227,7 +396,8 @@ __device__ __forceinline__ float2 angular_correction(int k0, int k1, int n, doub
 }
 
 template <int N, bool ANGULAR>
-__global__ __launch_bounds__(col_block<N>()) void col_pass_kernel(ColArgs a) {
+__global__ __launch_bounds__(col_block<N>()) __attribute__((amdgpu_waves_per_eu(TURPY_COL_WAVES, 0)))
+void col_pass_kernel(ColArgs a) {
   constexpr int T = N / kE;
   constexpr int K = col_width<N>();
   constexpr int STRIPS = N / K;
@@ -263,7 +433,8 @@ __global__ __launch_bounds__(col_block<N>()) void col_pass_kernel(ColArgs a) {
 // stored spectrum, then the unnormalised inverse transform along y.
 // ---------------------------------------------------------------------------
 template <int N>
-__global__ __launch_bounds__(col_block<N>()) void synth_col_kernel(SynthArgs a) {
+__global__ __launch_bounds__(col_block<N>()) __attribute__((amdgpu_waves_per_eu(TURPY_COL_WAVES, 0)))
+void synth_col_kernel(SynthArgs a) {
   constexpr int T = N / kE;
   constexpr int K = col_width<N>();
   constexpr int STRIPS = N / K;
@@ -517,14 +688,29 @@ hipError_t row_launch(const RowArgs& a, int64_t pairs, hipStream_t s) {
   dim3 block(row_block<N>());
   if (a.screen_mode == ROW_NO_SCREEN)
     hipLaunchKernelGGL((row_pass_kernel<N, ROW_NO_SCREEN, false>), grid, block, 0, s, a);
-  else if (a.screen_mode == ROW_SCRATCH && !a.backward)
-    hipLaunchKernelGGL((row_pass_kernel<N, ROW_SCRATCH, false>), grid, block, 0, s, a);
-  else if (a.screen_mode == ROW_SCRATCH)
-    hipLaunchKernelGGL((row_pass_kernel<N, ROW_SCRATCH, true>), grid, block, 0, s, a);
-  else if (!a.backward)
-    hipLaunchKernelGGL((row_pass_kernel<N, ROW_MATERIALIZED, false>), grid, block, 0, s, a);
-  else
-    hipLaunchKernelGGL((row_pass_kernel<N, ROW_MATERIALIZED, true>), grid, block, 0, s, a);
+  else if (a.phase_out || (pair_rows<N>() * (N / kE)) % 64 != 0) {
+    // screen output, or grids too small for the two halves to sit in separate waves
+    if (a.screen_mode == ROW_SCRATCH && !a.backward)
+      hipLaunchKernelGGL((row_pass_kernel<N, ROW_SCRATCH, false>), grid, block, 0, s, a);
+    else if (a.screen_mode == ROW_SCRATCH)
+      hipLaunchKernelGGL((row_pass_kernel<N, ROW_SCRATCH, true>), grid, block, 0, s, a);
+    else if (!a.backward)
+      hipLaunchKernelGGL((row_pass_kernel<N, ROW_MATERIALIZED, false>), grid, block, 0, s, a);
+    else
+      hipLaunchKernelGGL((row_pass_kernel<N, ROW_MATERIALIZED, true>), grid, block, 0, s, a);
+  } else {
+    constexpr int GP = pair_rows<N>();
+    const dim3 pgrid(N / GP, static_cast<uint32_t>(pairs));
+    const dim3 pblock(pair_block<N>());
+    if (a.screen_mode == ROW_SCRATCH && !a.backward)
+      hipLaunchKernelGGL((row_pair_kernel<N, ROW_SCRATCH, false>), pgrid, pblock, 0, s, a);
+    else if (a.screen_mode == ROW_SCRATCH)
+      hipLaunchKernelGGL((row_pair_kernel<N, ROW_SCRATCH, true>), pgrid, pblock, 0, s, a);
+    else if (!a.backward)
+      hipLaunchKernelGGL((row_pair_kernel<N, ROW_MATERIALIZED, false>), pgrid, pblock, 0, s, a);
+    else
+      hipLaunchKernelGGL((row_pair_kernel<N, ROW_MATERIALIZED, true>), pgrid, pblock, 0, s, a);
+  }
   return hipGetLastError();
 }
 

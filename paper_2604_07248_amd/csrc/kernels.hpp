@@ -114,17 +114,19 @@ struct FinalizeArgs {
 
 struct RecvArgs {
   const float2* tw;
-  const float2* in;
-  float2* out;
+  int n;
   int64_t batch;
   double dx;
   double radius2;           // (aperture diameter / 2)^2
-  const float* theta1;
-  const float* theta2;      // centred order
-  int mode;                 // see kernels.hip
-  const float2* aux;        // second input (backward)
-  float* partial;           // [chunks][n][n] partial mask gradients
-  int chunk;                // batch elements per chunk
+  const float* theta1;      // [n][n] real-space mask (radians)
+  const float* theta2;      // [n][n] Fourier-plane mask, centred (fftshift) order
+  const float2* u;          // receiver input fields [batch][n][n]
+  const float2* in;         // pass input [batch][n][n]
+  const float2* in2;        // second pass input (gradient path)
+  float2* out;              // pass output [batch][n][n]
+  float* partial;           // [chunks][n][n] per-chunk mask-gradient sums
+  int chunks;               // number of batch chunks
+  int conj_mask;            // use exp(-i theta2)
 };
 
 hipError_t launch_row(int n, const RowArgs& a, int64_t pairs, hipStream_t s);
@@ -134,6 +136,12 @@ hipError_t launch_sh(const ShArgs& a, hipStream_t s);
 hipError_t launch_evolve(const EvolveArgs& a, hipStream_t s);
 hipError_t launch_stats(const StatsArgs& a, hipStream_t s);
 hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s);
+// receiver passes (receiver.hip)
+hipError_t launch_recv_row_in(const RecvArgs& a, hipStream_t s);     // U1 = A u e^{i th1}, FFT along x
+hipError_t launch_recv_col(const RecvArgs& a, hipStream_t s);        // FFT_y, x e^{+-i th2}/N, IFFT_y
+hipError_t launch_recv_col_grad(const RecvArgs& a, hipStream_t s);   // th2 gradient partials + gradient path
+hipError_t launch_recv_row_grad(const RecvArgs& a, hipStream_t s);   // th1 gradient partials + grad u
+hipError_t launch_recv_reduce(const RecvArgs& a, float* grad, int centre_shift, hipStream_t s);
 hipError_t launch_copy(const float2* in, int64_t in_stride, float2* out, int64_t count, int64_t R,
                        hipStream_t s);
 

@@ -1,0 +1,53 @@
+// Launch geometry shared by the kernel files: elements per thread, rows per
+// row-pass block, columns per column-pass strip, XCD-aware block order.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace turpy {
+
+constexpr int kE = 16;  // elements per thread in every transform
+
+template <int N>
+constexpr int row_groups() {  // rows per block of the row kernels
+  return (256 / (N / kE)) < N ? (256 / (N / kE)) : N;
+}
+template <int N>
+constexpr int row_block() { return row_groups<N>() * (N / kE); }
+#ifndef TURPY_COL_K
+#define TURPY_COL_K 8
+#endif
+#ifndef TURPY_ROW_WAVES
+#define TURPY_ROW_WAVES 0
+#endif
+#ifndef TURPY_PAIR_WAVES
+#define TURPY_PAIR_WAVES 3
+#endif
+#ifndef TURPY_COL_WAVES
+#define TURPY_COL_WAVES 0
+#endif
+template <int N>
+constexpr int col_width() {
+  return N >= 2048 ? (TURPY_COL_K < 8 ? TURPY_COL_K : 8) : (N < TURPY_COL_K ? N : TURPY_COL_K);
+}
+template <int N>
+constexpr int col_block() { return col_width<N>() * (N / kE); }
+
+// Row-pair pass: each half of a block (whole waves for N >= 64) carries one
+// realization of a pair over `pair_rows` rows.
+template <int N>
+constexpr int pair_rows() {
+  return (128 / (N / kE)) < 1 ? 1 : ((128 / (N / kE)) < N ? (128 / (N / kE)) : N);
+}
+template <int N>
+constexpr int pair_block() { return 2 * pair_rows<N>() * (N / kE); }
+
+// Spread a 1-D block index so that consecutive logical tiles land on the same
+// XCD (blocks are dealt round-robin over the 8 XCDs, each with its own L2).
+__device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t nb) {
+  if (nb % 8u != 0u) return b;
+  return (b % 8u) * (nb / 8u) + b / 8u;
+}
+
+}  // namespace turpy
