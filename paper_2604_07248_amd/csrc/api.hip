@@ -42,6 +42,18 @@ turpy_status hip_fail(hipError_t e, const char* where) {
     if (e_ != hipSuccess) return hip_fail(e_, where); \
   } while (0)
 
+#define TURPY_HIP_E(call)            \
+  do {                               \
+    hipError_t e_ = (call);          \
+    if (e_ != hipSuccess) return e_; \
+  } while (0)
+
+#ifndef TURPY_FUSED_COLUMNS
+#define TURPY_FUSED_COLUMNS 0
+#endif
+// Column passes over realization pairs fused with the next screen's synthesis.
+constexpr bool kFusedColumns = TURPY_FUSED_COLUMNS != 0;
+
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kLog2e = 1.4426950408889634;
 constexpr size_t kAlign = 256;
@@ -350,9 +362,7 @@ ColArgs col_args(const turpy_plan* pl, int step, const float2* in, int64_t in_st
   return c;
 }
 
-// Enqueue the column half of screen s into ws.scratch (noise or stored spectra).
-hipError_t enqueue_screen_col(const turpy_plan* pl, uint64_t seed, uint32_t t, int s, const float2* spectra,
-                              const Ws& w, hipStream_t st) {
+SynthArgs synth_args(const turpy_plan* pl, uint64_t seed, uint32_t t, int s, const float2* spectra, const Ws& w) {
   SynthArgs a{};
   a.tw = pl->d_tw;
   a.scratch = w.scratch;
@@ -367,9 +377,36 @@ hipError_t enqueue_screen_col(const turpy_plan* pl, uint64_t seed, uint32_t t, i
   a.f02 = pl->f02;
   a.spectra = spectra;
   a.M = pl->M;
+  return a;
+}
+
+hipError_t enqueue_screen_col(const turpy_plan* pl, uint64_t seed, uint32_t t, int s, const float2* spectra,
+                              const Ws& w, hipStream_t st) {
+  const SynthArgs a = synth_args(pl, seed, t, s, spectra, w);
   return timed("synth", st, [&] { return launch_synth(pl->n, a, st); });
 }
 
+// Column pass of distance `step` over pairs; with synth_screen >= 0 the same
+// launch synthesises that screen's column half into ws.scratch.
+hipError_t enqueue_col(const turpy_plan* pl, int step, const float2* in, int64_t in_stride, float2* out,
+                       bool adjoint, int synth_screen, uint64_t seed, uint32_t t, const float2* spectra,
+                       const Ws& w, hipStream_t st) {
+  const ColArgs c = col_args(pl, step, in, in_stride, out, pl->R, adjoint);
+  if (!kFusedColumns || pl->n >= 2048) {
+    // separate launches: per-realization column pass, then the screen's column half
+    TURPY_HIP_E(timed("col", st, [&] { return launch_col(pl->n, c, st); }));
+    if (synth_screen >= 0) return enqueue_screen_col(pl, seed, t, synth_screen, spectra, w, st);
+    return hipSuccess;
+  }
+  if (synth_screen >= 0) {
+    const SynthArgs syn = synth_args(pl, seed, t, synth_screen, spectra, w);
+    return timed("col_synth", st, [&] { return launch_col_pair(pl->n, c, syn, 1, st); });
+  }
+  const SynthArgs none{};
+  return timed("col", st, [&] { return launch_col_pair(pl->n, c, none, 0, st); });
+}
+
+// Enqueue the column half of screen s into ws.scratch (noise or stored spectra).
 hipError_t enqueue_sh(const turpy_plan* pl, uint64_t seed, uint32_t t, const Ws& w, hipStream_t st) {
   ShArgs a{};
   a.sh = w.sh;
@@ -507,6 +544,9 @@ turpy_status turpy_propagate(turpy_plan* pl, uint64_t seed, int64_t t, const voi
   const float2* cur = uin;
   int64_t cur_stride = u_in_stride;
   bool spectral = false;
+  const bool synth = src != TURPY_SCREENS_MATERIALIZED;
+  const uint32_t tt = static_cast<uint32_t>(t);
+  bool scratch_ready = false;  // the scratch plane holds the next row pass's screen
   if (pl->dz[0] > 0) {
     // row transform of the source (x h_0(k1)), then the first column pass
     RowArgs a = base_row(pl);
@@ -522,16 +562,19 @@ turpy_status turpy_propagate(turpy_plan* pl, uint64_t seed, int64_t t, const voi
     }
     a.out = dst;
     a.R = rows_r;
-    TURPY_HIP(timed(row_family(a), st, [&] { return launch_row(n, a, (rows_r + 1) / 2, st); }), "propagate: source row transform");
-    ColArgs c = col_args(pl, 0, dst, u_in_stride == 0 ? 0 : plane, uout, pl->R, false);
-    TURPY_HIP(timed("col", st, [&] { return launch_col(n, c, st); }), "propagate: column pass 0");
+    TURPY_HIP(timed(row_family(a), st, [&] { return launch_row(n, a, (rows_r + 1) / 2, st); }),
+              "propagate: source row transform");
+    const int syn = synth && M > 0 ? 0 : -1;
+    TURPY_HIP(enqueue_col(pl, 0, dst, u_in_stride == 0 ? 0 : plane, uout, false, syn, seed, tt, spectra, w, st),
+              "propagate: column pass 0");
+    scratch_ready = syn >= 0;
     cur = uout;
     cur_stride = plane;
     spectral = true;
   }
   for (int s = 0; s < M; ++s) {
-    if (src != TURPY_SCREENS_MATERIALIZED)
-      TURPY_HIP(enqueue_screen_col(pl, seed, static_cast<uint32_t>(t), s, spectra, w, st), "propagate: screen col");
+    if (synth && !scratch_ready)
+      TURPY_HIP(enqueue_screen_col(pl, seed, tt, s, spectra, w, st), "propagate: screen col");
     const bool out_spec = pl->dz[s + 1] > 0;
     RowArgs a = base_row(pl);
     a.in = cur;
@@ -547,9 +590,12 @@ turpy_status turpy_propagate(turpy_plan* pl, uint64_t seed, int64_t t, const voi
     cur = uout;
     cur_stride = plane;
     spectral = out_spec;
+    scratch_ready = false;
     if (out_spec) {
-      ColArgs c = col_args(pl, s + 1, uout, plane, uout, pl->R, false);
-      TURPY_HIP(timed("col", st, [&] { return launch_col(n, c, st); }), "propagate: column pass");
+      const int syn = synth && s + 1 < M ? s + 1 : -1;
+      TURPY_HIP(enqueue_col(pl, s + 1, uout, plane, uout, false, syn, seed, tt, spectra, w, st),
+                "propagate: column pass");
+      scratch_ready = syn >= 0;
     }
   }
   if (spectral) {
@@ -591,6 +637,9 @@ turpy_status turpy_propagate_backward(turpy_plan* pl, uint64_t seed, int64_t t, 
 
   const float2* cur = gout;
   bool spectral = false;
+  const bool synth = src != TURPY_SCREENS_MATERIALIZED;
+  const uint32_t tt = static_cast<uint32_t>(t);
+  bool scratch_ready = false;
   if (pl->dz[M] > 0) {
     RowArgs a = base_row(pl);  // adjoint of the final (1/N) inverse row transform
     a.in = gout;
@@ -598,16 +647,18 @@ turpy_status turpy_propagate_backward(turpy_plan* pl, uint64_t seed, int64_t t, 
     a.out = g;
     a.out_spectral = 1;
     a.scale = inv_n;
-    TURPY_HIP(timed(row_family(a), st, [&] { return launch_row(n, a, pl->P, st); }), "propagate_backward: first row pass");
-    ColArgs c = col_args(pl, M, g, plane, g, pl->R, true);
-    TURPY_HIP(timed("col", st, [&] { return launch_col(n, c, st); }), "propagate_backward: column pass");
+    TURPY_HIP(timed(row_family(a), st, [&] { return launch_row(n, a, pl->P, st); }),
+              "propagate_backward: first row pass");
+    const int syn = synth && M > 0 ? M - 1 : -1;
+    TURPY_HIP(enqueue_col(pl, M, g, plane, g, true, syn, seed, tt, spectra, w, st),
+              "propagate_backward: column pass");
+    scratch_ready = syn >= 0;
     cur = g;
     spectral = true;
   }
   for (int s = M - 1; s >= 0; --s) {
-    if (src != TURPY_SCREENS_MATERIALIZED)
-      TURPY_HIP(enqueue_screen_col(pl, seed, static_cast<uint32_t>(t), s, spectra, w, st),
-                "propagate_backward: screen col");
+    if (synth && !scratch_ready)
+      TURPY_HIP(enqueue_screen_col(pl, seed, tt, s, spectra, w, st), "propagate_backward: screen col");
     const bool out_spec = pl->dz[s] > 0;
     RowArgs a = base_row(pl);
     a.in = cur;
@@ -622,12 +673,16 @@ turpy_status turpy_propagate_backward(turpy_plan* pl, uint64_t seed, int64_t t, 
     a.backward = 1;
     a.ckpt_in = static_cast<const float2*>(checkpoints);
     a.grad_screens = grad_screens;
-    TURPY_HIP(timed(row_family(a), st, [&] { return launch_row(n, a, pl->P, st); }), "propagate_backward: row pass");
+    TURPY_HIP(timed(row_family(a), st, [&] { return launch_row(n, a, pl->P, st); }),
+              "propagate_backward: row pass");
     cur = g;
     spectral = out_spec;
+    scratch_ready = false;
     if (out_spec) {
-      ColArgs c = col_args(pl, s, g, plane, g, pl->R, true);
-      TURPY_HIP(timed("col", st, [&] { return launch_col(n, c, st); }), "propagate_backward: column pass");
+      const int syn = synth && s > 0 ? s - 1 : -1;
+      TURPY_HIP(enqueue_col(pl, s, g, plane, g, true, syn, seed, tt, spectra, w, st),
+                "propagate_backward: column pass");
+      scratch_ready = syn >= 0;
     }
   }
   if (spectral) {

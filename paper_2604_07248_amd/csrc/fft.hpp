@@ -119,8 +119,25 @@ struct ColLds {
   __device__ __forceinline__ float2& operator[](int i) const { return base[i * K + c]; }
 };
 
+// Ordering of an LDS exchange.  A transform whose T threads sit inside one
+// wavefront (T <= 64, groups aligned to the wave) needs no block barrier: the
+// wave waits for its own outstanding LDS operations (lgkmcnt(0)) and the
+// compiler is kept from moving LDS accesses across the point.  Otherwise a
+// block-wide barrier.
+template <bool WAVE>
+__device__ __forceinline__ void lds_sync() {
+  if constexpr (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0), vmcnt / expcnt untouched
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
 // One Stockham pass of radix R at sub-length NS.  tw[i] = exp(-2 pi i * i / N).
-template <int N, int E, int R, int NS, bool INV, bool LAST, class Lds>
+template <int N, int E, int R, int NS, bool INV, bool LAST, bool WAVE, class Lds>
 __device__ __forceinline__ void stockham_pass(float2 (&x)[E], const Lds& lds, int t,
                                               const float2* __restrict__ tw) {
   constexpr int T = N / E;
@@ -153,33 +170,36 @@ __device__ __forceinline__ void stockham_pass(float2 (&x)[E], const Lds& lds, in
     }
   }
   if constexpr (!LAST) {
-    __syncthreads();
+    lds_sync<WAVE>();
 #pragma unroll
     for (int m = 0; m < E; ++m) x[m] = lds[t + T * m];
-    __syncthreads();
+    lds_sync<WAVE>();
   }
 }
 
 // Full length-N transform of the strided-layout registers (unnormalised in
 // both directions; forward uses exp(-2 pi i n k / N)).
-template <int N, int E, bool INV, class Lds>
+// WAVE: the T = N/E threads of the transform lie in one wavefront (see lds_sync).
+template <int N, int E, bool INV, bool WAVE = false, class Lds>
 __device__ __forceinline__ void fft(float2 (&x)[E], const Lds& lds, int t, const float2* __restrict__ tw) {
   static_assert(E == 16, "radix plan written for 16 elements per thread");
   static_assert(N >= 16 && N <= 4096 && (N & (N - 1)) == 0, "N must be a power of two in 16..4096");
+  static_assert(!WAVE || N / E <= 64, "a wave-local transform needs at most 64 threads");
   constexpr int REM1 = N / 16;
-  stockham_pass<N, E, 16, 1, INV, REM1 == 1>(x, lds, t, tw);
+  stockham_pass<N, E, 16, 1, INV, REM1 == 1, WAVE>(x, lds, t, tw);
   if constexpr (REM1 > 1) {
     constexpr int R2 = REM1 >= 16 ? 16 : REM1;
     constexpr int REM2 = REM1 / R2;
-    stockham_pass<N, E, R2, 16, INV, REM2 == 1>(x, lds, t, tw);
-    if constexpr (REM2 > 1) stockham_pass<N, E, REM2, 256, INV, true>(x, lds, t, tw);
+    stockham_pass<N, E, R2, 16, INV, REM2 == 1, WAVE>(x, lds, t, tw);
+    if constexpr (REM2 > 1) stockham_pass<N, E, REM2, 256, INV, true, WAVE>(x, lds, t, tw);
   }
 }
 
 // Barriers executed by fft<N, 16, ...>: a group with no transform to do calls
 // this so that every thread of a block passes the same barrier sequence.
-template <int N>
+template <int N, bool WAVE = false>
 __device__ __forceinline__ void idle_fft() {
+  if constexpr (WAVE) return;
   constexpr int REM1 = N / 16;
   constexpr int PASSES = REM1 == 1 ? 1 : (REM1 <= 16 ? 2 : 3);
 #pragma unroll

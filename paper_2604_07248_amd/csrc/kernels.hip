@@ -40,6 +40,7 @@ __global__ __launch_bounds__(row_block<N>()) __attribute__((amdgpu_waves_per_eu(
 void row_pass_kernel(RowArgs a) {
   constexpr int T = N / kE;
   constexpr int G = row_groups<N>();
+  constexpr bool WV = TURPY_WAVE_SYNC && T <= 64;  // each row's transform lives in one wavefront
   __shared__ float2 smem[G * RowLds::words(N)];
   const int g = threadIdx.x / T;
   const int t = threadIdx.x % T;
@@ -56,7 +57,7 @@ void row_pass_kernel(RowArgs a) {
     const float2* src = a.scratch + j * plane + row_off;
 #pragma unroll
     for (int m = 0; m < kE; ++m) z[m] = src[t + T * m];
-    fft<N, kE, true>(z, lds, t, tw);
+    fft<N, kE, true, WV>(z, lds, t, tw);
     if (a.sh_levels > 0) {
       const float2* c = a.sh + (static_cast<size_t>(j) * a.M + a.screen) * 32;
       const float2 mean = c[24];
@@ -127,7 +128,7 @@ void row_pass_kernel(RowArgs a) {
           x[m] = a.conj_tables ? c_mulc(x[m], h) : c_mul(x[m], h);
         }
       }
-      fft<N, kE, true>(x, lds, t, tw);
+      fft<N, kE, true, WV>(x, lds, t, tw);
     }
     const float* ph = b ? pb : pa;
     if constexpr (SCREEN != ROW_NO_SCREEN) {
@@ -165,7 +166,7 @@ void row_pass_kernel(RowArgs a) {
       }
     }
     if (a.out_spectral) {
-      fft<N, kE, false>(x, lds, t, tw);
+      fft<N, kE, false, WV>(x, lds, t, tw);
       if (a.post) {
 #pragma unroll
         for (int m = 0; m < kE; ++m) {
@@ -195,6 +196,7 @@ void row_pair_kernel(RowArgs a) {
   constexpr int T = N / kE;
   constexpr int G = pair_rows<N>();
   constexpr int HALF = G * T;
+  constexpr bool WV = TURPY_WAVE_SYNC && T <= 64;  // each row's transform lives in one wavefront
   __shared__ float2 smem[2 * G * RowLds::words(N)];
   const int role = threadIdx.x / HALF;
   const int g = (threadIdx.x % HALF) / T;
@@ -219,13 +221,13 @@ void row_pair_kernel(RowArgs a) {
       const float2* src = a.scratch + j * plane + row_off;
 #pragma unroll
       for (int m = 0; m < kE; ++m) x[m] = src[t + T * m];
-      fft<N, kE, true>(x, lds, t, tw);
+      fft<N, kE, true, WV>(x, lds, t, tw);
     } else {
       constexpr float inv2pi = 0.15915494309189535f;
       const float* sa = a.screens + (static_cast<size_t>(r) * a.M + a.screen) * plane + row_off;
 #pragma unroll
       for (int m = 0; m < kE; ++m) ph[m] = sa[t + T * m] * inv2pi;
-      if (in_spec) idle_fft<N>();
+      if (in_spec) idle_fft<N, WV>();
     }
   } else {
     const float2* src = a.in + r * a.in_stride + row_off;
@@ -239,9 +241,9 @@ void row_pair_kernel(RowArgs a) {
           x[m] = a.conj_tables ? c_mulc(x[m], h) : c_mul(x[m], h);
         }
       }
-      fft<N, kE, true>(x, lds, t, tw);
+      fft<N, kE, true, WV>(x, lds, t, tw);
     } else if (SCREEN == ROW_SCRATCH) {
-      idle_fft<N>();
+      idle_fft<N, WV>();
     }
   }
   // stage 2: phases of both halves
@@ -322,7 +324,7 @@ void row_pair_kernel(RowArgs a) {
       }
     }
     if (out_spec) {
-      fft<N, kE, false>(x, lds, t, tw);
+      fft<N, kE, false, WV>(x, lds, t, tw);
       if (a.post) {
 #pragma unroll
         for (int m = 0; m < kE; ++m) {
@@ -351,48 +353,53 @@ void row_pair_kernel(RowArgs a) {
           x[m] = a.conj_tables ? c_mulc(x[m], h) : c_mul(x[m], h);
         }
       }
-      fft<N, kE, true>(x, lds, t, tw);
+      fft<N, kE, true, WV>(x, lds, t, tw);
     } else if (out_spec) {
-      idle_fft<N>();
+      idle_fft<N, WV>();
     }
   } else {
     finish();
-    if (in_spec && !out_spec) idle_fft<N>();
+    if (in_spec && !out_spec) idle_fft<N, WV>();
   }
   // stage 4: A finishes
   if (role == 0) {
     finish();
   } else if (out_spec) {
-    idle_fft<N>();
+    idle_fft<N, WV>();
   }
 }
 
 // ---------------------------------------------------------------------------
 // Column pass: FFT along y, x h(k0)/N (x angular-spectrum correction), IFFT.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ float2 angular_correction(int k0, int k1, int n, double dz, double k,
-                                                     double df) {
-  // H_as / H_fresnel = exp(i dz (s - k + kappa^2/(2k))) = exp(-i dz kappa^4 / (2k (s+k)^2))
-  // for kappa < k (s = sqrt(k^2 - kappa^2)); evanescent bins decay as exp(-dz sqrt(kappa^2 - k^2)).
-  const double kx = signed_bin(k1, n), ky = signed_bin(k0, n);
-  const double kap2 = 4.0 * 3.14159265358979323846 * 3.14159265358979323846 * (kx * kx + ky * ky) * df * df;
-  const double k2 = k * k;
-  if (kap2 < k2) {
-    const double s = sqrt(k2 - kap2);
-    const double d = -dz * kap2 * kap2 / (2.0 * k * (s + k) * (s + k));
-    double rev = d * 0.15915494309189535;
-    rev -= rint(rev);
-    float sn, cs;
-    sincos_rev(static_cast<float>(rev), &sn, &cs);
-    return make_float2(cs, sn);
-  }
-  // exp(-dz sqrt(kappa^2 - k^2)) exp(-i k dz) / exp(-i dz kappa^2 / (2k))
-  const double mag = exp(-dz * sqrt(kap2 - k2));
+// Evanescent bins (kappa >= k): exp(-dz sqrt(kappa^2 - k^2)) exp(-i k dz) / exp(-i dz kappa^2 / (2k)),
+// with the large phase reduced in FP64.  Rare; kept out of line so that it
+// does not hold registers in the common path.
+__device__ __attribute__((noinline)) float2 evanescent_correction(float kap2f, double dz, double k) {
+  const double kap2 = kap2f;
+  const double decay = dz * sqrt(kap2 - k * k);
+  if (decay > 87.0) return make_float2(0.0f, 0.0f);  // below FP32's smallest normal
+  const double mag = exp(-decay);
   double rev = (-k * dz + dz * kap2 / (2.0 * k)) * 0.15915494309189535;
   rev -= rint(rev);
   float sn, cs;
   sincos_rev(static_cast<float>(rev), &sn, &cs);
   return make_float2(static_cast<float>(mag) * cs, static_cast<float>(mag) * sn);
+}
+
+// H_as / H_fresnel = exp(i dz (s - k + kappa^2/(2k))) = exp(-i dz kappa^4 / (2k (s+k)^2)),
+// s = sqrt(k^2 - kappa^2): a small, well-conditioned angle evaluated in FP32.
+__device__ __forceinline__ float2 angular_correction(int k0, int k1, int n, double dz, double k, double df) {
+  const float kx = static_cast<float>(signed_bin(k1, n)), ky = static_cast<float>(signed_bin(k0, n));
+  const float w = 6.283185307179586f * static_cast<float>(df);
+  const float kap2 = (kx * kx + ky * ky) * (w * w);
+  const float kf = static_cast<float>(k);
+  if (kap2 >= kf * kf) return evanescent_correction(kap2, dz, k);
+  const float sp = kf * sqrtf(1.0f - kap2 / (kf * kf)) + kf;
+  const float d = -static_cast<float>(dz) * kap2 * kap2 / (2.0f * kf * sp * sp);
+  float sn, cs;
+  sincos_rev(d * 0.15915494309189535f, &sn, &cs);
+  return make_float2(cs, sn);
 }
 
 template <int N, bool ANGULAR>
@@ -472,6 +479,107 @@ void synth_col_kernel(SynthArgs a) {
   float2* dst = a.scratch + j * static_cast<int64_t>(N) * N + k1;
 #pragma unroll
   for (int m = 0; m < kE; ++m) dst[static_cast<size_t>(t + T * m) * N] = x[m];
+}
+
+// ---------------------------------------------------------------------------
+// Column pass over a realization pair, fused with the column half of the next
+// screen's synthesis.  Block (strip, j): the loads of field 2j's strip are
+// issued first; while they are in flight the block draws the pair's noise (or
+// reads its stored spectrum), weights it and inverse-transforms it along y
+// into the scratch plane; then fields 2j and 2j+1 get FFT_y, x h(k0)/N and
+// IFFT_y.  The screen's column synthesis can only run after the previous row
+// pass consumed the scratch plane, which is exactly when this pass runs.
+// ---------------------------------------------------------------------------
+template <int N>
+__device__ __forceinline__ void synth_column(float2 (&z)[kE], const SynthArgs& a, int64_t j, int k1, int t) {
+  constexpr int T = N / kE;
+  if (a.spectra) {
+    constexpr float inv2pi = 0.15915494309189535f;
+    const float2* src = a.spectra + (static_cast<size_t>(j) * a.M + a.screen) * N * N + k1;
+#pragma unroll
+    for (int m = 0; m < kE; ++m) z[m] = c_scale(src[static_cast<size_t>(t + T * m) * N], inv2pi);
+  } else {
+    const int kx = signed_bin(k1, N);
+#pragma unroll
+    for (int m = 0; m < kE / 2; ++m) {
+      const int k0 = t + T * m;  // < N/2
+      const uint32_t e = static_cast<uint32_t>(k0) * N + k1;
+      const uint4 v = philox4x32_10(noise_counter(e, a.t, static_cast<uint32_t>(j), a.tag, a.screen), a.key0,
+                                    a.key1);
+      const int ky_hi = k0 - N / 2;
+      const float w_lo = psd_amp(k0 * k0 + kx * kx, a.amp, a.df2, a.inner, a.f02);
+      const float w_hi = psd_amp(ky_hi * ky_hi + kx * kx, a.amp, a.df2, a.inner, a.f02);
+      z[m] = c_scale(box_muller(v.x, v.y), w_lo);
+      z[m + kE / 2] = c_scale(box_muller(v.z, v.w), w_hi);
+    }
+  }
+}
+
+template <int N, bool ANGULAR>
+__device__ __forceinline__ void col_transfer(float2 (&x)[kE], const ColArgs& a, int k1, int t) {
+  constexpr int T = N / kE;
+#pragma unroll
+  for (int m = 0; m < kE; ++m) {
+    const int k0 = t + T * m;
+    float2 h = a.table[k0];
+    if constexpr (ANGULAR) h = c_mul(h, angular_correction(k0, k1, N, a.dz, a.k, a.df));
+    x[m] = a.conj_table ? c_mulc(x[m], h) : c_mul(x[m], h);
+  }
+}
+
+template <int N, bool ANGULAR, bool SYNTH>
+__global__ __launch_bounds__(col_block<N>()) __attribute__((amdgpu_waves_per_eu(TURPY_COL_WAVES, 0)))
+void col_pair_kernel(ColArgs a, SynthArgs syn) {
+  constexpr int T = N / kE;
+  constexpr int K = col_width<N>();
+  constexpr int STRIPS = N / K;
+  __shared__ float2 smem[N * K];
+  const uint32_t bid = xcd_remap(blockIdx.x, gridDim.x);
+  const int strip = bid % STRIPS;
+  const int64_t j = bid / STRIPS;
+  const int c = threadIdx.x % K;
+  const int t = threadIdx.x / K;
+  const int k1 = strip * K + c;
+  const ColLds<K> lds{smem, c};
+  const float2* __restrict__ tw = a.tw;
+  const size_t plane = static_cast<size_t>(N) * N;
+  const int64_t ra = 2 * j, rb = 2 * j + 1;
+
+  float2 x[kE];
+  const float2* sa = a.in + ra * a.in_stride + k1;
+#if TURPY_COL_PREFETCH
+#pragma unroll
+  for (int m = 0; m < kE; ++m) x[m] = sa[static_cast<size_t>(t + T * m) * N];
+#endif
+  if constexpr (SYNTH) {
+    float2 z[kE];
+    synth_column<N>(z, syn, j, k1, t);
+    fft<N, kE, true>(z, lds, t, tw);
+    float2* dz = syn.scratch + j * static_cast<int64_t>(plane) + k1;
+#pragma unroll
+    for (int m = 0; m < kE; ++m) dz[static_cast<size_t>(t + T * m) * N] = z[m];
+  }
+#if !TURPY_COL_PREFETCH
+#pragma unroll
+  for (int m = 0; m < kE; ++m) x[m] = sa[static_cast<size_t>(t + T * m) * N];
+#endif
+  fft<N, kE, false>(x, lds, t, tw);
+  col_transfer<N, ANGULAR>(x, a, k1, t);
+  fft<N, kE, true>(x, lds, t, tw);
+  float2* da = a.out + ra * static_cast<int64_t>(plane) + k1;
+#pragma unroll
+  for (int m = 0; m < kE; ++m) da[static_cast<size_t>(t + T * m) * N] = x[m];
+  if (rb < a.R) {  // uniform over the block
+    const float2* sb = a.in + rb * a.in_stride + k1;
+#pragma unroll
+    for (int m = 0; m < kE; ++m) x[m] = sb[static_cast<size_t>(t + T * m) * N];
+    fft<N, kE, false>(x, lds, t, tw);
+    col_transfer<N, ANGULAR>(x, a, k1, t);
+    fft<N, kE, true>(x, lds, t, tw);
+    float2* db = a.out + rb * static_cast<int64_t>(plane) + k1;
+#pragma unroll
+    for (int m = 0; m < kE; ++m) db[static_cast<size_t>(t + T * m) * N] = x[m];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -726,6 +834,22 @@ hipError_t col_launch(const ColArgs& a, hipStream_t s) {
 }
 
 template <int N>
+hipError_t col_pair_launch(const ColArgs& a, const SynthArgs& syn, int do_synth, hipStream_t s) {
+  constexpr int K = col_width<N>();
+  const int64_t pairs = (a.R + 1) / 2;
+  const dim3 grid(static_cast<uint32_t>(static_cast<uint64_t>(N / K) * pairs));
+  const dim3 block(col_block<N>());
+  if (a.angular) {
+    if (do_synth) hipLaunchKernelGGL((col_pair_kernel<N, true, true>), grid, block, 0, s, a, syn);
+    else hipLaunchKernelGGL((col_pair_kernel<N, true, false>), grid, block, 0, s, a, syn);
+  } else {
+    if (do_synth) hipLaunchKernelGGL((col_pair_kernel<N, false, true>), grid, block, 0, s, a, syn);
+    else hipLaunchKernelGGL((col_pair_kernel<N, false, false>), grid, block, 0, s, a, syn);
+  }
+  return hipGetLastError();
+}
+
+template <int N>
 hipError_t synth_launch(const SynthArgs& a, hipStream_t s) {
   constexpr int K = col_width<N>();
   const uint64_t blocks = static_cast<uint64_t>(N / K) * a.P;
@@ -753,6 +877,9 @@ hipError_t launch_row(int n, const RowArgs& a, int64_t pairs, hipStream_t s) {
 }
 hipError_t launch_col(int n, const ColArgs& a, hipStream_t s) { TURPY_DISPATCH_N(n, col_launch, a, s) }
 hipError_t launch_synth(int n, const SynthArgs& a, hipStream_t s) { TURPY_DISPATCH_N(n, synth_launch, a, s) }
+hipError_t launch_col_pair(int n, const ColArgs& c, const SynthArgs& syn, int do_synth, hipStream_t s) {
+  TURPY_DISPATCH_N(n, col_pair_launch, c, syn, do_synth, s)
+}
 
 hipError_t launch_sh(const ShArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(sh_kernel, dim3(static_cast<uint32_t>(a.P), a.M), dim3(64), 0, s, a);

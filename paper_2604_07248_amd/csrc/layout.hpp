@@ -21,8 +21,14 @@ constexpr int row_block() { return row_groups<N>() * (N / kE); }
 #ifndef TURPY_ROW_WAVES
 #define TURPY_ROW_WAVES 0
 #endif
+#ifndef TURPY_WAVE_SYNC
+#define TURPY_WAVE_SYNC 0
+#endif
 #ifndef TURPY_PAIR_WAVES
 #define TURPY_PAIR_WAVES 3
+#endif
+#ifndef TURPY_COL_PREFETCH
+#define TURPY_COL_PREFETCH 1
 #endif
 #ifndef TURPY_COL_WAVES
 #define TURPY_COL_WAVES 0
