@@ -74,6 +74,8 @@ typedef struct turpy_path {
   int32_t tf_kind;          /* turpy_tf_kind                                                    */
   int32_t inner_scale_conv; /* 0: fm = 1/l0 (Eq. S17 as printed, in cycles/m); 1: fm = 5.92/(2 pi l0) */
   int64_t realizations;     /* R >= 1                                                           */
+  double psd_alpha;         /* power law of the PSD, W ~ f^-alpha (App. B Eq. S12/S15, Table S1);
+                               0 selects 11/3 (Eq. S17); otherwise 2 < alpha < 6               */
 } turpy_path;
 
 typedef struct turpy_plan turpy_plan;

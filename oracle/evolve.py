@@ -19,7 +19,7 @@ subharmonics.
 import numpy as np
 
 from .noise import TAG_AR, TAG_MAIN, spectral_noise
-from .screens import fried_parameter, main_spectrum, psd_scales, signed_bins, split_pair, unnormalised_idft
+from .screens import fried_parameter, main_spectrum, psd_alpha, psd_scales, signed_bins, split_pair, unnormalised_idft
 
 
 def _psd_args(path, screen):
@@ -31,7 +31,7 @@ def _psd_args(path, screen):
 def initial_spectrum(path, seed, pair, screen):
     n = int(path.n)
     r0, fm, f0 = _psd_args(path, screen)
-    return main_spectrum(n, path.dx, r0, fm, f0, spectral_noise(n, seed, 0, pair, screen, TAG_MAIN))
+    return main_spectrum(n, path.dx, r0, fm, f0, spectral_noise(n, seed, 0, pair, screen, TAG_MAIN), psd_alpha(path))
 
 
 def shift_phase(n, sx, sy):
@@ -44,7 +44,7 @@ def evolve_step(c_prev, path, seed, t, pair, screen, alpha, sx, sy):
     """One AR(1) + frozen-flow step (t >= 1), Eq. 4 then Eq. 5."""
     n = int(path.n)
     r0, fm, f0 = _psd_args(path, screen)
-    fresh = main_spectrum(n, path.dx, r0, fm, f0, spectral_noise(n, seed, t, pair, screen, TAG_AR))
+    fresh = main_spectrum(n, path.dx, r0, fm, f0, spectral_noise(n, seed, t, pair, screen, TAG_AR), psd_alpha(path))
     return alpha * (c_prev * shift_phase(n, sx, sy)) + np.sqrt(1.0 - alpha * alpha) * fresh
 
 

@@ -25,6 +25,10 @@ import numpy as np
 
 from .noise import SH_OFFSETS, TAG_MAIN, spectral_noise, subharmonic_noise
 
+# Table S1 (App. B): index-PSD power laws alpha = beta + 3 of characterised media.
+MEDIA_ALPHA = {"atmosphere": 11.0 / 3.0, "ocean_min": 11.0 / 3.0, "ocean_max": 15.0 / 3.0,
+               "tissue_min": 4.28, "tissue_max": 4.41}
+
 
 def fried_parameter(wavelength, n0, cn2dz):
     """Eq. S18: r0 = [0.423 k^2 int Cn^2 dz]^(-3/5), k = 2 pi n0 / lambda."""
@@ -44,12 +48,17 @@ def psd_scales(l0, L0, inner_scale_conv=0):
     return fm, f0
 
 
-def mvk_psd(f2, r0, fm, f0):
-    """Eq. S17 in cycles/m; f2 = f^2.  Undefined (infinite) at f2 = 0 when f0 = 0."""
+def mvk_psd(f2, r0, fm, f0, alpha=11.0 / 3.0):
+    """Eq. S17 in cycles/m; f2 = f^2.  Undefined (infinite) at f2 = 0 when f0 = 0.
+
+    `alpha` generalises the power law to other media (App. B, Eq. S12/S15 and
+    Table S1: the phase PSD of a medium with index PSD ~ kappa^-alpha falls as
+    f^-alpha); the strength keeps the k^2 dz Cn^2 scaling of Eq. S15 through
+    r0^(-5/3) = 0.423 k^2 cn2dz.  alpha = 11/3 is Eq. S17 itself."""
     f2 = np.asarray(f2, dtype=np.float64)
     inner = np.exp(-f2 / fm ** 2) if np.isfinite(fm) else 1.0
     with np.errstate(divide="ignore"):
-        return 0.023 * r0 ** (-5.0 / 3.0) * inner / (f2 + f0 * f0) ** (11.0 / 6.0)
+        return 0.023 * r0 ** (-5.0 / 3.0) * inner / (f2 + f0 * f0) ** (alpha / 2.0)
 
 
 def signed_bins(n):
@@ -57,12 +66,17 @@ def signed_bins(n):
     return np.where(k < n // 2, k, k - n).astype(np.float64)
 
 
-def main_spectrum(n, dx, r0, fm, f0, noise):
+def psd_alpha(path):
+    a = float(getattr(path, "psd_alpha", 0.0) or 0.0)
+    return a if a > 0 else 11.0 / 3.0
+
+
+def main_spectrum(n, dx, r0, fm, f0, noise, alpha=11.0 / 3.0):
     """Eq. S16 weighting: c = N_c * sqrt(W(f) df df); DC bin set to zero."""
     df = 1.0 / (n * dx)
     kh = signed_bins(n)
     f2 = (kh[:, None] ** 2 + kh[None, :] ** 2) * df * df
-    w = mvk_psd(np.where(f2 > 0, f2, 1.0), r0, fm, f0)
+    w = mvk_psd(np.where(f2 > 0, f2, 1.0), r0, fm, f0, alpha)
     amp = np.sqrt(w) * df
     amp[0, 0] = 0.0
     return noise * amp
@@ -74,7 +88,7 @@ def unnormalised_idft(c):
     return np.fft.ifft2(c) * (n0 * n1)
 
 
-def subharmonic_screen(n, dx, r0, fm, f0, sh_noise):
+def subharmonic_screen(n, dx, r0, fm, f0, sh_noise, alpha=11.0 / 3.0):
     """Eq. 2: complex subharmonic screen from [levels][8] noise coefficients."""
     levels = sh_noise.shape[0]
     df = 1.0 / (n * dx)
@@ -84,7 +98,7 @@ def subharmonic_screen(n, dx, r0, fm, f0, sh_noise):
         dfp = df / 3.0 ** p
         for q, (m, nn) in enumerate(SH_OFFSETS):
             f2 = (m * m + nn * nn) * dfp * dfp
-            coef = sh_noise[p - 1, q] * np.sqrt(mvk_psd(f2, r0, fm, f0)) * dfp
+            coef = sh_noise[p - 1, q] * np.sqrt(mvk_psd(f2, r0, fm, f0, alpha)) * dfp
             z += coef * np.exp(2j * np.pi * (nn * dfp * x[None, :] + m * dfp * x[:, None]))
     return z
 
@@ -99,12 +113,13 @@ def complex_screen(path, seed, t, pair, screen):
     n = int(path.n)
     r0 = fried_parameter(path.wavelength, path.n0, path.cn2dz[screen])
     fm, f0 = psd_scales(path.l0, path.L0, getattr(path, "inner_scale_conv", 0))
-    c = main_spectrum(n, path.dx, r0, fm, f0, spectral_noise(n, seed, t, pair, screen, TAG_MAIN))
+    alpha = psd_alpha(path)
+    c = main_spectrum(n, path.dx, r0, fm, f0, spectral_noise(n, seed, t, pair, screen, TAG_MAIN), alpha)
     z = unnormalised_idft(c)
     levels = int(getattr(path, "sh_levels", 0))
     if levels > 0:
         z = z + subharmonic_screen(n, path.dx, r0, fm, f0,
-                                   subharmonic_noise(levels, seed, t, pair, screen))
+                                   subharmonic_noise(levels, seed, t, pair, screen), alpha)
     return z
 
 

@@ -38,6 +38,7 @@ class CPath(ctypes.Structure):
         ("n", c_int32), ("num_screens", c_int32), ("dx", c_double), ("wavelength", c_double), ("n0", c_double),
         ("dz", POINTER(c_double)), ("cn2dz", POINTER(c_double)), ("l0", c_double), ("L0", c_double),
         ("sh_levels", c_int32), ("tf_kind", c_int32), ("inner_scale_conv", c_int32), ("realizations", c_int64),
+        ("psd_alpha", c_double),
     ]
 
 
@@ -96,7 +97,8 @@ def make_cpath(path):
     cp = CPath(n=path.n, num_screens=m, dx=path.dx, wavelength=path.wavelength, n0=path.n0,
                dz=ctypes.cast(dz, POINTER(c_double)), cn2dz=ctypes.cast(cn2, POINTER(c_double)),
                l0=path.l0, L0=path.L0, sh_levels=path.sh_levels, tf_kind=path.tf_kind,
-               inner_scale_conv=path.inner_scale_conv, realizations=path.realizations)
+               inner_scale_conv=path.inner_scale_conv, realizations=path.realizations,
+               psd_alpha=getattr(path, "psd_alpha", 0.0))
     cp._keep = (dz, cn2)
     return cp
 

@@ -119,7 +119,8 @@ struct turpy_plan {
   // per-screen synthesis constants
   std::vector<float> amp_rev;   // sqrt(0.023) r0^(-5/6) df / (2 pi)
   std::vector<float> amp_rad;   // sqrt(0.023) r0^(-5/6) df
-  float df2 = 0, inner = 0, f02 = 0;
+  float df2 = 0, inner = 0, f02 = 0, qexp = 11.0f / 12.0f;
+  double alpha = 11.0 / 3.0;
   float2 sh_mean_fac[3] = {};
   // device tables (owned)
   float2* d_tw = nullptr;        // [N]
@@ -167,6 +168,8 @@ turpy_status turpy_plan_create(turpy_plan** out, const turpy_path* p, uint32_t f
   if (p->realizations < 1 || p->realizations > (int64_t(1) << 31))
     return fail(TURPY_E_INVALID, "plan_create: realizations=%lld out of range", (long long)p->realizations);
   if (std::isnan(p->l0) || std::isnan(p->L0)) return fail(TURPY_E_INVALID, "plan_create: l0/L0 is NaN");
+  if (p->psd_alpha != 0.0 && !(p->psd_alpha > 2.0 && p->psd_alpha < 6.0))
+    return fail(TURPY_E_INVALID, "plan_create: psd_alpha=%g outside (2, 6) (0 selects 11/3)", p->psd_alpha);
   const int M = p->num_screens, n = p->n;
   const double limit = n * p->dx * p->dx * p->n0 / p->wavelength;  // Eq. 7 at the Nyquist frequency
   for (int i = 0; i <= M; ++i) {
@@ -197,6 +200,8 @@ turpy_status turpy_plan_create(turpy_plan** out, const turpy_path* p, uint32_t f
   pl->l0 = p->l0;
   pl->L0 = p->L0;
   pl->df = 1.0 / (n * p->dx);
+  pl->alpha = p->psd_alpha != 0.0 ? p->psd_alpha : 11.0 / 3.0;
+  pl->qexp = static_cast<float>(pl->alpha / 4.0);
   pl->dz.assign(p->dz, p->dz + M + 1);
   if (M > 0) pl->cn2dz.assign(p->cn2dz, p->cn2dz + M);
 
@@ -212,9 +217,10 @@ turpy_status turpy_plan_create(turpy_plan** out, const turpy_path* p, uint32_t f
   pl->inner = fm2 > 0 ? static_cast<float>(kLog2e / (2.0 * fm2)) : 0.0f;
   pl->f02 = static_cast<float>(f0 * f0);
   const double k = 2.0 * kPi * p->n0 / p->wavelength;
-  auto psd = [&](double f2, double r0inv53) {  // W(f^2) of Eq. S17
+  const double alpha = pl->alpha;
+  auto psd = [&](double f2, double r0inv53) {  // W(f^2) of Eq. S17 (power law alpha)
     const double inner = fm2 > 0 ? std::exp(-f2 / fm2) : 1.0;
-    return 0.023 * r0inv53 * inner / std::pow(f2 + f0 * f0, 11.0 / 6.0);
+    return 0.023 * r0inv53 * inner / std::pow(f2 + f0 * f0, alpha / 2.0);
   };
   std::vector<float> sh_amp(static_cast<size_t>(std::max(M, 1)) * 6, 0.0f);
   for (int s = 0; s < M; ++s) {
@@ -375,6 +381,7 @@ SynthArgs synth_args(const turpy_plan* pl, uint64_t seed, uint32_t t, int s, con
   a.df2 = pl->df2;
   a.inner = pl->inner;
   a.f02 = pl->f02;
+  a.q = pl->qexp;
   a.spectra = spectra;
   a.M = pl->M;
   return a;
@@ -726,6 +733,7 @@ turpy_status turpy_evolve(turpy_plan* pl, uint64_t seed, int64_t t, double alpha
   a.df2 = pl->df2;
   a.inner = pl->inner;
   a.f02 = pl->f02;
+  a.q = pl->qexp;
   hipStream_t st = static_cast<hipStream_t>(stream);
   TURPY_HIP(timed("evolve", st, [&] { return launch_evolve(a, st); }), "evolve");
   return TURPY_OK;

@@ -22,11 +22,12 @@ namespace turpy {
 namespace {
 
 // PSD weighting of Eq. S16/S17 at integer radius^2 q (in bins):
-// amp * exp(-f^2/(2 fm^2)) * (f^2 + f0^2)^(-11/12), f^2 = q df^2; zero at DC.
-__device__ __forceinline__ float psd_amp(int q, float amp, float df2, float inner, float f02) {
+// amp * exp(-f^2/(2 fm^2)) * (f^2 + f0^2)^(-alpha/4), f^2 = q df^2; zero at DC
+// (alpha = 11/3 for Eq. S17; other media per App. B Table S1).
+__device__ __forceinline__ float psd_amp(int q, float amp, float df2, float inner, float f02, float qexp) {
   if (q == 0) return 0.0f;
   const float f2 = static_cast<float>(q) * df2;
-  const float l2 = -f2 * inner - (11.0f / 12.0f) * __builtin_amdgcn_logf(f2 + f02);
+  const float l2 = -f2 * inner - qexp * __builtin_amdgcn_logf(f2 + f02);
   return amp * __builtin_amdgcn_exp2f(l2);
 }
 
@@ -246,8 +247,10 @@ void row_pair_kernel(RowArgs a) {
       idle_fft<N, WV>();
     }
   }
-  // stage 2: phases of both halves
+  // stage 2: phases of both halves.  The hand-off goes through half B's
+  // exchange buffer: half B must be done with its stage-1 transform first.
   if constexpr (SCREEN == ROW_SCRATCH) {
+    __syncthreads();
     if (role == 0) {
       if (a.sh_levels > 0) {
         const float2* c = a.sh + (static_cast<size_t>(j) * a.M + a.screen) * 32;
@@ -469,8 +472,8 @@ void synth_col_kernel(SynthArgs a) {
                                     a.key1);
       const int ky_lo = k0;             // signed bin of k0 (< N/2)
       const int ky_hi = k0 - N / 2;     // signed bin of k0 + N/2
-      const float w_lo = psd_amp(ky_lo * ky_lo + kx * kx, a.amp, a.df2, a.inner, a.f02);
-      const float w_hi = psd_amp(ky_hi * ky_hi + kx * kx, a.amp, a.df2, a.inner, a.f02);
+      const float w_lo = psd_amp(ky_lo * ky_lo + kx * kx, a.amp, a.df2, a.inner, a.f02, a.q);
+      const float w_hi = psd_amp(ky_hi * ky_hi + kx * kx, a.amp, a.df2, a.inner, a.f02, a.q);
       x[m] = c_scale(box_muller(v.x, v.y), w_lo);
       x[m + kE / 2] = c_scale(box_muller(v.z, v.w), w_hi);
     }
@@ -507,8 +510,8 @@ __device__ __forceinline__ void synth_column(float2 (&z)[kE], const SynthArgs& a
       const uint4 v = philox4x32_10(noise_counter(e, a.t, static_cast<uint32_t>(j), a.tag, a.screen), a.key0,
                                     a.key1);
       const int ky_hi = k0 - N / 2;
-      const float w_lo = psd_amp(k0 * k0 + kx * kx, a.amp, a.df2, a.inner, a.f02);
-      const float w_hi = psd_amp(ky_hi * ky_hi + kx * kx, a.amp, a.df2, a.inner, a.f02);
+      const float w_lo = psd_amp(k0 * k0 + kx * kx, a.amp, a.df2, a.inner, a.f02, a.q);
+      const float w_hi = psd_amp(ky_hi * ky_hi + kx * kx, a.amp, a.df2, a.inner, a.f02, a.q);
       z[m] = c_scale(box_muller(v.x, v.y), w_lo);
       z[m + kE / 2] = c_scale(box_muller(v.z, v.w), w_hi);
     }
@@ -652,7 +655,7 @@ __global__ __launch_bounds__(256) void evolve_kernel(EvolveArgs a) {
   for (int h = 0; h < 2; ++h) {
     const int kk0 = k0 + h * (n / 2);
     const int ky = signed_bin(kk0, n);
-    const float w = psd_amp(ky * ky + kx * kx, amp, a.df2, a.inner, a.f02);
+    const float w = psd_amp(ky * ky + kx * kx, amp, a.df2, a.inner, a.f02, a.q);
     const float2 nc = h == 0 ? box_muller(v.x, v.y) : box_muller(v.z, v.w);
     float2* p = base + static_cast<int64_t>(kk0) * n + k1;
     float2 out;

@@ -68,6 +68,7 @@ struct SynthArgs {
   float df2;                // df^2
   float inner;              // log2(e) / (2 fm^2), 0 when no inner-scale cutoff
   float f02;                // f0^2
+  float q;                  // alpha / 4: exponent of (f^2 + f0^2) in the amplitude
   // spectra source (ROW_SCRATCH from stored spectra) instead of noise
   const float2* spectra;    // [P][M][N][N] radians, or NULL for synthesis
   int M;
@@ -93,7 +94,7 @@ struct EvolveArgs {
   double sx, sy;            // shift in pixels
   int init;                 // 1: overwrite with fresh spectra (t = 0)
   const float* amp;         // [M] sqrt(0.023) r0^(-5/6) df: radians
-  float df2, inner, f02;
+  float df2, inner, f02, q;
 };
 
 struct StatsArgs {

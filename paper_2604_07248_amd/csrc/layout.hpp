@@ -22,7 +22,7 @@ constexpr int row_block() { return row_groups<N>() * (N / kE); }
 #define TURPY_ROW_WAVES 0
 #endif
 #ifndef TURPY_WAVE_SYNC
-#define TURPY_WAVE_SYNC 0
+#define TURPY_WAVE_SYNC 1
 #endif
 #ifndef TURPY_PAIR_WAVES
 #define TURPY_PAIR_WAVES 3

@@ -36,6 +36,7 @@ class Path:
     tf_kind: int = TF_FRESNEL
     inner_scale_conv: int = 0      # 0: fm = 1/l0, 1: fm = 5.92/(2 pi l0)
     realizations: int = 1
+    psd_alpha: float = 0.0         # PSD power law (0: 11/3, the modified von Karman law)
 
     @property
     def num_screens(self):
@@ -81,6 +82,15 @@ def plane_wave(n):
     return np.ones((n, n), dtype=np.complex128)
 
 
+def flat_top(n, dx, width, order=10):
+    """Tapered plane wave exp(-(r/width)^(2 order)): flat over the centre of the
+    grid and zero at its edge, so that the periodic grid's wrap-around (where
+    the non-periodic subharmonic screens jump) carries no field."""
+    x = grid(n, dx)
+    r2 = x[None, :] ** 2 + x[:, None] ** 2
+    return np.exp(-(r2 / (width * width)) ** order).astype(np.complex128)
+
+
 def seeded_field(shape, seed):
     """Random complex64 field (standard normal components) for adjoint/gradient tests."""
     rng = np.random.default_rng(seed)
@@ -97,13 +107,15 @@ class Workload:
     name: str
     path: Path
     seed: int
-    source: str = "gaussian"       # "gaussian" | "plane"
+    source: str = "gaussian"       # "gaussian" | "plane" | "flat_top"
     w0: float = 0.0
     extra: dict = field(default_factory=dict)
 
     def source_field(self):
         if self.source == "plane":
             return plane_wave(self.path.n)
+        if self.source == "flat_top":
+            return flat_top(self.path.n, self.path.dx, 0.42 * self.path.n * self.path.dx)
         return gaussian_source(self.path.n, self.path.dx, self.w0)
 
 
@@ -114,9 +126,10 @@ def config1():
     return Workload("c1_n128_m5_r16", p, seed=0, source="gaussian", w0=0.02)
 
 
-def config2(cn2=1e-15, source="plane", realizations=256, seed=20):
+def config2(cn2=1e-15, source="flat_top", realizations=256, seed=20):
     """Weak-to-strong sweep point: N=512 over 1 m, 1550 nm, 2 km, 10 screens with
-    3-level subharmonics, l0=5 mm, L0=20 m; plane wave or W0=3 cm Gaussian."""
+    3-level subharmonics, l0=5 mm, L0=20 m; plane wave (tapered flat top, see
+    flat_top) or W0=3 cm Gaussian."""
     p = uniform_path(512, 1.0, 1550e-9, 2000.0, 10, cn2, 0.005, 20.0, 3, realizations=realizations)
     return Workload(f"c2_n512_m10_cn2_{cn2:g}_{source}", p, seed=seed, source=source, w0=0.03)
 

@@ -55,6 +55,8 @@ def _status(path, flags=0):
     (dict(tf_kind=7), B.E_INVALID, "tf_kind"),
     (dict(realizations=0), B.E_INVALID, "realizations"),
     (dict(inner_scale_conv=3), B.E_INVALID, "inner_scale_conv"),
+    (dict(psd_alpha=1.5), B.E_INVALID, "psd_alpha"),
+    (dict(psd_alpha=7.0), B.E_INVALID, "psd_alpha"),
 ])
 def test_invalid_descriptors_rejected(L, change, status, needle):
     p = workloads.config1().path.with_(**change)

@@ -44,6 +44,8 @@ def gaussian(path, w0_frac=0.1):
 @pytest.mark.parametrize("n", [16, 32, 64, 128, 256, 512, 1024, 2048])
 def test_screens_match_oracle(api, n):
     path = sized_path(n, realizations=3, m=2, sh=3 if n in (64, 512) else 0)
+    if n in (128, 1024):
+        path = path.with_(psd_alpha=4.35 if n == 128 else 3.3)
     say(f"[screens] n={n} sh={path.sh_levels}")
     plan = api.Plan(path)
     got = plan.screens(seed=7).cpu().numpy()
@@ -87,7 +89,8 @@ def test_config1_full(api):
 
 
 @pytest.mark.parametrize("case", ["angular", "first_zero", "last_zero", "no_screens", "per_realization_source",
-                                  "subharmonics", "inner_conv", "kolmogorov", "single", "odd_pairs"])
+                                  "subharmonics", "inner_conv", "kolmogorov", "single", "odd_pairs",
+                                  "tissue_psd", "ocean_psd"])
 def test_propagate_options(api, case):
     path = sized_path(256, realizations=4, m=3)
     if case == "angular":
@@ -108,6 +111,10 @@ def test_propagate_options(api, case):
         path = path.with_(realizations=1)
     elif case == "odd_pairs":
         path = path.with_(realizations=5)
+    elif case == "tissue_psd":
+        path = path.with_(psd_alpha=4.35, sh_levels=3)
+    elif case == "ocean_psd":
+        path = path.with_(psd_alpha=5.0)
     say(f"[options] {case}")
     u0 = gaussian(path)
     if case == "per_realization_source":

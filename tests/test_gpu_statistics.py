@@ -1,6 +1,9 @@
 """Ensemble statistics of the GPU path against closed forms (Sec. 3.2-3.3):
 config 2 geometry (N=512 over 1 m, 1550 nm, 2 km, 10 screens with 3-level
-subharmonics, l0=5 mm, L0=20 m).  In weak turbulence (Cn2=1e-15, sigma_R^2 =
+subharmonics, l0=5 mm, L0=20 m).  The plane wave is a flat-top taper that is
+zero at the grid edge: subharmonic screens are not periodic on the grid, and a
+field filling the whole periodic grid diffracts off the seam where they wrap
+(SI inflated by ~20 % in the centre and several-fold at the edges).  In weak turbulence (Cn2=1e-15, sigma_R^2 =
 0.071) the plane-wave scintillation index and the Gaussian long-term radius
 must sit within 2 % of the closed forms; the scintillation also matches the
 first-order sum over the discrete screens within its standard error."""
@@ -55,9 +58,9 @@ def test_weak_plane_wave_scintillation(api, variant):
     config2 (l0 = 5 mm, L0 = 20 m): SI equals the first-order sum over its own
     discrete screens (which the inner scale puts 1.6 % below the Kolmogorov
     closed form) within the ensemble's standard error."""
-    w = workloads.config2(cn2=1e-15, source="plane", seed=20)
+    w = workloads.config2(cn2=1e-15, source="flat_top", seed=20)
     if variant == "kolmogorov_limit":
-        w = workloads.Workload(w.name + "_kolmogorov", w.path.with_(l0=0.001, L0=100.0), seed=23, source="plane")
+        w = workloads.Workload(w.name + "_kolmogorov", w.path.with_(l0=0.001, L0=100.0), seed=23, source="flat_top")
     p = w.path
     si_map, s, groups = run_ensemble(api, w, 32768)
     s2 = theory.rytov_plane(1e-15, p.wavelength, p.length)
@@ -88,13 +91,15 @@ def test_weak_gaussian_broadening(api):
     assert abs(s["w_2nd"] / w_lt - 1) < 0.02
 
 
-def test_moderate_turbulence_reported(api):
-    """Cn2 = 1e-14 (sigma_R^2 = 0.71): SI follows the all-regime form, not the
-    linear weak law (the paper's transition regime); looser bounds."""
-    w = workloads.config2(cn2=1e-14, source="plane", seed=22)
+def test_moderate_turbulence_follows_weak_law(api):
+    """Cn2 = 1e-14 (sigma_R^2 = 0.71): the split-step scintillation keeps
+    following the weak-turbulence law SI = sigma_R^2 in this regime, as the
+    paper reports for its simulator up to sigma_R^2 ~ 8 (Sec. 3.3); the
+    all-regime closed form (Eq. S27, 0.56 here) is printed for reference."""
+    w = workloads.config2(cn2=1e-14, source="flat_top", seed=22)
     p = w.path
-    _, s, _ = run_ensemble(api, w, 2048)
+    _, s, _ = run_ensemble(api, w, 4096)
     s2 = theory.rytov_plane(1e-14, p.wavelength, p.length)
     ar = theory.si_all_regimes(s2)
     say(f"[stats] Cn2=1e-14 plane wave: SI {s['si_plane']:.4f}; weak {s2:.4f}; all-regime {ar:.4f}")
-    assert abs(s["si_plane"] / ar - 1) < 0.2
+    assert abs(s["si_plane"] / s2 - 1) < 0.1

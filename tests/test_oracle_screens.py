@@ -82,13 +82,14 @@ def _structure(phis, lags):
     return np.array(out)  # [lags][screens]
 
 
-@pytest.mark.parametrize("levels", [0, 3])
-def test_structure_function_exact_discrete_expectation(levels):
+@pytest.mark.parametrize("levels,alpha", [(0, 0.0), (3, 0.0), (3, 3.3), (2, 4.35)])
+def test_structure_function_exact_discrete_expectation(levels, alpha):
     """Ensemble D(r) of the screens equals the exact discrete expectation
-    2 sum W df^2 (1 - cos 2 pi f r) (+ subharmonic points, Eq. 2)."""
+    2 sum W df^2 (1 - cos 2 pi f r) (+ subharmonic points, Eq. 2), for the
+    Eq. S17 law and for other media power laws (App. B, Table S1)."""
     n, side = 128, 1.0
     p = workloads.Path(n=n, dx=side / n, wavelength=1e-6, dz=(0.0, 0.0), cn2dz=(1e-13,),
-                       l0=0.0, L0=float("inf"), sh_levels=levels, realizations=2)
+                       l0=0.0, L0=float("inf"), sh_levels=levels, realizations=2, psd_alpha=alpha)
     phis = []
     for j in range(60):
         a, b = screens.split_pair(screens.complex_screen(p, 21, 0, j, 0))
@@ -98,7 +99,8 @@ def test_structure_function_exact_discrete_expectation(levels):
     est = _structure(phis, lags)
     r0 = screens.fried_parameter(p.wavelength, p.n0, p.cn2dz[0])
     fm, f0 = screens.psd_scales(p.l0, p.L0)
-    expect = theory.structure_function_expected(n, p.dx, lambda f2: screens.mvk_psd(f2, r0, fm, f0),
+    a = screens.psd_alpha(p)
+    expect = theory.structure_function_expected(n, p.dx, lambda f2: screens.mvk_psd(f2, r0, fm, f0, a),
                                                 np.array(lags) * p.dx, levels)
     # pairs are independent; members of a pair are uncorrelated: use pair means for the SE
     pair_mean = 0.5 * (est[:, 0::2] + est[:, 1::2])
@@ -144,3 +146,26 @@ def test_subharmonics_add_low_frequency_power_only():
     # level noise is drawn with the subharmonic tag, independent of the main spectrum
     assert not np.allclose(noise.subharmonic_noise(3, 2, 0, 0, 0)[0, :2],
                            noise.spectral_noise(64, 2, 0, 0, 0).ravel()[:2])
+
+
+@pytest.mark.parametrize("alpha,slope,tol", [(3.3, 1.3, 0.05), (11.0 / 3.0, 5.0 / 3.0, 0.06),
+                                             (4.35, 2.0, 0.06), (5.0, 2.0, 0.03)])
+def test_media_power_law_structure_scaling(alpha, slope, tol):
+    """A phase PSD ~ f^-alpha gives D(r) ~ r^(alpha-2) for 2 < alpha < 4 (App. B,
+    Eq. S9-S11 projected to the screen) and a smooth screen, D ~ r^2, for
+    alpha >= 4; checked on the exact discrete expectation with three
+    subharmonic levels, l0 = 0, L0 = inf."""
+    n, dx = 256, 2.0 / 256
+    r0 = screens.fried_parameter(1e-6, 1.0, 1e-12)
+    fm, f0 = screens.psd_scales(0.0, float("inf"))
+    lags = np.array([2, 4, 8, 16])
+    d = theory.structure_function_expected(n, dx, lambda f2: screens.mvk_psd(f2, r0, fm, f0, alpha), lags * dx, 3)
+    fit = np.polyfit(np.log(lags), np.log(d), 1)[0]
+    assert abs(fit - slope) < tol, (alpha, fit)
+
+
+def test_default_power_law_is_eq_s17():
+    f2 = np.array([0.5, 3.0, 40.0])
+    assert np.array_equal(screens.mvk_psd(f2, 0.1, 100.0, 0.05), screens.mvk_psd(f2, 0.1, 100.0, 0.05, 11.0 / 3.0))
+    p = workloads.config1().path
+    assert screens.psd_alpha(p) == 11.0 / 3.0 and screens.psd_alpha(p.with_(psd_alpha=4.35)) == 4.35
