@@ -48,7 +48,8 @@ void row_pass_kernel(RowArgs a) {
   const int i0 = blockIdx.x * G + g;
   const int64_t j = blockIdx.y;
   const RowLds lds{smem + g * RowLds::words(N)};
-  const float2* __restrict__ tw = a.tw;
+  __shared__ float2 tw_lds[N];
+  const float2* tw = stage_twiddles<N>(tw_lds, a.tw);
   const size_t plane = static_cast<size_t>(N) * N;
   const size_t row_off = static_cast<size_t>(i0) * N;
 
@@ -209,7 +210,8 @@ void row_pair_kernel(RowArgs a) {
   const bool writes = role == 0 || has_b;
   const RowLds lds{smem + (role * G + g) * RowLds::words(N)};
   float* handoff = reinterpret_cast<float*>(smem + (G + g) * RowLds::words(N));  // half B's buffer
-  const float2* __restrict__ tw = a.tw;
+  __shared__ float2 tw_lds[N];
+  const float2* tw = stage_twiddles<N>(tw_lds, a.tw);
   const size_t plane = static_cast<size_t>(N) * N;
   const size_t row_off = static_cast<size_t>(i0) * N;
   const bool in_spec = a.in_spectral != 0, out_spec = a.out_spectral != 0;
@@ -411,7 +413,7 @@ void col_pass_kernel(ColArgs a) {
   constexpr int T = N / kE;
   constexpr int K = col_width<N>();
   constexpr int STRIPS = N / K;
-  __shared__ float2 smem[N * K];
+  __shared__ float2 smem[ColLds<K>::words(N)];
   const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
   const int strip = b % STRIPS;
   const int64_t r = b / STRIPS;
@@ -419,7 +421,8 @@ void col_pass_kernel(ColArgs a) {
   const int t = threadIdx.x / K;
   const int k1 = strip * K + c;
   const ColLds<K> lds{smem, c};
-  const float2* __restrict__ tw = a.tw;
+  __shared__ float2 tw_lds[N];
+  const float2* tw = stage_twiddles<N>(tw_lds, a.tw);
   const float2* src = a.in + r * a.in_stride + k1;
   float2 x[kE];
 #pragma unroll
@@ -448,7 +451,7 @@ void synth_col_kernel(SynthArgs a) {
   constexpr int T = N / kE;
   constexpr int K = col_width<N>();
   constexpr int STRIPS = N / K;
-  __shared__ float2 smem[N * K];
+  __shared__ float2 smem[ColLds<K>::words(N)];
   const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
   const int strip = b % STRIPS;
   const int64_t j = b / STRIPS;
@@ -456,6 +459,8 @@ void synth_col_kernel(SynthArgs a) {
   const int t = threadIdx.x / K;
   const int k1 = strip * K + c;
   const ColLds<K> lds{smem, c};
+  __shared__ float2 tw_lds[N];
+  const float2* tw = stage_twiddles<N>(tw_lds, a.tw);
   float2 x[kE];
   if (a.spectra) {
     constexpr float inv2pi = 0.15915494309189535f;
@@ -478,7 +483,7 @@ void synth_col_kernel(SynthArgs a) {
       x[m + kE / 2] = c_scale(box_muller(v.z, v.w), w_hi);
     }
   }
-  fft<N, kE, true>(x, lds, t, a.tw);
+  fft<N, kE, true>(x, lds, t, tw);
   float2* dst = a.scratch + j * static_cast<int64_t>(N) * N + k1;
 #pragma unroll
   for (int m = 0; m < kE; ++m) dst[static_cast<size_t>(t + T * m) * N] = x[m];
@@ -536,7 +541,7 @@ void col_pair_kernel(ColArgs a, SynthArgs syn) {
   constexpr int T = N / kE;
   constexpr int K = col_width<N>();
   constexpr int STRIPS = N / K;
-  __shared__ float2 smem[N * K];
+  __shared__ float2 smem[ColLds<K>::words(N)];
   const uint32_t bid = xcd_remap(blockIdx.x, gridDim.x);
   const int strip = bid % STRIPS;
   const int64_t j = bid / STRIPS;
@@ -544,7 +549,8 @@ void col_pair_kernel(ColArgs a, SynthArgs syn) {
   const int t = threadIdx.x / K;
   const int k1 = strip * K + c;
   const ColLds<K> lds{smem, c};
-  const float2* __restrict__ tw = a.tw;
+  __shared__ float2 tw_lds[N];
+  const float2* tw = stage_twiddles<N>(tw_lds, a.tw);
   const size_t plane = static_cast<size_t>(N) * N;
   const int64_t ra = 2 * j, rb = 2 * j + 1;
 

@@ -40,6 +40,8 @@ __global__ __launch_bounds__(row_block<N>()) void recv_row_in_kernel(RecvArgs a)
   const int i0 = blockIdx.x * G + g;
   const int64_t b = blockIdx.y;
   const RowLds lds{smem + g * RowLds::words(N)};
+  __shared__ float2 tw_lds[N];
+  const float2* tw = stage_twiddles<N>(tw_lds, a.tw);
   const size_t row = static_cast<size_t>(i0) * N;
   const float2* src = a.u + b * static_cast<int64_t>(N) * N + row;
   float2 x[kE];
@@ -49,7 +51,7 @@ __global__ __launch_bounds__(row_block<N>()) void recv_row_in_kernel(RecvArgs a)
     const float amp = aperture(i0, i1, N, a.dx, a.radius2);
     x[m] = c_scale(c_mul(src[i1], phase(a.theta1[row + i1])), amp);
   }
-  fft<N, kE, false>(x, lds, t, a.tw);
+  fft<N, kE, false>(x, lds, t, tw);
   float2* dst = a.out + b * static_cast<int64_t>(N) * N + row;
 #pragma unroll
   for (int m = 0; m < kE; ++m) dst[t + T * m] = x[m];
@@ -60,19 +62,21 @@ __global__ __launch_bounds__(col_block<N>()) void recv_col_kernel(RecvArgs a) {
   constexpr int T = N / kE;
   constexpr int K = col_width<N>();
   constexpr int STRIPS = N / K;
-  __shared__ float2 smem[N * K];
+  __shared__ float2 smem[ColLds<K>::words(N)];
   const uint32_t bid = xcd_remap(blockIdx.x, gridDim.x);
   const int strip = bid % STRIPS;
   const int64_t b = bid / STRIPS;
   const int c = threadIdx.x % K, t = threadIdx.x / K;
   const int k1 = strip * K + c;
   const ColLds<K> lds{smem, c};
+  __shared__ float2 tw_lds[N];
+  const float2* tw = stage_twiddles<N>(tw_lds, a.tw);
   const size_t plane = static_cast<size_t>(N) * N;
   const float2* src = a.in + b * plane + k1;
   float2 x[kE];
 #pragma unroll
   for (int m = 0; m < kE; ++m) x[m] = src[static_cast<size_t>(t + T * m) * N];
-  fft<N, kE, false>(x, lds, t, a.tw);
+  fft<N, kE, false>(x, lds, t, tw);
   constexpr float inv_n = 1.0f / N;
 #pragma unroll
   for (int m = 0; m < kE; ++m) {
@@ -81,7 +85,7 @@ __global__ __launch_bounds__(col_block<N>()) void recv_col_kernel(RecvArgs a) {
     if (a.conj_mask) h.y = -h.y;
     x[m] = c_scale(c_mul(x[m], h), inv_n);
   }
-  fft<N, kE, true>(x, lds, t, a.tw);
+  fft<N, kE, true>(x, lds, t, tw);
   float2* dst = a.out + b * plane + k1;
 #pragma unroll
   for (int m = 0; m < kE; ++m) dst[static_cast<size_t>(t + T * m) * N] = x[m];
@@ -96,12 +100,14 @@ __global__ __launch_bounds__(col_block<N>()) void recv_col_grad_kernel(RecvArgs 
   constexpr int T = N / kE;
   constexpr int K = col_width<N>();
   constexpr int STRIPS = N / K;
-  __shared__ float2 smem[N * K];
+  __shared__ float2 smem[ColLds<K>::words(N)];
   const int strip = blockIdx.x % STRIPS;
   const int chunk = blockIdx.x / STRIPS;
   const int c = threadIdx.x % K, t = threadIdx.x / K;
   const int k1 = strip * K + c;
   const ColLds<K> lds{smem, c};
+  __shared__ float2 tw_lds[N];
+  const float2* tw = stage_twiddles<N>(tw_lds, a.tw);
   const size_t plane = static_cast<size_t>(N) * N;
   const int64_t per = (a.batch + a.chunks - 1) / a.chunks;
   const int64_t b0 = chunk * per, b1 = b0 + per < a.batch ? b0 + per : a.batch;
@@ -119,17 +125,17 @@ __global__ __launch_bounds__(col_block<N>()) void recv_col_grad_kernel(RecvArgs 
     const float2* sg = a.in2 + b * plane + k1;
 #pragma unroll
     for (int m = 0; m < kE; ++m) x[m] = sx[static_cast<size_t>(t + T * m) * N];
-    fft<N, kE, false>(x, lds, t, a.tw);
+    fft<N, kE, false>(x, lds, t, tw);
 #pragma unroll
     for (int m = 0; m < kE; ++m) gg[m] = sg[static_cast<size_t>(t + T * m) * N];
-    fft<N, kE, false>(gg, lds, t, a.tw);
+    fft<N, kE, false>(gg, lds, t, tw);
 #pragma unroll
     for (int m = 0; m < kE; ++m) {
       const float2 z = c_mul(x[m], mask[m]);
       acc[m] += (z.x * gg[m].y - z.y * gg[m].x) * inv_n2;  // Im(conj(Z) G) / N^2
       gg[m] = c_scale(c_mulc(gg[m], mask[m]), inv_n);
     }
-    fft<N, kE, true>(gg, lds, t, a.tw);
+    fft<N, kE, true>(gg, lds, t, tw);
     float2* dst = a.out + b * plane + k1;
 #pragma unroll
     for (int m = 0; m < kE; ++m) dst[static_cast<size_t>(t + T * m) * N] = gg[m];
@@ -151,6 +157,8 @@ __global__ __launch_bounds__(row_block<N>()) void recv_row_grad_kernel(RecvArgs 
   const int i0 = blockIdx.x * G + g;
   const int chunk = blockIdx.y;
   const RowLds lds{smem + g * RowLds::words(N)};
+  __shared__ float2 tw_lds[N];
+  const float2* tw = stage_twiddles<N>(tw_lds, a.tw);
   const size_t plane = static_cast<size_t>(N) * N;
   const size_t row = static_cast<size_t>(i0) * N;
   const int64_t per = (a.batch + a.chunks - 1) / a.chunks;
@@ -170,7 +178,7 @@ __global__ __launch_bounds__(row_block<N>()) void recv_row_grad_kernel(RecvArgs 
     const float2* src = a.in + b * plane + row;
 #pragma unroll
     for (int m = 0; m < kE; ++m) x[m] = src[t + T * m];
-    fft<N, kE, true>(x, lds, t, a.tw);
+    fft<N, kE, true>(x, lds, t, tw);
     const float2* us = a.u + b * plane + row;
 #pragma unroll
     for (int m = 0; m < kE; ++m) {
