@@ -422,6 +422,13 @@ void col_pass_kernel(ColArgs a) {
   const int k1 = strip * K + c;
   const ColLds<K> lds{smem, c};
   __shared__ float2 tw_lds[N];
+#if TURPY_CHIRP_LDS
+  __shared__ float2 h_lds[N];
+  for (int i = threadIdx.x; i < N; i += blockDim.x) h_lds[i] = a.table[i];
+  const float2* chirp = h_lds;
+#else
+  const float2* chirp = a.table;
+#endif
   const float2* tw = stage_twiddles<N>(tw_lds, a.tw);
   const float2* src = a.in + r * a.in_stride + k1;
   float2 x[kE];
@@ -431,7 +438,7 @@ void col_pass_kernel(ColArgs a) {
 #pragma unroll
   for (int m = 0; m < kE; ++m) {
     const int k0 = t + T * m;
-    float2 h = a.table[k0];
+    float2 h = chirp[k0];
     if constexpr (ANGULAR) h = c_mul(h, angular_correction(k0, k1, N, a.dz, a.k, a.df));
     x[m] = a.conj_table ? c_mulc(x[m], h) : c_mul(x[m], h);
   }
@@ -689,8 +696,7 @@ __global__ __launch_bounds__(256) void stats_kernel(StatsArgs a) {
   if (p >= np) return;
   float s1 = a.moments[p], c1 = a.moments[np + p];
   float s2 = a.moments[2 * np + p], c2 = a.moments[3 * np + p];
-  for (int64_t b = 0; b < a.batch; ++b) {
-    const float2 u = a.u[b * np + p];
+  auto add = [&](float2 u) {
     const float i = u.x * u.x + u.y * u.y;
     float y = i - c1;
     float tt = s1 + y;
@@ -700,7 +706,18 @@ __global__ __launch_bounds__(256) void stats_kernel(StatsArgs a) {
     tt = s2 + y;
     c2 = (tt - s2) - y;
     s2 = tt;
+  };
+  // eight loads in flight per thread; the sums stay in batch order
+  constexpr int U = 8;
+  int64_t b = 0;
+  for (; b + U <= a.batch; b += U) {
+    float2 u[U];
+#pragma unroll
+    for (int q = 0; q < U; ++q) u[q] = a.u[(b + q) * np + p];
+#pragma unroll
+    for (int q = 0; q < U; ++q) add(u[q]);
   }
+  for (; b < a.batch; ++b) add(a.u[b * np + p]);
   a.moments[p] = s1;
   a.moments[np + p] = c1;
   a.moments[2 * np + p] = s2;
