@@ -48,56 +48,102 @@ def parse():
     return ap.parse_args()
 
 
-def algorithmic_bytes(path, family, checkpoints=False):
-    """Minimum HBM bytes one launch of a kernel family moves (see the design notes)."""
+def step_bytes(path, leg):
+    """Minimum HBM bytes per benchmark step of each kernel family, following
+    the pass schedule of turpy_propagate / turpy_propagate_backward for a
+    shared source plane, synthesised (or stored-spectrum) screens, nonzero
+    first and last distances and no subharmonics (the headline and AR
+    workloads).  plane = one N x N complex64 field."""
     plane = path.n * path.n * 8
-    r, p = path.realizations, (path.realizations + 1) // 2
-    if family == "row_fwd":
-        return (2 * r + p) * plane + (r * plane if checkpoints else 0)
-    if family == "row_bwd":
-        # g read + write, scratch read, checkpoint read, dL/dphi write (4 B/px)
-        return (3 * r + p) * plane + r * plane // 2
-    if family == "col":
-        return 2 * r * plane
-    if family == "synth":
-        return p * plane
-    if family == "copy":
-        return 2 * r * plane
-    if family == "evolve":
-        return 2 * p * path.num_screens * plane
-    return None
+    r, p, m = path.realizations, (path.realizations + 1) // 2, path.num_screens
+    moments = 4 * 4 * 2 * path.n * path.n  # four float accumulators, read and written
+    ck = r if leg == "fwdbwd" else 0
+    spec = p if leg == "ar" else 0  # stored spectra read by the synthesis
+    out = {
+        # source row transform (1 plane in, 1 out) and the final inverse row pass
+        "row_plain": (2 + 2 * r) * plane,
+        # column pass 0 diffracts the single shared source plane in place
+        "col": (2 + 2 * r * m) * plane,
+        # the first screen pass reads that one plane for every realization
+        "row_fwd": (m * (2 * r + p + ck) - (r - 1)) * plane,
+        "synth": m * (p + spec) * plane,
+    }
+    if leg in ("fwd", "ar"):
+        out["stats"] = r * plane + moments
+    if leg == "ar":
+        out["evolve"] = 2 * p * m * plane
+    if leg == "fwdbwd":
+        # adjoint: first and last row passes (g in and out), M + 1 column passes,
+        # M screen passes reading g, scratch and checkpoint, writing g and dL/dphi
+        out["row_plain"] += 4 * r * plane
+        out["col"] += (m + 1) * 2 * r * plane
+        out["row_bwd"] = m * (3 * r + p) * plane + m * r * path.n * path.n * 4
+        out["synth"] += m * p * plane
+    if leg == "copy":
+        return {"copy": 2 * r * plane}
+    return out
 
 
-def timed_region(torch, fn, steps, warmup, binding, families):
-    for i in range(warmup):
-        fn(i)
-    torch.cuda.synchronize()
-    binding.profile(True)
-    t0 = time.perf_counter()
+def run_steps(torch, fn, first, steps):
     for i in range(steps):
-        fn(warmup + i)
+        fn(first + i)
     torch.cuda.synchronize()
+
+
+def measure(torch, fn, steps, warmup, binding, families, path, leg):
+    """Warm-up, then one untimed pass with every kernel family bracketed by HIP
+    events (the per-kernel table), then the timed region: `steps` steps with
+    only the dominant family bracketed, on the stream its kernels run on.
+    Returns (seconds per step, kernel table, dominant family)."""
+    run_steps(torch, fn, 0, warmup)
+    binding.profile_only(None)
+    binding.profile(True)
+    run_steps(torch, fn, warmup, steps)
+    table = kernel_table(binding, families, steps, path, leg)
+    binding.profile(False)
+    timed = [f for f in table if "bytes_per_launch" in table[f]]
+    dom = max(timed, key=lambda f: table[f]["total_ms"]) if timed else None
+    binding.profile_only(dom)
+    binding.profile(dom is not None)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run_steps(torch, fn, warmup + steps, steps)
     t1 = time.perf_counter()
-    per = {}
+    if dom is not None:
+        n, ms = binding.profile_read(dom)
+        d = table[dom]
+        d["timed_region_avg_us"] = 1e3 * ms / n
+        d["timed_region_launches"] = n
+    binding.profile(False)
+    binding.profile_only(None)
+    return (t1 - t0) / steps, table, dom
+
+
+def kernel_table(binding, families, steps, path, leg):
+    per_step = step_bytes(path, leg)
+    out = {}
     for f in families:
         n, ms = binding.profile_read(f)
-        if n:
-            per[f] = {"launches": n, "avg_us": 1e3 * ms / n, "total_ms": ms}
-    binding.profile(False)
-    return (t1 - t0) / steps, per
-
-
-def kernel_table(path, per, checkpoints):
-    out = {}
-    for f, d in per.items():
-        b = algorithmic_bytes(path, f, checkpoints)
-        e = dict(d)
-        if b is not None:
-            e["bytes_per_launch"] = b
-            e["GBps"] = b / (d["avg_us"] * 1e-6) / 1e9
+        if not n:
+            continue
+        e = {"launches": n, "avg_us": 1e3 * ms / n, "total_ms": ms}
+        if f in per_step:
+            e["bytes_per_launch"] = per_step[f] * steps / n
+            e["GBps"] = e["bytes_per_launch"] / (e["avg_us"] * 1e-6) / 1e9
             e["frac_hbm"] = e["GBps"] / HBM_PEAK_GBPS
         out[f] = e
     return out
+
+
+def roofline(table, dom, traffic):
+    """Roofline entry of the dominant family: algorithmic bytes per launch over
+    its average launch duration inside the timed region."""
+    d = table[dom]
+    us = d.get("timed_region_avg_us", d["avg_us"])
+    gbps = d["bytes_per_launch"] / (us * 1e-6) / 1e9
+    return {"bound": "hbm", "kernel": dom, "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "frac": gbps / HBM_PEAK_GBPS, "traffic": traffic.get(dom),
+            "bytes_per_launch": d["bytes_per_launch"], "avg_us": us}
 
 
 def plain_forward(torch, plan, path, u0, seed, t, H, phi):
@@ -137,9 +183,16 @@ def cpu_baseline(w, pairs):
     opr.propagate(u0, path, phi)
     dt = time.perf_counter() - t0
     ss = path.realizations * path.num_screens
+    cpu = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu = next(line.split(":", 1)[1].strip() for line in f if line.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
     return {"value": ss / dt, "unit": "screen-steps/s", "cores": 1, "kind": "oracle",
             "sample": f"{path.realizations} realizations x {path.num_screens} screens of the forward workload "
-                      f"at N={path.n} (synthesis + propagation), numpy float64, single thread, {dt:.1f} s"}
+                      f"at N={path.n} (synthesis + propagation), numpy float64, single thread, {dt:.1f} s "
+                      f"on {cpu} ({os.cpu_count()} logical CPUs visible)"}
 
 
 def main():
@@ -151,7 +204,7 @@ def main():
     import numpy as np
     import torch
 
-    from paper_2604_07248_amd import api, binding, workloads
+    from paper_2604_07248_amd import api, binding, prof_summary, workloads
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
@@ -168,7 +221,6 @@ def main():
     u_out = torch.empty((path.realizations, path.n, path.n), dtype=torch.complex64, device=dev)
     moments = api.Moments(path.n, path.dx)
     ss_per_step = path.realizations * path.num_screens
-    plane_px = path.n * path.n
     result = {"metric": METRIC, "unit": "screen-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
               "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c64",
               "data": "synthetic (seeded Philox screens, Gaussian source)",
@@ -182,18 +234,13 @@ def main():
         moments.add(u_out)
 
     if args.only in ("all", "fwd"):
-        sec, per = timed_region(torch, fwd, args.steps, args.warmup, binding, fams)
+        sec, ktab, dom = measure(torch, fwd, args.steps, args.warmup, binding, fams, path, "fwd")
         result["value"] = ss_per_step / sec
         result["ms_per_step"] = 1e3 * sec
-        ktab = kernel_table(path, per, False)
         result["kernels"] = ktab
-        # whole-path effective bandwidth: 32 B/px field + 8 B/px per pair of screen scratch
-        result["path_effective_GBps"] = (32 + 16 / 2) * plane_px * ss_per_step / sec / 1e9
-        dom = max((f for f in ktab if "GBps" in ktab[f]), key=lambda f: ktab[f]["total_ms"])
-        d = ktab[dom]
-        result["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": d["GBps"], "peak": HBM_PEAK_GBPS,
-                              "unit": "GB/s", "frac": d["GBps"] / HBM_PEAK_GBPS, "traffic": None,
-                              "bytes_per_launch": d["bytes_per_launch"], "avg_us": d["avg_us"]}
+        # whole-path effective bandwidth: every family's algorithmic bytes per step
+        result["path_effective_GBps"] = sum(step_bytes(path, "fwd").values()) / sec / 1e9
+        result["roofline"] = roofline(ktab, dom, prof_summary.load_traffic(os.path.join(ROOT, "profiles"), "fwd"))
 
     if args.only in ("all", "fwdbwd"):
         ck = torch.empty((path.realizations, path.num_screens, path.n, path.n), dtype=torch.complex64, device=dev)
@@ -202,9 +249,10 @@ def main():
             out, c = plan.propagate(u0, seed=w.seed, t=i, out=u_out, checkpoints=ck)
             plan.propagate_backward(out, c, seed=w.seed, t=i)
 
-        sec, per = timed_region(torch, fwdbwd, args.steps, args.warmup, binding, fams)
+        sec, ktab, dom = measure(torch, fwdbwd, args.steps, args.warmup, binding, fams, path, "fwdbwd")
         result["fwd_bwd"] = {"value": ss_per_step / sec, "unit": "screen-steps/s", "ms_per_step": 1e3 * sec,
-                             "kernels": kernel_table(path, per, True)}
+                             "kernels": ktab, "dominant": dom,
+                             "path_effective_GBps": sum(step_bytes(path, "fwdbwd").values()) / sec / 1e9}
         del ck
 
     if args.only in ("all", "ar"):
@@ -222,11 +270,12 @@ def main():
             plan3.propagate(u3, spectra=spec, out=o3)
             m3.add(o3)
 
-        sec, per = timed_region(torch, ar, args.steps, args.warmup, binding, fams)
+        sec, ktab, dom = measure(torch, ar, args.steps, args.warmup, binding, fams, p3, "ar")
         ss3 = p3.realizations * p3.num_screens
         result["ar"] = {"value": ss3 / sec, "unit": "screen-steps/s", "ms_per_step": 1e3 * sec,
                         "workload": w3.name + " (32 sequences, alpha=0.99, shift 0.5 px/step)",
-                        "seconds_for_1000_steps": 1000 * sec, "kernels": kernel_table(p3, per, False)}
+                        "seconds_for_1000_steps": 1000 * sec, "kernels": ktab, "dominant": dom,
+                        "path_effective_GBps": sum(step_bytes(p3, "ar").values()) / sec / 1e9}
         plan3.close()
         del spec
 
@@ -238,7 +287,11 @@ def main():
             u = plain_forward(torch, plan, path, u0, w.seed, i, H, phi)
             moments.add(u)
 
-        sec, _ = timed_region(torch, plain, max(2, args.steps // 5), 2, binding, [])
+        k = max(2, args.steps // 5)
+        run_steps(torch, plain, 0, 2)
+        t0 = time.perf_counter()
+        run_steps(torch, plain, 2, k)
+        sec = (time.perf_counter() - t0) / k
         # same screens, same physics: report the agreement of the two versions
         fused = plan.propagate(u0, seed=w.seed, t=0)
         ref = plain_forward(torch, plan, path, u0, w.seed, 0, H, phi)
@@ -256,9 +309,9 @@ def main():
                             realizations=path.realizations)
         planc = api.Plan(pc)
         src = torch.empty_like(u_out).copy_(u0.expand_as(u_out))
-        sec, per = timed_region(torch, lambda i: planc.propagate(src, out=u_out), args.steps, args.warmup, binding,
-                                fams)
-        result["copy"] = kernel_table(pc, per, False)
+        _, ktab, _ = measure(torch, lambda i: planc.propagate(src, out=u_out), args.steps, args.warmup, binding,
+                             fams, pc, "copy")
+        result["copy"] = ktab
         result["value"] = 0.0
 
     if args.only == "all" and not args.no_cpu_baseline:

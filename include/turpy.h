@@ -194,8 +194,13 @@ turpy_status turpy_receiver_backward(int32_t n, double dx, double aperture_diame
  * "finalize", "copy", "recv_row", "recv_col", "recv_col_grad", "recv_row_grad",
  * "recv_reduce".  turpy_profile_read waits for the recorded events and
  * returns the launch count and summed duration (ms) of one family (zero when it
- * never ran).  Host-side state, process-wide; not thread-safe. */
+ * never ran).  turpy_profile_only(family) restricts the bracketing to one
+ * family (the others launch with no events around them, so that timing one
+ * kernel perturbs the rest of a pass as little as possible); NULL or "" times
+ * every family again.  The family string is copied.  Host-side state,
+ * process-wide; not thread-safe. */
 turpy_status turpy_profile(int32_t enable);
+turpy_status turpy_profile_only(const char* family);
 turpy_status turpy_profile_read(const char* family, int64_t* launches, double* total_ms);
 
 #ifdef __cplusplus

@@ -23,7 +23,7 @@ EXPORTS = [
     "turpy_version", "turpy_last_error", "turpy_plan_create", "turpy_plan_destroy", "turpy_workspace_size",
     "turpy_screen_generate", "turpy_propagate", "turpy_evolve", "turpy_propagate_backward", "turpy_stats",
     "turpy_receiver_workspace_size", "turpy_receiver", "turpy_receiver_backward", "turpy_profile",
-    "turpy_profile_read",
+    "turpy_profile_only", "turpy_profile_read",
 ]
 
 
@@ -72,6 +72,7 @@ def lib():
         L.turpy_receiver_backward.argtypes = [c_int32, c_double, c_double, c_int64, c_void_p, c_void_p, c_void_p,
                                               c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]
         L.turpy_profile.argtypes = [c_int32]
+        L.turpy_profile_only.argtypes = [c_char_p]
         L.turpy_profile_read.argtypes = [c_char_p, POINTER(c_int64), POINTER(c_double)]
         for name in EXPORTS:
             if name not in ("turpy_version", "turpy_last_error"):
@@ -163,6 +164,11 @@ def receiver_backward(n, dx, diameter, batch, u_ptr, th1_ptr, th2_ptr, gout_ptr,
 
 def profile(enable):
     check(lib().turpy_profile(1 if enable else 0))
+
+
+def profile_only(family):
+    """Time only `family` while profiling (None: every family)."""
+    check(lib().turpy_profile_only(family.encode() if family else None))
 
 
 def profile_read(family):

@@ -54,12 +54,6 @@ turpy_status hip_fail(hipError_t e, const char* where) {
 // Column passes over realization pairs fused with the next screen's synthesis.
 constexpr bool kFusedColumns = TURPY_FUSED_COLUMNS != 0;
 
-#ifndef TURPY_SIDE_STREAM
-#define TURPY_SIDE_STREAM 0
-#endif
-// Screen synthesis overlapped with the field passes on a second stream.
-constexpr bool kSideStream = TURPY_SIDE_STREAM != 0;
-
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kLog2e = 1.4426950408889634;
 constexpr size_t kAlign = 256;
@@ -81,6 +75,7 @@ struct EventPair {
 };
 struct Profiler {
   bool on = false;
+  std::string only;  // time only this family when non-empty
   std::map<std::string, std::vector<EventPair>> live;
   std::vector<EventPair> pool;
   EventPair take() {
@@ -105,7 +100,7 @@ Profiler g_prof;
 // Launch `fn` (returning hipError_t) bracketed by events when profiling is on.
 template <class Fn>
 hipError_t timed(const char* family, hipStream_t st, Fn&& fn) {
-  if (!g_prof.on) return fn();
+  if (!g_prof.on || (!g_prof.only.empty() && g_prof.only != family)) return fn();
   EventPair e = g_prof.take();
   (void)hipEventRecord(e.start, st);
   const hipError_t r = fn();
@@ -135,14 +130,9 @@ struct turpy_plan {
   float2* d_sh_phasor = nullptr; // [3][N]
   float* d_sh_amp = nullptr;     // [M][3][2]
   float* d_amp_rad = nullptr;    // [M]
-  // screen synthesis runs on a second stream of default priority, ordered by
-  // events against the caller's stream (double-buffered scratch planes)
-  hipStream_t side = nullptr;
-  std::vector<hipEvent_t> events;  // [0] start, [1..M] synthesis done, [M+1..2M] row pass done
 
   size_t plane_bytes() const { return static_cast<size_t>(n) * n * sizeof(float2); }
-  size_t scratch_bytes() const { return align_up(static_cast<size_t>(P) * plane_bytes()); }
-  size_t off_sh() const { return (kSideStream ? 2 : 1) * scratch_bytes(); }
+  size_t off_sh() const { return align_up(static_cast<size_t>(P) * plane_bytes()); }
   size_t off_src() const {
     return off_sh() + align_up(sh_levels > 0 ? static_cast<size_t>(P) * (M > 0 ? M : 1) * 32 * sizeof(float2) : 0);
   }
@@ -289,17 +279,9 @@ turpy_status turpy_plan_create(turpy_plan** out, const turpy_path* p, uint32_t f
   std::vector<float> amp_rad = pl->amp_rad;
   if (amp_rad.empty()) amp_rad.push_back(0.0f);
   if (e == hipSuccess) e = upload(&pl->d_amp_rad, amp_rad.data(), amp_rad.size() * sizeof(float));
-  if (e == hipSuccess && kSideStream) {
-    e = hipStreamCreateWithFlags(&pl->side, hipStreamNonBlocking);
-    for (int i = 0; e == hipSuccess && i < 2 * M + 1; ++i) {
-      hipEvent_t ev = nullptr;
-      e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
-      if (e == hipSuccess) pl->events.push_back(ev);
-    }
-  }
   if (e != hipSuccess) {
     turpy_plan_destroy(pl);
-    return hip_fail(e, "plan_create: tables, stream and events");
+    return hip_fail(e, "plan_create: table upload");
   }
   *out = pl;
   return TURPY_OK;
@@ -313,8 +295,6 @@ turpy_status turpy_plan_destroy(turpy_plan* pl) {
   (void)hipFree(pl->d_sh_phasor);
   (void)hipFree(pl->d_sh_amp);
   (void)hipFree(pl->d_amp_rad);
-  for (hipEvent_t ev : pl->events) (void)hipEventDestroy(ev);
-  if (pl->side) (void)hipStreamDestroy(pl->side);
   delete pl;
   return TURPY_OK;
 }
@@ -335,19 +315,16 @@ turpy_status turpy_workspace_size(const turpy_plan* pl, int32_t op, size_t* byte
 namespace {
 
 struct Ws {
-  float2* scratch;   // scratch plane 0 (the only one without the side stream)
-  float2* scratch1;  // scratch plane 1 (double buffering with the side stream)
+  float2* scratch;
   float2* sh;
   float2* src;
   float2* gbuf;
-  float2* plane_for(int screen) const { return (kSideStream && (screen & 1)) ? scratch1 : scratch; }
 };
 
 Ws carve(const turpy_plan* pl, void* ws) {
   char* b = static_cast<char*>(ws);
-  return Ws{reinterpret_cast<float2*>(b), reinterpret_cast<float2*>(b + pl->scratch_bytes()),
-            reinterpret_cast<float2*>(b + pl->off_sh()), reinterpret_cast<float2*>(b + pl->off_src()),
-            reinterpret_cast<float2*>(b + pl->off_gbuf())};
+  return Ws{reinterpret_cast<float2*>(b), reinterpret_cast<float2*>(b + pl->off_sh()),
+            reinterpret_cast<float2*>(b + pl->off_src()), reinterpret_cast<float2*>(b + pl->off_gbuf())};
 }
 
 void key_of(uint64_t seed, uint32_t* k0, uint32_t* k1) {
@@ -395,7 +372,7 @@ ColArgs col_args(const turpy_plan* pl, int step, const float2* in, int64_t in_st
 SynthArgs synth_args(const turpy_plan* pl, uint64_t seed, uint32_t t, int s, const float2* spectra, const Ws& w) {
   SynthArgs a{};
   a.tw = pl->d_tw;
-  a.scratch = w.plane_for(s);
+  a.scratch = w.scratch;
   a.P = pl->P;
   key_of(seed, &a.key0, &a.key1);
   a.t = t;
@@ -460,7 +437,7 @@ turpy_status screen_fields(const turpy_plan* pl, int32_t src, const void* screen
     a->screens = static_cast<const float*>(screens_or_spectra);
   } else {
     a->screen_mode = ROW_SCRATCH;
-    a->scratch = w.plane_for(s);
+    a->scratch = w.scratch;
     a->sh_levels = src == TURPY_SCREENS_SYNTH ? pl->sh_levels : 0;
     a->sh = w.sh;
   }
@@ -595,12 +572,22 @@ turpy_status turpy_propagate(turpy_plan* pl, uint64_t seed, int64_t t, const voi
     a.R = rows_r;
     TURPY_HIP(timed(row_family(a), st, [&] { return launch_row(n, a, (rows_r + 1) / 2, st); }),
               "propagate: source row transform");
-    const int syn = synth && M > 0 ? 0 : -1;
-    TURPY_HIP(enqueue_col(pl, 0, dst, u_in_stride == 0 ? 0 : plane, uout, false, syn, seed, tt, spectra, w, st),
-              "propagate: column pass 0");
-    scratch_ready = syn >= 0;
-    cur = uout;
-    cur_stride = plane;
+    if (u_in_stride == 0) {
+      // Shared source: the diffraction before the first screen is the same for
+      // every realization, so it runs once, in place on the source plane, and
+      // the first screen pass reads that plane for all of them.
+      const ColArgs c = col_args(pl, 0, w.src, 0, w.src, 1, false);
+      TURPY_HIP(timed("col", st, [&] { return launch_col(n, c, st); }), "propagate: column pass 0");
+      cur = w.src;
+      cur_stride = 0;
+    } else {
+      const int syn = synth && M > 0 ? 0 : -1;
+      TURPY_HIP(enqueue_col(pl, 0, dst, plane, uout, false, syn, seed, tt, spectra, w, st),
+                "propagate: column pass 0");
+      scratch_ready = syn >= 0;
+      cur = uout;
+      cur_stride = plane;
+    }
     spectral = true;
   }
   for (int s = 0; s < M; ++s) {
@@ -631,8 +618,8 @@ turpy_status turpy_propagate(turpy_plan* pl, uint64_t seed, int64_t t, const voi
   }
   if (spectral) {
     RowArgs a = base_row(pl);
-    a.in = uout;
-    a.in_stride = plane;
+    a.in = cur;  // the shared source plane when there are no screens
+    a.in_stride = cur_stride;
     a.out = uout;
     a.in_spectral = 1;
     a.scale = inv_n;
@@ -787,6 +774,11 @@ turpy_status turpy_stats(int32_t n, double dx, int64_t batch, const void* u, flo
 turpy_status turpy_profile(int32_t enable) {
   g_prof.recycle();
   g_prof.on = enable != 0;
+  return TURPY_OK;
+}
+
+turpy_status turpy_profile_only(const char* family) {
+  g_prof.only = family ? family : "";
   return TURPY_OK;
 }
 

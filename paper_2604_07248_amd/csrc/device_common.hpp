@@ -55,7 +55,9 @@ __device__ __forceinline__ void sincos_rev(float x, float* s, float* c) {
 __device__ __forceinline__ float2 box_muller(uint32_t va, uint32_t vb) {
   const float ua = u01(va);
   const float ub = u01(vb);
-  const float rho = sqrtf(-2.0f * 0.69314718055994531f * __builtin_amdgcn_logf(ua));
+  // hardware square root (about 1 ulp): the argument is at least about 2^-23,
+  // far from the denormal range that the correctly rounded expansion guards
+  const float rho = __builtin_amdgcn_sqrtf(-2.0f * 0.69314718055994531f * __builtin_amdgcn_logf(ua));
   float s, c;
   sincos_rev(ub, &s, &c);
   return make_float2(rho * c, rho * s);
