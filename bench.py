@@ -44,7 +44,7 @@ def parse():
     ap.add_argument("--only", choices=["all", "fwd", "fwdbwd", "ar", "plain", "copy"], default="all",
                     help="run one leg (profiling runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-pairs", type=int, default=2, help="realization pairs in the oracle sample")
+    ap.add_argument("--cpu-pairs", type=int, default=16, help="realization pairs in the oracle sample (about 20 s of CPU work)")
     return ap.parse_args()
 
 
