@@ -36,8 +36,24 @@ def hufnagel_valley(z, A=1.7e-14, V=21.0):
             + 2.7e-16 * np.exp(-z / 1500.0) + A * np.exp(-z / 100.0))
 
 
-def _quad(f, a, b):
-    return integrate.quad(f, a, b, epsabs=0.0, epsrel=1e-12, limit=400)[0]
+def table_profile(z, values):
+    """Cn2 piecewise linear through (z[i], values[i]), constant beyond the ends."""
+    z = np.asarray(z, dtype=np.float64)
+    v = np.asarray(values, dtype=np.float64)
+
+    def cn2(h):
+        return np.interp(h, z, v)
+    cn2.nodes = z
+    return cn2
+
+
+def _quad(f, a, b, cn2=None):
+    nodes = getattr(cn2, "nodes", None)
+    pts = None
+    if nodes is not None:
+        inside = [float(x) for x in nodes if a < x < b]
+        pts = inside or None
+    return integrate.quad(f, a, b, epsabs=0.0, epsrel=1e-12, limit=400, points=pts)[0]
 
 
 def wavenumber(wavelength, n0=1.0):
@@ -48,12 +64,12 @@ def rytov_interval(cn2, a, b, wavelength, n0=1.0):
     """Eq. S19 over [a, b]."""
     d = b - a
     k = wavenumber(wavelength, n0)
-    w = _quad(lambda z: float(cn2(z)) * (1.0 - (z - a) / d) ** (5.0 / 3.0), a, b)
+    w = _quad(lambda z: float(cn2(z)) * (1.0 - (z - a) / d) ** (5.0 / 3.0), a, b, cn2)
     return 3.27 * k ** (7.0 / 6.0) * d ** (5.0 / 6.0) * w
 
 
 def integrated_cn2(cn2, a, b):
-    return _quad(lambda z: float(cn2(z)), a, b)
+    return _quad(lambda z: float(cn2(z)), a, b, cn2)
 
 
 def fried_interval(cn2, a, b, wavelength, n0=1.0):
@@ -66,7 +82,7 @@ def fried_weak_limit(cn2, a, b, wavelength, n0=1.0):
     """Eq. S20: the interval's r0 at which its Rytov variance (Eq. S19) is 1."""
     d = b - a
     k = wavenumber(wavelength, n0)
-    w = _quad(lambda z: float(cn2(z)) * (1.0 - (z - a) / d) ** (5.0 / 3.0), a, b)
+    w = _quad(lambda z: float(cn2(z)) * (1.0 - (z - a) / d) ** (5.0 / 3.0), a, b, cn2)
     ratio = w / integrated_cn2(cn2, a, b)
     return (0.129 * k ** (5.0 / 6.0) / d ** (5.0 / 6.0) / ratio) ** (-3.0 / 5.0)
 
@@ -120,13 +136,24 @@ def place_screens(cn2, length, wavelength, n, dx, rytov_limit, initial=1, n0=1.0
         else:
             merged.append(b)
     bounds = merged
-    # (4) linear fit on the cumulative strength, then split again
+    # (4) linear fit on the cumulative strength: boundary j goes where the
+    # cumulative s2, linear within each interval, reaches j/M of the total (in
+    # the first interval whose end reaches it); then split again
     m = len(bounds) - 1
     if m > 1:
-        cum = np.concatenate([[0.0], np.cumsum([s2(bounds[i], bounds[i + 1]) for i in range(m)])])
-        targets = cum[-1] * np.arange(1, m) / m
-        interior = np.interp(targets, cum, np.asarray(bounds))
-        bounds = [0.0] + list(interior) + [float(length)]
+        cum = [0.0]
+        for i in range(m):
+            cum.append(cum[-1] + s2(bounds[i], bounds[i + 1]))
+        new = [0.0]
+        for j in range(1, m):
+            target = cum[m] * j / m
+            i = 0
+            while i + 1 < m and cum[i + 1] < target:
+                i += 1
+            span = cum[i + 1] - cum[i]
+            frac = (target - cum[i]) / span if span > 0 else 0.0
+            new.append(bounds[i] + frac * (bounds[i + 1] - bounds[i]))
+        bounds = new + [float(length)]
         bounds = _split(bounds, over)
     # (5) Eq. 7
     dzmax = aliasing_step(n, dx, wavelength, n0)

@@ -116,3 +116,18 @@ def test_linear_fit_evens_out_strength():
 def test_rejects_bad_limit():
     with pytest.raises(ValueError):
         opl.place_screens(uniform(1e-14), 100.0, LAM, 256, 1e-3, 0.0)
+
+
+def test_table_profile_ramp_closed_form():
+    """Cn2 linear in z through two table points: int Cn2 = c0 D + c1 (b^2 - a^2)/2
+    and, since int_0^1 t (1-t)^(5/3) dt = B(2, 8/3) = 9/88, Eq. S19's weighted
+    integral is (c0 + c1 a) D 3/8 + c1 D^2 9/88."""
+    c0, c1, a, b = 2e-15, 3e-18, 100.0, 2600.0
+    prof = opl.table_profile([0.0, 5000.0], [c0, c0 + c1 * 5000.0])
+    d = b - a
+    assert opl.integrated_cn2(prof, a, b) == pytest.approx(c0 * d + c1 * (b * b - a * a) / 2, rel=1e-12)
+    k = 2 * math.pi / LAM
+    w = (c0 + c1 * a) * d * 0.375 + c1 * d * d * 9 / 88
+    assert opl.rytov_interval(prof, a, b, LAM) == pytest.approx(3.27 * k ** (7 / 6) * d ** (5 / 6) * w, rel=1e-10)
+    # beyond the table the profile is constant
+    assert float(prof(6000.0)) == pytest.approx(c0 + c1 * 5000.0)
