@@ -43,7 +43,8 @@ typedef enum {
   TURPY_E_UNSUPPORTED = 2,  /* well-formed but outside what is implemented   */
   TURPY_E_ALIASING = 3,     /* a step exceeds the transfer-function sampling limit (Sec. 2.4, Eq. 7) */
   TURPY_E_WORKSPACE = 4,    /* workspace NULL or smaller than turpy_workspace_size() */
-  TURPY_E_HIP = 5           /* a HIP runtime call failed (message has the HIP error) */
+  TURPY_E_HIP = 5,          /* a HIP runtime call failed (message has the HIP error) */
+  TURPY_E_CAPACITY = 6      /* a host output array is smaller than the result */
 } turpy_status;
 
 typedef enum { TURPY_TF_FRESNEL = 0, TURPY_TF_ANGULAR_SPECTRUM = 1 } turpy_tf_kind;
@@ -186,6 +187,53 @@ turpy_status turpy_receiver_backward(int32_t n, double dx, double aperture_diame
                                      const void* u, const float* theta1, const float* theta2,
                                      const void* grad_out, void* grad_u, float* grad_theta1,
                                      float* grad_theta2, void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Screen placement (Sec. 2.4; App. C Eq. S18-S21).  Host arithmetic only: no
+ * device memory, no stream and no GPU are involved.
+ * ------------------------------------------------------------------------- */
+typedef enum {
+  TURPY_CN2_UNIFORM = 0,         /* Cn2(z) = cn2                                                     */
+  TURPY_CN2_HUFNAGEL_VALLEY = 1, /* Eq. S21 with ground constant A [m^-2/3] and wind speed V [m/s];
+                                    z is the height above the ground (vertical path from the ground) */
+  TURPY_CN2_TABLE = 2            /* piecewise linear through (z[i], values[i]), count >= 1, z strictly
+                                    increasing; constant beyond the first and the last point         */
+} turpy_cn2_kind;
+
+typedef struct turpy_cn2_profile {
+  int32_t kind;                  /* turpy_cn2_kind                                                   */
+  double cn2;                    /* UNIFORM: Cn2 >= 0                                                */
+  double A, V;                   /* HUFNAGEL_VALLEY: A >= 0, V >= 0                                  */
+  const double* z;               /* TABLE: HOST [count] positions [m]                                */
+  const double* values;          /* TABLE: HOST [count] Cn2 >= 0                                     */
+  int64_t count;                 /* TABLE: number of points                                          */
+} turpy_cn2_profile;
+
+/* Screen placement along [0, length] for a grid of n points spaced dx
+ * (Sec. 2.4).  In order:
+ *  1. `initial` >= 1 equal intervals;
+ *  2. every interval whose Rytov variance (Eq. S19 over the interval, with
+ *     k = 2 pi n0 / wavelength) exceeds rytov_limit is halved, until none does;
+ *  3. neighbours are merged, left to right, while the merged interval stays
+ *     within the limit;
+ *  4. the interior boundaries move, keeping their number, to equal shares of
+ *     the cumulative Rytov variance interpolated linearly between the current
+ *     boundaries; step 2 is repeated;
+ *  5. every interval longer than the Eq. 7 step (N dx / 2) sqrt(n0^2 k0^2 -
+ *     kappa0^2) / kappa0, kappa0 = 2 pi / dx, k0 = 2 pi / wavelength, is halved
+ *     until none is.
+ * One screen sits at the middle of each interval.  Outputs, HOST arrays sized
+ * by max_screens: dz [M+1] in the layout of turpy_path.dz, cn2dz [M] the
+ * integral of Cn2 over each interval, rytov [M] Eq. S19 of each interval (may
+ * be NULL); *num_screens = M.  Integrals use composite Gauss-Legendre
+ * quadrature (relative error near 1e-13 for the profiles above).
+ * Errors: TURPY_E_INVALID for a malformed profile or argument, for dx <=
+ * wavelength / n0 (Eq. 7 has no real step) or when more than 65536 intervals
+ * would be needed; TURPY_E_CAPACITY when M > max_screens (*num_screens then
+ * holds M and the arrays are untouched). */
+turpy_status turpy_place_screens(const turpy_cn2_profile* profile, double length, double wavelength, double n0,
+                                 int32_t n, double dx, double rytov_limit, int32_t initial, int32_t max_screens,
+                                 int32_t* num_screens, double* dz, double* cn2dz, double* rytov);
 
 /* Per-kernel timing for benchmarking.  turpy_profile(1) clears the record and
  * starts bracketing every kernel the library enqueues with a pair of HIP events

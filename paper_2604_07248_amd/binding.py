@@ -12,7 +12,8 @@ from ctypes import POINTER, c_char_p, c_double, c_float, c_int32, c_int64, c_siz
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libturpy.so")
 
-OK, E_INVALID, E_UNSUPPORTED, E_ALIASING, E_WORKSPACE, E_HIP = range(6)
+OK, E_INVALID, E_UNSUPPORTED, E_ALIASING, E_WORKSPACE, E_HIP, E_CAPACITY = range(7)
+CN2_UNIFORM, CN2_HUFNAGEL_VALLEY, CN2_TABLE = 0, 1, 2
 TF_FRESNEL, TF_ANGULAR_SPECTRUM = 0, 1
 SCREENS_SYNTH, SCREENS_MATERIALIZED, SCREENS_SPECTRA = 0, 1, 2
 ALLOW_ALIASING = 1
@@ -23,7 +24,7 @@ EXPORTS = [
     "turpy_version", "turpy_last_error", "turpy_plan_create", "turpy_plan_destroy", "turpy_workspace_size",
     "turpy_screen_generate", "turpy_propagate", "turpy_evolve", "turpy_propagate_backward", "turpy_stats",
     "turpy_receiver_workspace_size", "turpy_receiver", "turpy_receiver_backward", "turpy_profile",
-    "turpy_profile_only", "turpy_profile_read",
+    "turpy_profile_only", "turpy_profile_read", "turpy_place_screens",
 ]
 
 
@@ -39,6 +40,13 @@ class CPath(ctypes.Structure):
         ("dz", POINTER(c_double)), ("cn2dz", POINTER(c_double)), ("l0", c_double), ("L0", c_double),
         ("sh_levels", c_int32), ("tf_kind", c_int32), ("inner_scale_conv", c_int32), ("realizations", c_int64),
         ("psd_alpha", c_double),
+    ]
+
+
+class CCn2Profile(ctypes.Structure):
+    _fields_ = [
+        ("kind", c_int32), ("cn2", c_double), ("A", c_double), ("V", c_double),
+        ("z", POINTER(c_double)), ("values", POINTER(c_double)), ("count", c_int64),
     ]
 
 
@@ -74,6 +82,9 @@ def lib():
         L.turpy_profile.argtypes = [c_int32]
         L.turpy_profile_only.argtypes = [c_char_p]
         L.turpy_profile_read.argtypes = [c_char_p, POINTER(c_int64), POINTER(c_double)]
+        L.turpy_place_screens.argtypes = [POINTER(CCn2Profile), c_double, c_double, c_double, c_int32, c_double,
+                                          c_double, c_int32, c_int32, POINTER(c_int32), POINTER(c_double),
+                                          POINTER(c_double), POINTER(c_double)]
         for name in EXPORTS:
             if name not in ("turpy_version", "turpy_last_error"):
                 getattr(L, name).restype = c_int32
@@ -175,6 +186,37 @@ def profile_read(family):
     n, ms = c_int64(), c_double()
     check(lib().turpy_profile_read(family.encode(), ctypes.byref(n), ctypes.byref(ms)))
     return n.value, ms.value
+
+
+def make_cn2_profile(kind, cn2=0.0, A=0.0, V=0.0, z=None, values=None):
+    """ctypes profile descriptor (the table arrays stay referenced by the result)."""
+    zt = vt = None
+    count = 0
+    if z is not None:
+        count = len(z)
+        zt = (c_double * count)(*z)
+        vt = (c_double * count)(*values)
+    prof = CCn2Profile(kind=kind, cn2=cn2, A=A, V=V, z=ctypes.cast(zt, POINTER(c_double)) if zt else None,
+                       values=ctypes.cast(vt, POINTER(c_double)) if vt else None, count=count)
+    prof._keep = (zt, vt)
+    return prof
+
+
+def place_screens(profile, length, wavelength, n0, n, dx, rytov_limit, initial, capacity=256):
+    """Returns (dz [M+1], cn2dz [M], rytov [M]) as Python lists; retries once
+    with the reported count when `capacity` is too small."""
+    m = c_int32()
+    for _ in range(2):
+        cap = max(int(capacity), 1)
+        dz, cn2, ry = (c_double * (cap + 1))(), (c_double * cap)(), (c_double * cap)()
+        st = lib().turpy_place_screens(ctypes.byref(profile), length, wavelength, n0, n, dx, rytov_limit, initial,
+                                       cap, ctypes.byref(m), dz, cn2, ry)
+        if st != E_CAPACITY:
+            break
+        capacity = m.value
+    check(st)
+    k = m.value
+    return list(dz[:k + 1]), list(cn2[:k]), list(ry[:k])
 
 
 __all__ = [n for n in dir() if not n.startswith("_")]

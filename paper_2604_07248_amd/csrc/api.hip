@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "kernels.hpp"
+#include "report.hpp"
 #include "turpy.h"
 
 using namespace turpy;
@@ -31,6 +32,20 @@ turpy_status fail(turpy_status st, const char* fmt, ...) {
   g_last_error = buf;
   return st;
 }
+
+}  // namespace
+
+turpy_status turpy::report(turpy_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+namespace {
 
 turpy_status hip_fail(hipError_t e, const char* where) {
   return fail(TURPY_E_HIP, "%s: %s", where, hipGetErrorString(e));
