@@ -53,12 +53,25 @@ class CCn2Profile(ctypes.Structure):
 _LIB = None
 
 
+def _init_torch_gpu():
+    """PyTorch ships its own HIP runtime beside the system one the library
+    links; the library's runtime finds the device only when PyTorch's has
+    initialised first.  Harmless without a GPU or without PyTorch."""
+    try:
+        import torch
+    except ImportError:
+        return
+    if torch.cuda.is_available():
+        torch.cuda.init()
+
+
 def lib():
     """Load libturpy.so once; raises if it is missing or cannot be loaded."""
     global _LIB
     if _LIB is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2604_07248_amd.build`")
+        _init_torch_gpu()
         L = ctypes.CDLL(LIB_PATH)
         L.turpy_version.restype = c_char_p
         L.turpy_last_error.restype = c_char_p

@@ -1,0 +1,160 @@
+"""The paper's validation sweeps on vertical Hufnagel-Valley paths with placed
+screens (Sec. 3.2 broadening, Sec. 3.3 scintillation; App. C Eq. S19-S27).
+
+    python -m paper_2604_07248_amd.sweeps broadening [--trials 4000]
+    python -m paper_2604_07248_amd.sweeps scintillation [--trials 4000]
+
+Each point: Eq. S21 with ground constant A (V = 21 m/s), screens placed by
+turpy_place_screens (Rytov limit per interval 0.1 for the beams, 0.01 for the
+20 km plane-wave path, whose weak upper air otherwise gets 10 km intervals;
+Eq. 7 for the grid),
+`trials` independent realizations propagated on the GPU in batches, moments
+accumulated by turpy_stats.  Printed: one JSON object per point, then a
+markdown table.
+
+Closed forms, evaluated on the same profile:
+  * broadening: W_LT = W sqrt(1 + T), T = 1.33 sigma^2 Lambda^(5/6) (Eq. S24),
+    sigma^2 from Eq. S19 over the path (its (1 - z/L)^(5/3) weighting is that
+    of a beam leaving the ground), Lambda = 2 L / (k W^2); also the strong-
+    regime W (1 + T)^(3/5).
+  * scintillation: the plane-wave Rytov variance 2.25 k^(7/6) int Cn2 (L - z)^(5/6)
+    dz, the weak law SI = sigma^2 (Eq. S26) and the all-regime form (Eq. S27).
+Grids: N = 1024.  Broadening: side = 6 x the weak-regime W_LT estimate (at
+least 8 W0).  Scintillation: dx = min(r0 / 2, sqrt(lambda L) / 8) (the path's
+r0 and the Fresnel scale resolved), flat-top plane wave (zero at the grid
+edge) and the SI averaged over the central half.
+"""
+
+import argparse
+import json
+import math
+import sys
+
+import numpy as np
+
+HV_V = 21.0
+
+
+def hv(z, A):
+    """Eq. S21."""
+    return (0.00594 * (HV_V / 27.0) ** 2 * (1e-5 * z) ** 10 * math.exp(-z / 1000.0)
+            + 2.7e-16 * math.exp(-z / 1500.0) + A * math.exp(-z / 100.0))
+
+
+def _integral(f, a, b, panels=4000):
+    """Composite Simpson rule (the profile is smooth; panels resolve its 100 m layer)."""
+    h = (b - a) / panels
+    s = f(a) + f(b)
+    for i in range(1, panels):
+        s += (4 if i % 2 else 2) * f(a + i * h)
+    return s * h / 3.0
+
+
+def rytov_s19(A, L, wavelength):
+    k = 2 * math.pi / wavelength
+    return 3.27 * k ** (7 / 6) * L ** (5 / 6) * _integral(lambda z: hv(z, A) * (1 - z / L) ** (5 / 3), 0.0, L)
+
+
+def rytov_plane(A, L, wavelength):
+    k = 2 * math.pi / wavelength
+    return 2.25 * k ** (7 / 6) * _integral(lambda z: hv(z, A) * (L - z) ** (5 / 6), 0.0, L)
+
+
+def fried_path(A, L, wavelength):
+    k = 2 * math.pi / wavelength
+    return (0.423 * k * k * _integral(lambda z: hv(z, A), 0.0, L)) ** (-3 / 5)
+
+
+def si_all_regimes(s2):
+    """Eq. S27 read with the 7/6 and 5/6 powers."""
+    s = math.sqrt(s2)
+    return math.exp(0.49 * s2 / (1 + 1.11 * s ** 2.4) ** (7 / 6) + 0.51 * s2 / (1 + 0.69 * s ** 2.4) ** (5 / 6)) - 1
+
+
+def _run(path, source, seed, trials, batch, w0=0.0):
+    import torch
+
+    from . import api
+    from .workloads import Workload
+    p = path.with_(realizations=batch)
+    plan = api.Plan(p)
+    w = Workload("sweep", p, seed=seed, source=source, w0=w0)
+    u0 = torch.from_numpy(w.source_field().astype(np.complex64)).cuda()
+    mom = api.Moments(p.n, p.dx)
+    out = torch.empty((batch, p.n, p.n), dtype=torch.complex64, device="cuda")
+    for t in range((trials + batch - 1) // batch):
+        plan.propagate(u0, seed=seed, t=t, out=out)
+        mom.add(out)
+    _, s = mom.finalize()
+    plan.close()
+    return s
+
+
+def broadening(trials, batch, n=1024, wavelength=1.064e-6, theta0=5e-5):
+    from . import placement
+    w0 = wavelength / (math.pi * theta0)
+    k = 2 * math.pi / wavelength
+    rows = []
+    for A in (1e-13, 1e-12, 1e-11):
+        for L in (10.0, 100.0, 500.0, 1000.0, 2000.0, 5000.0):
+            zr = math.pi * w0 * w0 / wavelength
+            w_vac = w0 * math.sqrt(1 + (L / zr) ** 2)
+            s2 = rytov_s19(A, L, wavelength)
+            lam = 2 * L / (k * w_vac * w_vac)
+            t = 1.33 * s2 * lam ** (5 / 6)
+            side = max(6 * w_vac * math.sqrt(1 + t), 8 * w0)
+            dx = side / n
+            path = placement.placed_path(placement.hufnagel_valley(A, HV_V), L, wavelength, n, dx, 0.1,
+                                         l0=0.005, L0=20.0, sh_levels=3, realizations=batch)
+            s = _run(path, "gaussian", 40, trials, batch, w0)
+            row = {"A": A, "L": L, "screens": path.num_screens, "dx_mm": 1e3 * dx, "sigma2_S19": s2,
+                   "r0_over_dx": fried_path(A, L, wavelength) / dx,
+                   "W_vac_cm": 100 * w_vac, "W_sim_cm": 100 * s["w_fit"], "W_2nd_cm": 100 * s["w_2nd"],
+                   "W_S24_cm": 100 * w_vac * math.sqrt(1 + t), "W_strong_cm": 100 * w_vac * (1 + t) ** 0.6}
+            rows.append(row)
+            print(json.dumps(row), flush=True)
+    print("\n| A | L [m] | screens | r0/dx | sigma^2 (S19) | W vac [cm] | W sim (1/e^2 fit) [cm] | W S24 [cm] | "
+          "W (1+T)^(3/5) [cm] |")
+    print("|---|---:|---:|---:|---:|---:|---:|---:|---:|")
+    for r in rows:
+        print(f"| {r['A']:.0e} | {r['L']:.0f} | {r['screens']} | {r['r0_over_dx']:.1f} | {r['sigma2_S19']:.3g} | "
+              f"{r['W_vac_cm']:.3f} | {r['W_sim_cm']:.3f} | {r['W_S24_cm']:.3f} | {r['W_strong_cm']:.3f} |")
+
+
+def scintillation(trials, batch, n=1024, wavelength=1.064e-6, length=20000.0):
+    from . import placement
+    rows = []
+    for e in (-17.5, -17.0, -16.5, -16.0, -15.5, -15.0, -14.5, -14.0, -13.5):
+        A = 10.0 ** e
+        r0 = fried_path(A, length, wavelength)
+        dx = min(0.5 * r0, math.sqrt(wavelength * length) / 8)  # resolve r0 and the Fresnel scale
+        path = placement.placed_path(placement.hufnagel_valley(A, HV_V), length, wavelength, n, dx, 0.01,
+                                     l0=0.005, L0=20.0, sh_levels=3, realizations=batch)
+        s = _run(path, "flat_top", 50, trials, batch)
+        s2 = rytov_plane(A, length, wavelength)
+        row = {"A": A, "screens": path.num_screens, "r0_cm": 100 * r0, "dx_mm": 1e3 * dx, "sigma2_plane": s2,
+               "sigma2_S19": rytov_s19(A, length, wavelength), "SI_sim": s["si_plane"],
+               "SI_weak": s2, "SI_all_regime": si_all_regimes(s2)}
+        rows.append(row)
+        print(json.dumps(row), flush=True)
+    print("\n| A | screens | r0 [cm] | sigma^2 plane wave | sigma^2 (S19) | SI sim | SI weak (S26) | SI all-regime (S27) |")
+    print("|---|---:|---:|---:|---:|---:|---:|---:|")
+    for r in rows:
+        print(f"| 1e{math.log10(r['A']):.1f} | {r['screens']} | {r['r0_cm']:.2f} | {r['sigma2_plane']:.3g} | "
+              f"{r['sigma2_S19']:.3g} | {r['SI_sim']:.3f} | {r['SI_weak']:.3f} | {r['SI_all_regime']:.3f} |")
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("sweep", choices=["broadening", "scintillation"])
+    ap.add_argument("--trials", type=int, default=4000)
+    ap.add_argument("--batch", type=int, default=200)
+    a = ap.parse_args(argv)
+    if a.sweep == "broadening":
+        broadening(a.trials, a.batch)
+    else:
+        scintillation(a.trials, a.batch)
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -261,3 +261,26 @@ def test_headline_full_size_sampled(api):
     # energy is conserved by every realization (unitary steps)
     e0 = np.sum(np.abs(u0.astype(np.complex128)) ** 2)
     assert np.max(np.abs(np.sum(np.abs(out.astype(np.complex128)) ** 2, axis=(1, 2)) / e0 - 1)) < 1e-4
+
+
+def test_library_loaded_by_host_call_before_gpu_work():
+    """A host-only call (screen placement) may load the library before any GPU
+    work; plans created afterwards must still find the device.  Run in a fresh
+    process so that nothing else has initialised the GPU first."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = (
+        "from paper_2604_07248_amd import placement\n"
+        "p = placement.placed_path(placement.hufnagel_valley(), 1000.0, 1.55e-6, 128, 4e-3, 0.1, realizations=2)\n"
+        "import torch\n"
+        "from paper_2604_07248_amd import api\n"
+        "u0 = torch.ones((128, 128), dtype=torch.complex64, device='cuda')\n"
+        "out = api.Plan(p).propagate(u0, seed=1)\n"
+        "torch.cuda.synchronize()\n"
+        "print('ok', p.num_screens, float(out.abs().square().sum()))\n")
+    say("[order] placement before GPU work, fresh process")
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=240)
+    say(r.stdout.strip(), r.stderr.strip()[-500:])
+    assert r.returncode == 0 and r.stdout.startswith("ok")

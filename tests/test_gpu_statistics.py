@@ -103,3 +103,59 @@ def test_moderate_turbulence_follows_weak_law(api):
     ar = theory.si_all_regimes(s2)
     say(f"[stats] Cn2=1e-14 plane wave: SI {s['si_plane']:.4f}; weak {s2:.4f}; all-regime {ar:.4f}")
     assert abs(s["si_plane"] / s2 - 1) < 0.1
+
+
+def _placed_hv_workload(source, seed, realizations=512):
+    """Standard HV 5/7 profile (Eq. S21) on a 1.5 km vertical path from the
+    ground at 1550 nm, screens placed by turpy_place_screens (Sec. 2.4,
+    Rytov limit 0.005 per interval, Eq. 7 at N = 512, dx = 2 mm): six screens;
+    Kolmogorov limits l0 = 1 mm, L0 = 100 m; three subharmonic levels."""
+    from paper_2604_07248_amd import placement
+    p = placement.placed_path(placement.hufnagel_valley(1.7e-14, 21.0), 1500.0, 1.55e-6, 512, 2e-3, 0.005,
+                              l0=0.001, L0=100.0, sh_levels=3, realizations=realizations)
+    return workloads.Workload(f"hv57_1500m_{source}", p, seed=seed, source=source, w0=0.03)
+
+
+def _hv_integral(weight, length, wavelength):
+    from scipy import integrate
+    from oracle import planner as opl
+    return integrate.quad(lambda z: float(opl.hufnagel_valley(z)) * weight(z), 0.0, length, limit=400,
+                          points=[100.0, 1000.0])[0]
+
+
+def test_placed_hufnagel_valley_scintillation(api):
+    """Plane wave through the placed screens: SI equals the first-order sum over
+    the discrete screens within its standard error, and the continuous
+    plane-wave Rytov variance 2.25 k^(7/6) int Cn2 (L - z)^(5/6) dz within 3 %."""
+    w = _placed_hv_workload("flat_top", seed=31)
+    p = w.path
+    _, s, groups = run_ensemble(api, w, 32768)
+    disc = discrete_first_order(p)
+    k = 2 * np.pi / p.wavelength
+    pw = 2.25 * k ** (7 / 6) * _hv_integral(lambda z: (p.length - z) ** (5 / 6), p.length, p.wavelength)
+    g = np.array([x["si_plane"] for x in groups])
+    se = g.std(ddof=1) / np.sqrt(len(g))
+    say(f"[stats] placed HV 5/7: M={p.num_screens} SI {s['si_plane']:.5f} +- {se:.5f}; discrete first-order "
+        f"{disc:.5f}; plane-wave Rytov variance {pw:.5f}")
+    assert abs(s["si_plane"] - disc) < 4 * se + 0.01 * disc
+    assert abs(s["si_plane"] / pw - 1) < 0.03
+
+
+def test_placed_hufnagel_valley_broadening(api):
+    """Collimated Gaussian beam from the ground through the placed screens: the
+    long-term 1/e^2 radius (the paper's estimator, Sec. 3.2) matches
+    W sqrt(1 + 1.33 sigma^2 Lambda^(5/6)) (Eq. S24) with sigma^2 from Eq. S19
+    over the whole path, whose (1 - z/L)^(5/3) weighting is the one of a beam
+    leaving the ground, within 2 %.  The second-moment radius is printed only:
+    with l0 = 1 mm the long-term profile grows non-Gaussian wings, which a
+    second moment weights heavily (measured 5 % above the 1/e^2 radius)."""
+    from oracle import planner as opl
+    w = _placed_hv_workload("gaussian", seed=32)
+    p = w.path
+    _, s, _ = run_ensemble(api, w, 4096)
+    s2 = opl.rytov_interval(lambda z: float(opl.hufnagel_valley(z)), 0.0, p.length, p.wavelength)
+    w_vac = theory.gaussian_radius(w.w0, p.wavelength, p.length)
+    w_lt = theory.long_term_radius(w.w0, p.wavelength, p.length, s2)
+    say(f"[stats] placed HV 5/7 gaussian: W_fit {100 * s['w_fit']:.4f} cm, W_2nd {100 * s['w_2nd']:.4f} cm, "
+        f"Eq. S24 {100 * w_lt:.4f} cm (vacuum {100 * w_vac:.4f}, Eq. S19 sigma^2 {s2:.4f})")
+    assert abs(s["w_fit"] / w_lt - 1) < 0.02
