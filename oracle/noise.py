@@ -11,7 +11,8 @@ Counter layout (the paper fixes no generator; this build's contract):
     t   time step (0 for static screens and for the initial AR spectrum)
     j   realization-pair index (realizations 2j and 2j+1 share one complex screen)
     s   screen index along the path
-    tag 1 = main spectrum, 2 = subharmonics, 3 = AR innovation
+    tag 1 = main spectrum, 2 = subharmonics, 3 = AR innovation, 4 = AR innovation
+    of the subharmonic coefficients
   main / AR spectrum of an N x N grid: e = k0*N + k1 for 0 <= k0 < N/2; words
     (v0, v1) give bin (k0, k1) and words (v2, v3) give bin (k0 + N/2, k1).
   subharmonics: level p (1-based), offset index q in 0..7 over the 3x3 grid
@@ -32,6 +33,7 @@ from .philox import philox4x32_10
 TAG_MAIN = 1
 TAG_SH = 2
 TAG_AR = 3
+TAG_AR_SH = 4
 
 # 3x3 sub-grid offsets (m = y offset, n = x offset) without the centre, Eq. 2.
 SH_OFFSETS = [(m, n) for m in (-1, 0, 1) for n in (-1, 0, 1) if (m, n) != (0, 0)]
@@ -76,12 +78,13 @@ def spectral_noise(n, seed, t, pair, screen, tag=TAG_MAIN):
     return out
 
 
-def subharmonic_noise(levels, seed, t, pair, screen):
-    """[levels][8] complex noise for the subharmonic coefficients of Eq. 2."""
+def subharmonic_noise(levels, seed, t, pair, screen, tag=TAG_SH):
+    """[levels][8] complex noise for the subharmonic coefficients of Eq. 2
+    (tag TAG_AR_SH: the innovations of their AR evolution)."""
     out = np.zeros((levels, 8), dtype=np.complex128)
     for p in range(1, levels + 1):
         e = np.array([4 * (p - 1) + q for q in range(4)], dtype=np.uint64)
-        v = philox4x32_10(counters(e, t, pair, TAG_SH, screen), seed_key(seed))
+        v = philox4x32_10(counters(e, t, pair, tag, screen), seed_key(seed))
         for q in range(8):
             w = v[q // 2]
             out[p - 1, q] = box_muller(w[0], w[1]) if q % 2 == 0 else box_muller(w[2], w[3])

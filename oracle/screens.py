@@ -88,19 +88,41 @@ def unnormalised_idft(c):
     return np.fft.ifft2(c) * (n0 * n1)
 
 
-def subharmonic_screen(n, dx, r0, fm, f0, sh_noise, alpha=11.0 / 3.0):
-    """Eq. 2: complex subharmonic screen from [levels][8] noise coefficients."""
+def subharmonic_coefficients(n, dx, r0, fm, f0, sh_noise, alpha=11.0 / 3.0):
+    """Eq. 2 weights: [levels][8] complex coefficients N_pq sqrt(W(f_pq)) df_p
+    at the offsets SH_OFFSETS (m along y, n along x) of level p, df_p = df/3^p."""
     levels = sh_noise.shape[0]
     df = 1.0 / (n * dx)
-    x = (np.arange(n) - n // 2) * dx
-    z = np.zeros((n, n), dtype=np.complex128)
+    out = np.zeros((levels, 8), dtype=np.complex128)
     for p in range(1, levels + 1):
         dfp = df / 3.0 ** p
         for q, (m, nn) in enumerate(SH_OFFSETS):
             f2 = (m * m + nn * nn) * dfp * dfp
-            coef = sh_noise[p - 1, q] * np.sqrt(mvk_psd(f2, r0, fm, f0, alpha)) * dfp
-            z += coef * np.exp(2j * np.pi * (nn * dfp * x[None, :] + m * dfp * x[:, None]))
+            out[p - 1, q] = sh_noise[p - 1, q] * np.sqrt(mvk_psd(f2, r0, fm, f0, alpha)) * dfp
+    return out
+
+
+def subharmonic_field(n, dx, coefs, x=None, y=None):
+    """Eq. 2 sum: sum_pq c_pq exp(2 pi i (n df_p x + m df_p y)) on the centred
+    grid, or at the given coordinate vectors x (columns) and y (rows)."""
+    df = 1.0 / (n * dx)
+    if x is None:
+        x = (np.arange(n) - n // 2) * dx
+    if y is None:
+        y = (np.arange(n) - n // 2) * dx
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    z = np.zeros((len(y), len(x)), dtype=np.complex128)
+    for p in range(1, coefs.shape[0] + 1):
+        dfp = df / 3.0 ** p
+        for q, (m, nn) in enumerate(SH_OFFSETS):
+            z += coefs[p - 1, q] * np.exp(2j * np.pi * (nn * dfp * x[None, :] + m * dfp * y[:, None]))
     return z
+
+
+def subharmonic_screen(n, dx, r0, fm, f0, sh_noise, alpha=11.0 / 3.0):
+    """Eq. 2: complex subharmonic screen from [levels][8] noise coefficients."""
+    return subharmonic_field(n, dx, subharmonic_coefficients(n, dx, r0, fm, f0, sh_noise, alpha))
 
 
 def remove_piston(phi):
