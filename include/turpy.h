@@ -22,7 +22,8 @@
  *    enqueued, and turpy_last_error() returns a message for this thread.
  *  - Noise is Philox4x32-10 keyed by the 64-bit seed with counter
  *    (e, t, j, tag<<28 | s): t time step, j realization pair, s screen, tag 1
- *    main spectrum / 2 subharmonics / 3 AR innovation.  Realizations 2j and
+ *    main spectrum / 2 subharmonics / 3 AR innovation / 4 AR innovation of the
+ *    subharmonic coefficients.  Realizations 2j and
  *    2j+1 take the real and imaginary parts of one complex screen.
  *  - Gradients follow PyTorch's convention for real losses:
  *    g = dL/dRe(u) + i dL/dIm(u).
@@ -53,7 +54,8 @@ typedef enum { TURPY_TF_FRESNEL = 0, TURPY_TF_ANGULAR_SPECTRUM = 1 } turpy_tf_ki
 typedef enum {
   TURPY_SCREENS_SYNTH = 0,        /* synthesised from (seed, t) inside the passes (Eq. S16, Eq. 2-3) */
   TURPY_SCREENS_MATERIALIZED = 1, /* float [R][M][N][N] radians supplied by the caller               */
-  TURPY_SCREENS_SPECTRA = 2       /* complex64 [ceil(R/2)][M][N][N] pair spectra (AR state, Eq. 5)   */
+  TURPY_SCREENS_SPECTRA = 2       /* an AR state (turpy_evolve): pair spectra and, with subharmonic
+                                     levels, their subharmonic coefficients                        */
 } turpy_screen_src;
 
 /* Plan flags. */
@@ -133,13 +135,24 @@ turpy_status turpy_propagate(turpy_plan* plan, uint64_t seed, int64_t t, const v
                              int64_t u_in_stride, int32_t src, const void* screens_or_spectra,
                              void* u_out, void* checkpoints, void* ws, size_t ws_bytes, void* stream);
 
-/* Screen-spectrum evolution (Sec. 2.3): with t == 0 initialise
- * spectra[ceil(R/2)][M][N][N] to the static main spectra of Eq. S16 (DC zero);
- * with t >= 1 apply the frozen-flow shift of Eq. 4 by (shift_x, shift_y)
- * pixels (= T v / dx) and then the AR(1) blend of Eq. 5 with innovation noise
- * drawn at time step t.  0 <= alpha <= 1.  In place. */
+/* Screen-spectrum evolution (Sec. 2.3) of an AR state, in place.  The state
+ * (turpy_state_size bytes, device memory) is complex64 spectra
+ * [ceil(R/2)][M][N][N] in radians, followed, when the plan has subharmonic
+ * levels, by [ceil(R/2)][M][32] complex64 subharmonic coefficients in radians
+ * (the 24 points of Eq. 2, level-major in the offset order (m, n) = (-1,-1),
+ * (-1,0), (-1,1), (0,-1), (0,1), (1,-1), (1,0), (1,1); then their grid mean;
+ * then padding).  With t == 0: the static main spectra of Eq. S16 (DC zero)
+ * and the static subharmonic coefficients, so that the state reproduces the
+ * synthesised screens of t = 0.  With t >= 1: the frozen-flow shift of Eq. 4
+ * by (shift_x, shift_y) pixels (= T v / dx), then the AR(1) blend of Eq. 5 with
+ * innovation noise drawn at time step t; the subharmonic coefficients take
+ * the same two steps at their frequencies (n, m) df / 3^p (innovation tag 4).
+ * 0 <= alpha <= 1. */
 turpy_status turpy_evolve(turpy_plan* plan, uint64_t seed, int64_t t, double alpha, double shift_x,
                           double shift_y, void* spectra, void* ws, size_t ws_bytes, void* stream);
+
+/* Bytes of the plan's AR state (see turpy_evolve). */
+turpy_status turpy_state_size(const turpy_plan* plan, size_t* bytes);
 
 /* Adjoint of turpy_propagate with the same plan, seed, t and screens.
  *  grad_u_out  complex64 [R][N][N], read only.

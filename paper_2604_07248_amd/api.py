@@ -68,13 +68,35 @@ class Plan:
         return out
 
     def init_spectra(self, seed):
-        """AR state complex64 [ceil(R/2)][M][N][N] at t = 0 (static main spectra)."""
-        spec = torch.empty((self.pairs, self.m, self.n, self.n), dtype=torch.complex64, device=self.device)
+        """AR state at t = 0: the pair spectra complex64 [ceil(R/2)][M][N][N]
+        (radians), a view at the start of a buffer that also holds the
+        subharmonic coefficients when the plan has subharmonic levels
+        (`sh_coefficients`)."""
+        elems = B.state_size(self.handle) // 8
+        buf = torch.empty(elems, dtype=torch.complex64, device=self.device)
+        spec = buf[: self.pairs * self.m * self.n * self.n].view(self.pairs, self.m, self.n, self.n)
         B.evolve(self.handle, seed, 0, 0.0, 0.0, 0.0, _ptr(spec), None, 0, _stream())
         return spec
 
-    def evolve(self, spectra, seed, t, alpha, shift_x=0.0, shift_y=0.0):
+    def _need_state(self, spectra):
         _need(spectra, torch.complex64, (self.pairs, self.m, self.n, self.n), "spectra")
+        room = spectra.untyped_storage().nbytes() - spectra.storage_offset() * spectra.element_size()
+        if room < B.state_size(self.handle):
+            raise ValueError("spectra: the AR state needs room for the subharmonic coefficients after the "
+                             "spectra; allocate it with init_spectra")
+
+    def sh_coefficients(self, spectra):
+        """The state's subharmonic block complex64 [ceil(R/2)][M][32] (radians;
+        24 coefficients, their grid mean, padding), or None without levels."""
+        self._need_state(spectra)
+        if self.path.sh_levels == 0 or self.m == 0:
+            return None
+        base = spectra.storage_offset() + spectra.numel()
+        return torch.empty(0, dtype=torch.complex64, device=self.device).set_(
+            spectra.untyped_storage(), base, (self.pairs, self.m, 32))
+
+    def evolve(self, spectra, seed, t, alpha, shift_x=0.0, shift_y=0.0):
+        self._need_state(spectra)
         if t < 1:
             raise ValueError("evolve: t must be >= 1 (t = 0 is init_spectra)")
         B.evolve(self.handle, seed, t, alpha, shift_x, shift_y, _ptr(spectra), None, 0, _stream())
@@ -95,7 +117,7 @@ class Plan:
             _need(screens, torch.float32, (self.r, self.m, self.n, self.n), "screens")
             return B.SCREENS_MATERIALIZED, screens
         if spectra is not None:
-            _need(spectra, torch.complex64, (self.pairs, self.m, self.n, self.n), "spectra")
+            self._need_state(spectra)
             return B.SCREENS_SPECTRA, spectra
         return B.SCREENS_SYNTH, None
 

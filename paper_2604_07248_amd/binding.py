@@ -24,7 +24,7 @@ EXPORTS = [
     "turpy_version", "turpy_last_error", "turpy_plan_create", "turpy_plan_destroy", "turpy_workspace_size",
     "turpy_screen_generate", "turpy_propagate", "turpy_evolve", "turpy_propagate_backward", "turpy_stats",
     "turpy_receiver_workspace_size", "turpy_receiver", "turpy_receiver_backward", "turpy_profile",
-    "turpy_profile_only", "turpy_profile_read", "turpy_place_screens",
+    "turpy_profile_only", "turpy_profile_read", "turpy_place_screens", "turpy_state_size",
 ]
 
 
@@ -95,6 +95,7 @@ def lib():
         L.turpy_profile.argtypes = [c_int32]
         L.turpy_profile_only.argtypes = [c_char_p]
         L.turpy_profile_read.argtypes = [c_char_p, POINTER(c_int64), POINTER(c_double)]
+        L.turpy_state_size.argtypes = [c_void_p, POINTER(c_size_t)]
         L.turpy_place_screens.argtypes = [POINTER(CCn2Profile), c_double, c_double, c_double, c_int32, c_double,
                                           c_double, c_int32, c_int32, POINTER(c_int32), POINTER(c_double),
                                           POINTER(c_double), POINTER(c_double)]
@@ -133,6 +134,12 @@ def plan_create(path, flags=0):
     handle = c_void_p()
     check(lib().turpy_plan_create(ctypes.byref(handle), ctypes.byref(cp), flags))
     return handle
+
+
+def state_size(handle):
+    b = c_size_t()
+    check(lib().turpy_state_size(handle, ctypes.byref(b)))
+    return b.value
 
 
 def plan_destroy(handle):

@@ -359,6 +359,7 @@ RowArgs base_row(const turpy_plan* pl) {
   a.scale = 1.0f;
   a.M = pl->M;
   a.sh_phasor = pl->d_sh_phasor;
+  a.sh_scale = 1.0f;
   return a;
 }
 
@@ -430,17 +431,32 @@ hipError_t enqueue_col(const turpy_plan* pl, int step, const float2* in, int64_t
 }
 
 // Enqueue the column half of screen s into ws.scratch (noise or stored spectra).
-hipError_t enqueue_sh(const turpy_plan* pl, uint64_t seed, uint32_t t, const Ws& w, hipStream_t st) {
+ShArgs sh_args(const turpy_plan* pl, uint64_t seed, uint32_t t, float2* sh) {
   ShArgs a{};
-  a.sh = w.sh;
+  a.sh = sh;
   a.P = pl->P;
   a.M = pl->M;
   a.levels = pl->sh_levels;
+  a.n = pl->n;
   key_of(seed, &a.key0, &a.key1);
   a.t = t;
+  a.tag = TAG_SH;
   a.amp = pl->d_sh_amp;
+  a.scale = 1.0f;
   for (int i = 0; i < 3; ++i) a.mean_fac[i] = pl->sh_mean_fac[i];
+  return a;
+}
+
+// Fresh subharmonic coefficients of every pair and screen (revolutions) into ws.sh.
+hipError_t enqueue_sh(const turpy_plan* pl, uint64_t seed, uint32_t t, const Ws& w, hipStream_t st) {
+  const ShArgs a = sh_args(pl, seed, t, w.sh);
   return timed("sh", st, [&] { return launch_sh(a, st); });
+}
+
+// The subharmonic block of an AR state: after the pair spectra.
+float2* state_sh(const turpy_plan* pl, const void* spectra) {
+  return const_cast<float2*>(static_cast<const float2*>(spectra)) +
+         static_cast<size_t>(pl->P) * pl->M * pl->n * pl->n;
 }
 
 // Fill the screen fields of a row pass for screen s.
@@ -453,8 +469,14 @@ turpy_status screen_fields(const turpy_plan* pl, int32_t src, const void* screen
   } else {
     a->screen_mode = ROW_SCRATCH;
     a->scratch = w.scratch;
-    a->sh_levels = src == TURPY_SCREENS_SYNTH ? pl->sh_levels : 0;
-    a->sh = w.sh;
+    a->sh_levels = pl->sh_levels;
+    if (src == TURPY_SCREENS_SYNTH) {
+      a->sh = w.sh;
+      a->sh_scale = 1.0f;
+    } else {  // the AR state's subharmonic block, in radians
+      a->sh = state_sh(pl, screens_or_spectra);
+      a->sh_scale = static_cast<float>(1.0 / (2.0 * kPi));
+    }
   }
   return TURPY_OK;
 }
@@ -762,6 +784,25 @@ turpy_status turpy_evolve(turpy_plan* pl, uint64_t seed, int64_t t, double alpha
   a.q = pl->qexp;
   hipStream_t st = static_cast<hipStream_t>(stream);
   TURPY_HIP(timed("evolve", st, [&] { return launch_evolve(a, st); }), "evolve");
+  if (pl->sh_levels > 0) {
+    // the subharmonic coefficients after the spectra: fresh at t = 0 (the
+    // static ones), else the same translation and blend at their frequencies
+    ShArgs b = sh_args(pl, seed, static_cast<uint32_t>(t), state_sh(pl, spectra));
+    b.scale = static_cast<float>(2.0 * kPi);
+    b.ar = t == 0 ? 0 : 1;
+    b.tag = t == 0 ? TAG_SH : TAG_AR_SH;
+    b.alpha = alpha;
+    b.sx = shift_x;
+    b.sy = shift_y;
+    TURPY_HIP(timed("sh", st, [&] { return launch_sh(b, st); }), "evolve: subharmonics");
+  }
+  return TURPY_OK;
+}
+
+turpy_status turpy_state_size(const turpy_plan* pl, size_t* bytes) {
+  if (!pl || !bytes) return fail(TURPY_E_INVALID, "state_size: NULL argument");
+  const size_t spectra = static_cast<size_t>(pl->P) * pl->M * pl->n * pl->n * sizeof(float2);
+  *bytes = spectra + (pl->sh_levels > 0 ? static_cast<size_t>(pl->P) * pl->M * 32 * sizeof(float2) : 0);
   return TURPY_OK;
 }
 

@@ -62,7 +62,7 @@ void row_pass_kernel(RowArgs a) {
     fft<N, kE, true, WV>(z, lds, t, tw);
     if (a.sh_levels > 0) {
       const float2* c = a.sh + (static_cast<size_t>(j) * a.M + a.screen) * 32;
-      const float2 mean = c[24];
+      const float2 mean = c_scale(c[24], a.sh_scale);
 #pragma unroll
       for (int m = 0; m < kE; ++m) z[m] = c_sub(z[m], mean);
       for (int p = 0; p < a.sh_levels; ++p) {
@@ -71,9 +71,9 @@ void row_pass_kernel(RowArgs a) {
         const float2 ey = ph[i0];
         const float2 eyc = make_float2(ey.x, -ey.y);
         // offsets (m, n): 0 (-1,-1) 1 (-1,0) 2 (-1,1) 3 (0,-1) 4 (0,1) 5 (1,-1) 6 (1,0) 7 (1,1)
-        const float2 dm = c_add(c_add(c_mul(cp[0], eyc), cp[3]), c_mul(cp[5], ey));
-        const float2 d0 = c_add(c_mul(cp[1], eyc), c_mul(cp[6], ey));
-        const float2 dp = c_add(c_add(c_mul(cp[2], eyc), cp[4]), c_mul(cp[7], ey));
+        const float2 dm = c_scale(c_add(c_add(c_mul(cp[0], eyc), cp[3]), c_mul(cp[5], ey)), a.sh_scale);
+        const float2 d0 = c_scale(c_add(c_mul(cp[1], eyc), c_mul(cp[6], ey)), a.sh_scale);
+        const float2 dp = c_scale(c_add(c_add(c_mul(cp[2], eyc), cp[4]), c_mul(cp[7], ey)), a.sh_scale);
         const float2 sa = c_add(dp, dm);
         const float2 sb = c_sub(dp, dm);
 #pragma unroll
@@ -256,7 +256,7 @@ void row_pair_kernel(RowArgs a) {
     if (role == 0) {
       if (a.sh_levels > 0) {
         const float2* c = a.sh + (static_cast<size_t>(j) * a.M + a.screen) * 32;
-        const float2 mean = c[24];
+        const float2 mean = c_scale(c[24], a.sh_scale);
 #pragma unroll
         for (int m = 0; m < kE; ++m) x[m] = c_sub(x[m], mean);
         for (int p = 0; p < a.sh_levels; ++p) {
@@ -265,9 +265,9 @@ void row_pair_kernel(RowArgs a) {
           const float2 ey = phs[i0];
           const float2 eyc = make_float2(ey.x, -ey.y);
           // offsets (m, n): 0 (-1,-1) 1 (-1,0) 2 (-1,1) 3 (0,-1) 4 (0,1) 5 (1,-1) 6 (1,0) 7 (1,1)
-          const float2 dm = c_add(c_add(c_mul(cp[0], eyc), cp[3]), c_mul(cp[5], ey));
-          const float2 d0 = c_add(c_mul(cp[1], eyc), c_mul(cp[6], ey));
-          const float2 dp = c_add(c_add(c_mul(cp[2], eyc), cp[4]), c_mul(cp[7], ey));
+          const float2 dm = c_scale(c_add(c_add(c_mul(cp[0], eyc), cp[3]), c_mul(cp[5], ey)), a.sh_scale);
+          const float2 d0 = c_scale(c_add(c_mul(cp[1], eyc), c_mul(cp[6], ey)), a.sh_scale);
+          const float2 dp = c_scale(c_add(c_add(c_mul(cp[2], eyc), cp[4]), c_mul(cp[7], ey)), a.sh_scale);
           const float2 sa = c_add(dp, dm);
           const float2 sb = c_sub(dp, dm);
 #pragma unroll
@@ -606,21 +606,34 @@ __global__ __launch_bounds__(64) void sh_kernel(ShArgs a) {
   const int64_t j = blockIdx.x;
   const int s = blockIdx.y;
   const int l = threadIdx.x;
+  float2* out = a.sh + (static_cast<size_t>(j) * a.M + s) * 32;
   if (l < 4 * a.levels) {
     const int p = l / 4;
-    const uint4 v = philox4x32_10(noise_counter(static_cast<uint32_t>(l), a.t, static_cast<uint32_t>(j), TAG_SH,
+    const uint4 v = philox4x32_10(noise_counter(static_cast<uint32_t>(l), a.t, static_cast<uint32_t>(j), a.tag,
                                                 static_cast<uint32_t>(s)),
                                   a.key0, a.key1);
-    const int q0 = 2 * (l % 4), q1 = q0 + 1;
-    // offsets with |m| + |n| = 2 (diagonal) are q = 0, 2, 5, 7
-    const bool diag0 = (q0 == 0 || q0 == 2 || q0 == 5 || q0 == 7);
-    const bool diag1 = (q1 == 0 || q1 == 2 || q1 == 5 || q1 == 7);
     const float* amp = a.amp + (static_cast<size_t>(s) * 3 + p) * 2;
-    coef[8 * p + q0] = c_scale(box_muller(v.x, v.y), amp[diag0 ? 1 : 0]);
-    coef[8 * p + q1] = c_scale(box_muller(v.z, v.w), amp[diag1 ? 1 : 0]);
+    for (int h = 0; h < 2; ++h) {
+      const int q = 2 * (l % 4) + h;
+      // offset (m, n) of point q: 0 (-1,-1) 1 (-1,0) 2 (-1,1) 3 (0,-1) 4 (0,1) 5 (1,-1) 6 (1,0) 7 (1,1)
+      const int m = q < 3 ? -1 : (q < 5 ? 0 : 1);
+      const int nn = q < 3 ? q - 1 : (q == 3 ? -1 : (q == 4 ? 1 : q - 6));
+      const bool diag = m != 0 && nn != 0;
+      float2 c = c_scale(h == 0 ? box_muller(v.x, v.y) : box_muller(v.z, v.w), amp[diag ? 1 : 0] * a.scale);
+      if (a.ar) {
+        // Eq. 4 at (n df_p, m df_p): exp(-2 pi i (n sx + m sy) / (3^p N)), then Eq. 5
+        double rev = -(nn * a.sx + m * a.sy) / (a.n * (p == 0 ? 3.0 : (p == 1 ? 9.0 : 27.0)));
+        rev -= rint(rev);
+        float sn, cs;
+        sincos_rev(static_cast<float>(rev), &sn, &cs);
+        const float2 old = out[8 * p + q];
+        c = c_add(c_scale(c_mul(old, make_float2(cs, sn)), static_cast<float>(a.alpha)),
+                  c_scale(c, static_cast<float>(sqrt(1.0 - a.alpha * a.alpha))));
+      }
+      coef[8 * p + q] = c;
+    }
   }
   __syncthreads();
-  float2* out = a.sh + (static_cast<size_t>(j) * a.M + s) * 32;
   if (l < 24) out[l] = l < 8 * a.levels ? coef[l] : make_float2(0.0f, 0.0f);
   if (l == 0) {
     float2 mean = make_float2(0.0f, 0.0f);

@@ -11,6 +11,7 @@ namespace turpy {
 constexpr uint32_t TAG_MAIN = 1;
 constexpr uint32_t TAG_SH = 2;
 constexpr uint32_t TAG_AR = 3;
+constexpr uint32_t TAG_AR_SH = 4;  // AR innovations of the subharmonic coefficients
 
 // Screen source inside a row pass.
 enum RowScreen : int { ROW_NO_SCREEN = 0, ROW_SCRATCH = 1, ROW_MATERIALIZED = 2 };
@@ -33,7 +34,8 @@ struct RowArgs {
   int screen;               // screen index s
   int M;                    // screens per path
   int sh_levels;            // 0..3
-  const float2* sh;         // [P][M][32] subharmonic coefficients (revolutions), [24] = mean
+  const float2* sh;         // [P][M][32] subharmonic coefficients, [24] = their grid mean
+  float sh_scale;           // to revolutions: 1 (synthesised) or 1/(2 pi) (AR state, radians)
   const float2* sh_phasor;  // [3][N] exp(2 pi i (i - N/2) / (N 3^p))
   int backward;             // 0: W = U e^{i phi}; 1: adjoint (read checkpoint, write dL/dphi, e^{-i phi})
   float2* ckpt_out;         // forward: [R][M][N][N] field after the screen, or NULL
@@ -75,12 +77,16 @@ struct SynthArgs {
 };
 
 struct ShArgs {
-  float2* sh;               // [P][M][32]
+  float2* sh;               // [P][M][32], in place for an AR step
   int64_t P;
   int M;
   int levels;
-  uint32_t key0, key1, t;
+  int n;                    // grid size (translation phase of an AR step)
+  uint32_t key0, key1, t, tag;
   const float* amp;         // [M][3][2] amplitude (revolutions) for |offset|^2 = 1, 2
+  float scale;              // output units per revolution: 1, or 2 pi for radians
+  int ar;                   // 0: fresh coefficients; 1: Eq. 4 + Eq. 5 step of the stored ones
+  double alpha, sx, sy;     // AR step: blend and translation in pixels
   float2 mean_fac[3];       // mean over the grid of exp(2 pi i (i - N/2)/(N 3^p))
 };
 

@@ -184,6 +184,44 @@ def test_evolve_and_spectra_propagation(api):
     assert e_spec < TOL and e_out < TOL
 
 
+def test_evolve_with_subharmonics(api):
+    """AR state with three subharmonic levels: at t = 0 it reproduces the
+    synthesised screens; after three Eq. 4 + Eq. 5 steps (fractional shifts)
+    the spectra, the subharmonic coefficients, the propagated field and the
+    adjoint match the oracle."""
+    path = sized_path(256, realizations=3, m=2, sh=3)
+    say("[evolve-sh] n=256 sh=3")
+    plan = api.Plan(path)
+    u0 = gaussian(path).astype(np.complex64)
+    spec = plan.init_spectra(seed=4)
+    ref_c, ref_d = oev.initial_spectra(path, 4), oev.initial_sh(path, 4)
+    sh = plan.sh_coefficients(spec)
+    assert rel_l2(sh[:, :, :24].cpu().numpy(), ref_d.reshape(ref_d.shape[0], ref_d.shape[1], 24)) < TOL
+    a = plan.propagate(c64(u0), spectra=spec).cpu().numpy()
+    b = plan.propagate(c64(u0), seed=4).cpu().numpy()  # the synthesised screens of t = 0
+    e0 = rel_l2(a, b)
+    for t in (1, 2, 3):
+        plan.evolve(spec, seed=4, t=t, alpha=0.9, shift_x=0.6, shift_y=-0.35)
+        ref_c = oev.evolve(ref_c, path, 4, t, 0.9, 0.6, -0.35)
+        ref_d = oev.evolve_sh(ref_d, path, 4, t, 0.9, 0.6, -0.35)
+    e_spec = rel_l2(spec.cpu().numpy(), ref_c)
+    e_sh = rel_l2(sh[:, :, :24].cpu().numpy(), ref_d.reshape(ref_d.shape[0], ref_d.shape[1], 24))
+    out, ck = plan.propagate(c64(u0), spectra=spec, checkpoints=True)
+    phi = oev.screens_from_state(ref_c, ref_d, path, path.realizations)
+    ref_out, ref_ck = opr.propagate(u0.astype(np.complex128), path, phi)
+    e_out = rel_l2(out.cpu().numpy(), ref_out)
+    rng = np.random.default_rng(5)
+    g = (rng.standard_normal(ref_out.shape) + 1j * rng.standard_normal(ref_out.shape)).astype(np.complex64)
+    g_in, g_phi = plan.propagate_backward(c64(g), ck, spectra=spec)
+    ref_gin, ref_gphi = opr.propagate_adjoint(g.astype(np.complex128), path, phi, ref_ck)
+    e_gin, e_gphi = rel_l2(g_in.cpu().numpy(), ref_gin), rel_l2(g_phi.cpu().numpy(), ref_gphi)
+    say(f"[evolve-sh] t=0 state vs synthesised {e0:.2e}; spectra {e_spec:.2e} sh {e_sh:.2e} field {e_out:.2e} "
+        f"grad_in {e_gin:.2e} grad_phi {e_gphi:.2e}")
+    assert e0 < 1e-5 and e_spec < TOL and e_sh < TOL and e_out < TOL and e_gin < TOL and e_gphi < TOL
+    with pytest.raises(ValueError):
+        plan.propagate(c64(u0), spectra=spec.clone())  # a copy without the subharmonic block
+
+
 def test_stats_match_oracle(api):
     rng = np.random.default_rng(8)
     n, dx = 128, 0.004
