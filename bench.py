@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--realizations", type=int, default=64)
-    ap.add_argument("--only", choices=["all", "fwd", "fwdbwd", "ar", "plain", "copy"], default="all",
+    ap.add_argument("--only", choices=["all", "fwd", "fwdbwd", "ar", "plain", "copy", "fwd_as"], default="all",
                     help="run one leg (profiling runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-pairs", type=int, default=16, help="realization pairs in the oracle sample (about 20 s of CPU work)")
@@ -241,6 +241,20 @@ def main():
         # whole-path effective bandwidth: every family's algorithmic bytes per step
         result["path_effective_GBps"] = sum(step_bytes(path, "fwd").values()) / sec / 1e9
         result["roofline"] = roofline(ktab, dom, prof_summary.load_traffic(os.path.join(ROOT, "profiles"), "fwd"))
+
+    if args.only in ("all", "fwd_as"):
+        # the same forward step with the angular-spectrum transfer function (Sec. 2.1)
+        pas = path.with_(tf_kind=workloads.TF_ANGULAR_SPECTRUM)
+        plan_as = api.Plan(pas)
+
+        def fwd_as(i):
+            plan_as.propagate(u0, seed=w.seed, t=i, out=u_out)
+            moments.add(u_out)
+
+        sec, ktab, dom = measure(torch, fwd_as, args.steps, args.warmup, binding, fams, pas, "fwd")
+        result["fwd_angular_spectrum"] = {"value": ss_per_step / sec, "unit": "screen-steps/s",
+                                          "ms_per_step": 1e3 * sec, "kernels": ktab, "dominant": dom}
+        plan_as.close()
 
     if args.only in ("all", "fwdbwd"):
         ck = torch.empty((path.realizations, path.num_screens, path.n, path.n), dtype=torch.complex64, device=dev)

@@ -142,6 +142,10 @@ struct turpy_plan {
   float2* d_tw = nullptr;        // [N]
   float2* d_row = nullptr;       // [M+1][N] h_i[k]
   float2* d_col = nullptr;       // [M+1][N] h_i[k] / N
+  // angular spectrum: H_as / H_fresnel as a function of q = k0^2 + k1^2 (signed
+  // bins), one table of N^2/2 + 1 entries per distinct distance
+  float2* d_as = nullptr;
+  std::vector<int> as_index;     // [M+1] table of each step
   float2* d_sh_phasor = nullptr; // [3][N]
   float* d_sh_amp = nullptr;     // [M][3][2]
   float* d_amp_rad = nullptr;    // [M]
@@ -280,6 +284,46 @@ turpy_status turpy_plan_create(turpy_plan** out, const turpy_path* p, uint32_t f
     }
     pl->sh_mean_fac[lv] = make_float2(static_cast<float>(mr / n), static_cast<float>(mi / n));
   }
+  // Angular-spectrum correction (Sec. 2.1, R1): H_as / H_fresnel at
+  // kappa^2 = (2 pi df)^2 q, in FP64 with exact range reduction:
+  //   propagating (kappa < k): exp(-i dz kappa^4 / (2k (s + k)^2)), s = sqrt(k^2 - kappa^2)
+  //   evanescent: exp(-dz sqrt(kappa^2 - k^2)) exp(i dz (kappa^2 / (2k) - k))
+  std::vector<float2> as;
+  // the grid corner kappa^2 = 2 (pi/dx)^2 against k^2: tables only where bins are evanescent
+  const bool evanescent = 2.0 * (kPi / pl->dx) * (kPi / pl->dx) >= 0.999 * k * k;
+  if (pl->tf_kind == TURPY_TF_ANGULAR_SPECTRUM && evanescent) {
+    const size_t qn = static_cast<size_t>(n) * n / 2 + 1;
+    std::vector<double> distinct;
+    for (int s = 0; s <= M; ++s) {
+      int idx = -1;
+      for (size_t d = 0; d < distinct.size(); ++d)
+        if (distinct[d] == pl->dz[s]) idx = static_cast<int>(d);
+      if (idx < 0) {
+        idx = static_cast<int>(distinct.size());
+        distinct.push_back(pl->dz[s]);
+      }
+      pl->as_index.push_back(idx);
+    }
+    as.resize(distinct.size() * qn);
+    const double w2 = (2.0 * kPi * df) * (2.0 * kPi * df);
+    for (size_t d = 0; d < distinct.size(); ++d) {
+      const double dz = distinct[d];
+      for (size_t q = 0; q < qn; ++q) {
+        const double kap2 = w2 * static_cast<double>(q);
+        float2 v;
+        if (kap2 < k * k) {
+          const double sp = std::sqrt(k * k - kap2) + k;
+          v = phasor(-dz * kap2 * kap2 / (2.0 * k * sp * sp) / (2.0 * kPi));
+        } else {
+          const double decay = dz * std::sqrt(kap2 - k * k);
+          const double mag = decay > 745.0 ? 0.0 : std::exp(-decay);
+          const float2 ph = phasor(dz * (kap2 / (2.0 * k) - k) / (2.0 * kPi));
+          v = make_float2(static_cast<float>(mag * ph.x), static_cast<float>(mag * ph.y));
+        }
+        as[d * qn + q] = v;
+      }
+    }
+  }
   auto upload = [&](auto** dst, const void* src, size_t bytes) -> hipError_t {
     hipError_t e = hipMalloc(reinterpret_cast<void**>(dst), bytes);
     if (e != hipSuccess) return e;
@@ -289,6 +333,7 @@ turpy_status turpy_plan_create(turpy_plan** out, const turpy_path* p, uint32_t f
   if (e == hipSuccess) e = upload(&pl->d_tw, tw.data(), tw.size() * sizeof(float2));
   if (e == hipSuccess) e = upload(&pl->d_row, row.data(), row.size() * sizeof(float2));
   if (e == hipSuccess) e = upload(&pl->d_col, col.data(), col.size() * sizeof(float2));
+  if (e == hipSuccess && !as.empty()) e = upload(&pl->d_as, as.data(), as.size() * sizeof(float2));
   if (e == hipSuccess) e = upload(&pl->d_sh_phasor, shp.data(), shp.size() * sizeof(float2));
   if (e == hipSuccess) e = upload(&pl->d_sh_amp, sh_amp.data(), sh_amp.size() * sizeof(float));
   std::vector<float> amp_rad = pl->amp_rad;
@@ -307,6 +352,7 @@ turpy_status turpy_plan_destroy(turpy_plan* pl) {
   (void)hipFree(pl->d_tw);
   (void)hipFree(pl->d_row);
   (void)hipFree(pl->d_col);
+  (void)hipFree(pl->d_as);
   (void)hipFree(pl->d_sh_phasor);
   (void)hipFree(pl->d_sh_amp);
   (void)hipFree(pl->d_amp_rad);
@@ -379,9 +425,14 @@ ColArgs col_args(const turpy_plan* pl, int step, const float2* in, int64_t in_st
   c.table = pl->d_col + static_cast<size_t>(step) * pl->n;
   c.conj_table = adjoint ? 1 : 0;
   c.angular = pl->tf_kind == TURPY_TF_ANGULAR_SPECTRUM ? 1 : 0;
-  c.dz = pl->dz[step];
-  c.k = 2.0 * kPi * pl->n0 / pl->wavelength;
-  c.df = pl->df;
+  if (c.angular) {
+    if (pl->d_as)
+      c.as_table = pl->d_as + static_cast<size_t>(pl->as_index[step]) * (static_cast<size_t>(pl->n) * pl->n / 2 + 1);
+    const double k = 2.0 * kPi * pl->n0 / pl->wavelength;
+    const double w2 = (2.0 * kPi * pl->df) * (2.0 * kPi * pl->df);
+    c.as_b = static_cast<float>(w2 / (k * k));
+    c.as_c = static_cast<float>(-pl->dz[step] * w2 * w2 / (4.0 * kPi * k * k * k));
+  }
   return c;
 }
 

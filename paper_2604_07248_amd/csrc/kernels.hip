@@ -377,37 +377,34 @@ void row_pair_kernel(RowArgs a) {
 // ---------------------------------------------------------------------------
 // Column pass: FFT along y, x h(k0)/N (x angular-spectrum correction), IFFT.
 // ---------------------------------------------------------------------------
-// Evanescent bins (kappa >= k): exp(-dz sqrt(kappa^2 - k^2)) exp(-i k dz) / exp(-i dz kappa^2 / (2k)),
-// with the large phase reduced in FP64.  Rare; kept out of line so that it
-// does not hold registers in the common path.
-__device__ __attribute__((noinline)) float2 evanescent_correction(float kap2f, double dz, double k) {
-  const double kap2 = kap2f;
-  const double decay = dz * sqrt(kap2 - k * k);
-  if (decay > 87.0) return make_float2(0.0f, 0.0f);  // below FP32's smallest normal
-  const double mag = exp(-decay);
-  double rev = (-k * dz + dz * kap2 / (2.0 * k)) * 0.15915494309189535;
-  rev -= rint(rev);
-  float sn, cs;
-  sincos_rev(static_cast<float>(rev), &sn, &cs);
-  return make_float2(static_cast<float>(mag) * cs, static_cast<float>(mag) * sn);
+// Transfer-function modes of the column pass: Fresnel chirp only, or the
+// angular-spectrum correction H_as / H_fresnel on top of it (Sec. 2.1).
+constexpr int TF_FRESNEL_ONLY = 0;
+constexpr int TF_AS_FP32 = 1;   // every bin propagates: the small angle in FP32
+constexpr int TF_AS_TABLE = 2;  // evanescent bins present: the plan's FP64 radial table
+
+// Correction of bin (k0, k1), a function of q = k0^2 + k1^2 (signed bins).
+// FP32 form: -dz kappa^4 / (2k (s + k)^2), s = sqrt(k^2 - kappa^2), written as
+// C q^2 / (1 + sqrt(1 - B q))^2 revolutions with kappa^2 = (2 pi df)^2 q,
+// B = (2 pi df)^2 / k^2, C = -dz (2 pi df)^4 / (4 pi k^3); well conditioned
+// (no cancellation) for every propagating bin.
+template <int MODE>
+__device__ __forceinline__ float2 angular_correction(const ColArgs& a, int k0, int k1, int n) {
+  const int kx = signed_bin(k1, n), ky = signed_bin(k0, n);
+  const int q = kx * kx + ky * ky;
+  if constexpr (MODE == TF_AS_TABLE) {
+    return a.as_table[q];
+  } else {
+    const float qf = static_cast<float>(q);
+    const float r = 1.0f + __builtin_amdgcn_sqrtf(1.0f - qf * a.as_b);
+    const float rev = a.as_c * qf * qf * __builtin_amdgcn_rcpf(r * r);
+    float sn, cs;
+    sincos_rev(rev, &sn, &cs);
+    return make_float2(cs, sn);
+  }
 }
 
-// H_as / H_fresnel = exp(i dz (s - k + kappa^2/(2k))) = exp(-i dz kappa^4 / (2k (s+k)^2)),
-// s = sqrt(k^2 - kappa^2): a small, well-conditioned angle evaluated in FP32.
-__device__ __forceinline__ float2 angular_correction(int k0, int k1, int n, double dz, double k, double df) {
-  const float kx = static_cast<float>(signed_bin(k1, n)), ky = static_cast<float>(signed_bin(k0, n));
-  const float w = 6.283185307179586f * static_cast<float>(df);
-  const float kap2 = (kx * kx + ky * ky) * (w * w);
-  const float kf = static_cast<float>(k);
-  if (kap2 >= kf * kf) return evanescent_correction(kap2, dz, k);
-  const float sp = kf * sqrtf(1.0f - kap2 / (kf * kf)) + kf;
-  const float d = -static_cast<float>(dz) * kap2 * kap2 / (2.0f * kf * sp * sp);
-  float sn, cs;
-  sincos_rev(d * 0.15915494309189535f, &sn, &cs);
-  return make_float2(cs, sn);
-}
-
-template <int N, bool ANGULAR>
+template <int N, int ANGULAR>
 __global__ __launch_bounds__(col_block<N>()) __attribute__((amdgpu_waves_per_eu(TURPY_COL_WAVES, 0)))
 void col_pass_kernel(ColArgs a) {
   constexpr int T = N / kE;
@@ -439,7 +436,7 @@ void col_pass_kernel(ColArgs a) {
   for (int m = 0; m < kE; ++m) {
     const int k0 = t + T * m;
     float2 h = chirp[k0];
-    if constexpr (ANGULAR) h = c_mul(h, angular_correction(k0, k1, N, a.dz, a.k, a.df));
+    if constexpr (ANGULAR != TF_FRESNEL_ONLY) h = c_mul(h, angular_correction<ANGULAR>(a, k0, k1, N));
     x[m] = a.conj_table ? c_mulc(x[m], h) : c_mul(x[m], h);
   }
   fft<N, kE, true>(x, lds, t, tw);
@@ -530,19 +527,19 @@ __device__ __forceinline__ void synth_column(float2 (&z)[kE], const SynthArgs& a
   }
 }
 
-template <int N, bool ANGULAR>
+template <int N, int ANGULAR>
 __device__ __forceinline__ void col_transfer(float2 (&x)[kE], const ColArgs& a, int k1, int t) {
   constexpr int T = N / kE;
 #pragma unroll
   for (int m = 0; m < kE; ++m) {
     const int k0 = t + T * m;
     float2 h = a.table[k0];
-    if constexpr (ANGULAR) h = c_mul(h, angular_correction(k0, k1, N, a.dz, a.k, a.df));
+    if constexpr (ANGULAR != TF_FRESNEL_ONLY) h = c_mul(h, angular_correction<ANGULAR>(a, k0, k1, N));
     x[m] = a.conj_table ? c_mulc(x[m], h) : c_mul(x[m], h);
   }
 }
 
-template <int N, bool ANGULAR, bool SYNTH>
+template <int N, int ANGULAR, bool SYNTH>
 __global__ __launch_bounds__(col_block<N>()) __attribute__((amdgpu_waves_per_eu(TURPY_COL_WAVES, 0)))
 void col_pair_kernel(ColArgs a, SynthArgs syn) {
   constexpr int T = N / kE;
@@ -865,10 +862,13 @@ template <int N>
 hipError_t col_launch(const ColArgs& a, hipStream_t s) {
   constexpr int K = col_width<N>();
   const uint64_t blocks = static_cast<uint64_t>(N / K) * a.R;
-  if (a.angular)
-    hipLaunchKernelGGL((col_pass_kernel<N, true>), dim3(static_cast<uint32_t>(blocks)), dim3(col_block<N>()), 0, s, a);
+  const dim3 grid(static_cast<uint32_t>(blocks)), block(col_block<N>());
+  if (!a.angular)
+    hipLaunchKernelGGL((col_pass_kernel<N, TF_FRESNEL_ONLY>), grid, block, 0, s, a);
+  else if (a.as_table)
+    hipLaunchKernelGGL((col_pass_kernel<N, TF_AS_TABLE>), grid, block, 0, s, a);
   else
-    hipLaunchKernelGGL((col_pass_kernel<N, false>), dim3(static_cast<uint32_t>(blocks)), dim3(col_block<N>()), 0, s, a);
+    hipLaunchKernelGGL((col_pass_kernel<N, TF_AS_FP32>), grid, block, 0, s, a);
   return hipGetLastError();
 }
 
@@ -878,12 +878,15 @@ hipError_t col_pair_launch(const ColArgs& a, const SynthArgs& syn, int do_synth,
   const int64_t pairs = (a.R + 1) / 2;
   const dim3 grid(static_cast<uint32_t>(static_cast<uint64_t>(N / K) * pairs));
   const dim3 block(col_block<N>());
-  if (a.angular) {
-    if (do_synth) hipLaunchKernelGGL((col_pair_kernel<N, true, true>), grid, block, 0, s, a, syn);
-    else hipLaunchKernelGGL((col_pair_kernel<N, true, false>), grid, block, 0, s, a, syn);
+  if (a.angular && a.as_table) {
+    if (do_synth) hipLaunchKernelGGL((col_pair_kernel<N, TF_AS_TABLE, true>), grid, block, 0, s, a, syn);
+    else hipLaunchKernelGGL((col_pair_kernel<N, TF_AS_TABLE, false>), grid, block, 0, s, a, syn);
+  } else if (a.angular) {
+    if (do_synth) hipLaunchKernelGGL((col_pair_kernel<N, TF_AS_FP32, true>), grid, block, 0, s, a, syn);
+    else hipLaunchKernelGGL((col_pair_kernel<N, TF_AS_FP32, false>), grid, block, 0, s, a, syn);
   } else {
-    if (do_synth) hipLaunchKernelGGL((col_pair_kernel<N, false, true>), grid, block, 0, s, a, syn);
-    else hipLaunchKernelGGL((col_pair_kernel<N, false, false>), grid, block, 0, s, a, syn);
+    if (do_synth) hipLaunchKernelGGL((col_pair_kernel<N, TF_FRESNEL_ONLY, true>), grid, block, 0, s, a, syn);
+    else hipLaunchKernelGGL((col_pair_kernel<N, TF_FRESNEL_ONLY, false>), grid, block, 0, s, a, syn);
   }
   return hipGetLastError();
 }

@@ -53,9 +53,9 @@ struct ColArgs {
   const float2* table;      // h[k0] / N for this distance, [N]
   int conj_table;
   int angular;              // angular-spectrum correction on top of the separable Fresnel chirp
-  double dz;                // distance (for the angular-spectrum correction)
-  double k;                 // 2 pi n0 / lambda
-  double df;                // 1 / (N dx)
+  const float2* as_table;   // [N^2/2 + 1]: H_as / H_fresnel at q = k0^2 + k1^2 (signed bins), or NULL
+  float as_b;               // (2 pi df)^2 / k^2: kappa^2 / k^2 per unit of q
+  float as_c;               // -dz (2 pi df)^4 / (4 pi k^3): revolutions per q^2 / (1 + sqrt(1 - B q))^2
 };
 
 struct SynthArgs {

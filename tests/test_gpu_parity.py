@@ -129,6 +129,31 @@ def test_propagate_options(api, case):
     assert err < TOL
 
 
+def test_angular_spectrum_evanescent_grid(api):
+    """dx = lambda/2: the grid's outer bins have kappa > k and decay
+    (evanescent), so the angular-spectrum correction comes from the plan's
+    FP64 radial table instead of the FP32 propagating-only form."""
+    lam, dx, n = 1e-6, 0.5e-6, 64
+    path = workloads.Path(n=n, dx=dx, wavelength=lam, dz=(4e-6, 7e-6, 4e-6), cn2dz=(2e-17, 2e-17),
+                          l0=0.0, L0=float("inf"), tf_kind=workloads.TF_ANGULAR_SPECTRUM, realizations=3)
+    say("[options] evanescent n=64 dx=lambda/2")
+    u0 = workloads.seeded_field((n, n), 13)  # broadband: energy in the evanescent bins too
+    plan = api.Plan(path)
+    out, ck = plan.propagate(c64(u0), seed=11, checkpoints=True)
+    ref, ref_ck = oracle_propagate(path, 11, u0)
+    err = rel_l2(out.cpu().numpy(), ref)
+    kept = float(np.sum(np.abs(ref[0]) ** 2) / np.sum(np.abs(u0.astype(np.complex128)) ** 2))
+    assert kept < 0.9  # the decay of the evanescent bins is part of what is compared
+    rng = np.random.default_rng(12)
+    g = (rng.standard_normal(ref.shape) + 1j * rng.standard_normal(ref.shape)).astype(np.complex64)
+    g_in, _ = plan.propagate_backward(c64(g), ck, seed=11)
+    phi = oracle_screens(path, 11, range(3))
+    ref_gin, _ = opr.propagate_adjoint(g.astype(np.complex128), path, phi, ref_ck)
+    eg = rel_l2(g_in.cpu().numpy(), ref_gin)
+    say(f"[options] evanescent rel-L2 {err:.2e} grad_in {eg:.2e} energy kept {kept:.3f}")
+    assert err < TOL and eg < TOL
+
+
 def test_materialized_equals_synthesised(api):
     path = sized_path(512, realizations=4, m=3, sh=3)
     say("[materialized] n=512")
