@@ -121,10 +121,13 @@ def broadening(trials, batch, n=1024, wavelength=1.064e-6, theta0=5e-5):
               f"{r['W_vac_cm']:.3f} | {r['W_sim_cm']:.3f} | {r['W_S24_cm']:.3f} | {r['W_strong_cm']:.3f} |")
 
 
-def scintillation(trials, batch, n=1024, wavelength=1.064e-6, length=20000.0):
+SCINT_EXPONENTS = (-17.5, -17.0, -16.5, -16.0, -15.5, -15.0, -14.5, -14.0, -13.5)
+
+
+def scintillation(trials, batch, n=1024, wavelength=1.064e-6, length=20000.0, exponents=SCINT_EXPONENTS):
     from . import placement
     rows = []
-    for e in (-17.5, -17.0, -16.5, -16.0, -15.5, -15.0, -14.5, -14.0, -13.5):
+    for e in exponents:
         A = 10.0 ** e
         r0 = fried_path(A, length, wavelength)
         dx = min(0.5 * r0, math.sqrt(wavelength * length) / 8)  # resolve r0 and the Fresnel scale
@@ -149,11 +152,13 @@ def main(argv=None):
     ap.add_argument("sweep", choices=["broadening", "scintillation"])
     ap.add_argument("--trials", type=int, default=4000)
     ap.add_argument("--batch", type=int, default=200)
+    ap.add_argument("--n", type=int, default=1024, help="grid size")
+    ap.add_argument("--log10-a", type=float, nargs="*", help="scintillation: ground constants (log10 A)")
     a = ap.parse_args(argv)
     if a.sweep == "broadening":
-        broadening(a.trials, a.batch)
+        broadening(a.trials, a.batch, n=a.n)
     else:
-        scintillation(a.trials, a.batch)
+        scintillation(a.trials, a.batch, n=a.n, exponents=tuple(a.log10_a) if a.log10_a else SCINT_EXPONENTS)
 
 
 if __name__ == "__main__":
