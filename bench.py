@@ -41,7 +41,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--realizations", type=int, default=64)
-    ap.add_argument("--only", choices=["all", "fwd", "fwdbwd", "ar", "plain", "copy", "fwd_as"], default="all",
+    ap.add_argument("--only", choices=["all", "fwd", "fwdbwd", "fwdbwd_rev", "ar", "plain", "copy", "fwd_as"],
+                    default="all",
                     help="run one leg (profiling runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-pairs", type=int, default=16, help="realization pairs in the oracle sample (about 20 s of CPU work)")
@@ -268,6 +269,18 @@ def main():
                              "kernels": ktab, "dominant": dom,
                              "path_effective_GBps": sum(step_bytes(path, "fwdbwd").values()) / sec / 1e9}
         del ck
+
+    if args.only in ("all", "fwdbwd_rev"):
+        # the checkpoint-free adjoint: screen-plane fields rebuilt from u_out
+        def fwdbwd_rev(i):
+            out = plan.propagate(u0, seed=w.seed, t=i, out=u_out)
+            plan.propagate_backward(out, None, seed=w.seed, t=i, u_out=out)
+
+        sec, ktab, dom = measure(torch, fwdbwd_rev, args.steps, args.warmup, binding, fams, path, "fwdbwd")
+        ck_bytes = path.realizations * path.num_screens * path.n * path.n * 8
+        result["fwd_bwd_reversible"] = {"value": ss_per_step / sec, "unit": "screen-steps/s",
+                                        "ms_per_step": 1e3 * sec, "kernels": ktab, "dominant": dom,
+                                        "checkpoint_bytes_saved": ck_bytes - 2 * path.realizations * path.n * path.n * 8}
 
     if args.only in ("all", "ar"):
         w3 = workloads.config3()

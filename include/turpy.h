@@ -88,7 +88,8 @@ typedef enum {
   TURPY_OP_SCREEN_GENERATE = 0,
   TURPY_OP_PROPAGATE = 1,
   TURPY_OP_PROPAGATE_BACKWARD = 2,
-  TURPY_OP_EVOLVE = 3
+  TURPY_OP_EVOLVE = 3,
+  TURPY_OP_PROPAGATE_BACKWARD_REVERSIBLE = 4
 } turpy_op;
 
 /* Library version string (static storage). */
@@ -166,6 +167,22 @@ turpy_status turpy_propagate_backward(turpy_plan* plan, uint64_t seed, int64_t t
                                       const void* checkpoints, int32_t src, const void* screens_or_spectra,
                                       void* grad_u_in, float* grad_screens, void* ws, size_t ws_bytes,
                                       void* stream);
+
+/* The adjoint of turpy_propagate without checkpoints.  Every step of the
+ * path is unitary, so the forward field at each screen plane is rebuilt by
+ * running the same adjoint steps on the forward output: the memory of the
+ * [R][M][N][N] checkpoints is replaced by two [R][N][N] fields in the
+ * workspace, at the price of a second chain of passes.  Results equal
+ * turpy_propagate_backward's up to FP32 rounding (the rebuilt fields carry
+ * the rounding of both chains).
+ *  u_out   complex64 [R][N][N], the output of the forward call with the same
+ *          plan, seed, t and screens; read only.  May be NULL when M = 0.
+ *  Other arguments as for turpy_propagate_backward; ws holds
+ *  turpy_workspace_size(TURPY_OP_PROPAGATE_BACKWARD_REVERSIBLE) bytes. */
+turpy_status turpy_propagate_backward_reversible(turpy_plan* plan, uint64_t seed, int64_t t,
+                                                 const void* grad_u_out, const void* u_out, int32_t src,
+                                                 const void* screens_or_spectra, void* grad_u_in,
+                                                 float* grad_screens, void* ws, size_t ws_bytes, void* stream);
 
 /* Ensemble statistics of received fields (Sec. 3.2-3.3, Eq. S25).
  *  If batch > 0: accumulate I = |u|^2 of u[batch][n][n] into

@@ -141,18 +141,29 @@ class Plan:
         return (u_out, ck) if ck is not None else u_out
 
     def propagate_backward(self, grad_out, checkpoints, seed=0, t=0, screens=None, spectra=None, want_input=True,
-                           want_screens=True):
+                           want_screens=True, u_out=None):
+        """Adjoint of propagate.  With checkpoints=None and the forward output
+        u_out, the screen-plane fields are rebuilt from u_out instead
+        (turpy_propagate_backward_reversible)."""
         shape = (self.r, self.n, self.n)
         _need(grad_out, torch.complex64, shape, "grad_out")
         src, sbuf = self._screen_src(screens, spectra)
-        if self.m > 0:
+        reversible = checkpoints is None and u_out is not None
+        if reversible:
+            _need(u_out, torch.complex64, shape, "u_out")
+        elif self.m > 0:
             _need(checkpoints, torch.complex64, (self.r, self.m, self.n, self.n), "checkpoints")
         g_in = torch.empty(shape, dtype=torch.complex64, device=self.device) if want_input else None
         g_phi = (torch.empty((self.r, self.m, self.n, self.n), dtype=torch.float32, device=self.device)
                  if want_screens else None)
-        ws, size = self.workspace(B.OP_PROPAGATE_BACKWARD)
-        B.propagate_backward(self.handle, seed, t, _ptr(grad_out), _ptr(checkpoints), src, _ptr(sbuf), _ptr(g_in),
-                             _ptr(g_phi), _ptr(ws), size, _stream())
+        if reversible:
+            ws, size = self.workspace(B.OP_PROPAGATE_BACKWARD_REVERSIBLE)
+            B.propagate_backward_reversible(self.handle, seed, t, _ptr(grad_out), _ptr(u_out), src, _ptr(sbuf),
+                                            _ptr(g_in), _ptr(g_phi), _ptr(ws), size, _stream())
+        else:
+            ws, size = self.workspace(B.OP_PROPAGATE_BACKWARD)
+            B.propagate_backward(self.handle, seed, t, _ptr(grad_out), _ptr(checkpoints), src, _ptr(sbuf),
+                                 _ptr(g_in), _ptr(g_phi), _ptr(ws), size, _stream())
         return g_in, g_phi
 
 
@@ -232,27 +243,35 @@ class ReceiverFn(torch.autograd.Function):
 class Propagate(torch.autograd.Function):
     """u_out = propagate(u_in, phi) with the hand-written adjoint as backward.
 
-    Fields are checkpointed at the screen planes only; the backward regenerates
-    synthesised screens from (seed, t).  `screens` may be None (synthesised) or a
-    float32 [R][M][N][N] tensor (materialised; receives dL/dphi)."""
+    Fields are checkpointed at the screen planes only (or, with
+    reversible=True, rebuilt from the output in the backward: no checkpoint
+    memory); the backward regenerates synthesised screens from (seed, t).
+    `screens` may be None (synthesised) or a float32 [R][M][N][N] tensor
+    (materialised; receives dL/dphi)."""
 
     @staticmethod
-    def forward(ctx, u_in, screens, plan, seed, t):
-        u_out, ck = plan.propagate(u_in.contiguous(), seed, t,
-                                   screens=screens.contiguous() if screens is not None else None, checkpoints=True)
-        ctx.plan, ctx.seed, ctx.t = plan, seed, t
+    def forward(ctx, u_in, screens, plan, seed, t, reversible=False):
+        scr = screens.contiguous() if screens is not None else None
+        if reversible:
+            u_out = plan.propagate(u_in.contiguous(), seed, t, screens=scr)
+            ctx.save_for_backward(u_out, screens)
+        else:
+            u_out, ck = plan.propagate(u_in.contiguous(), seed, t, screens=scr, checkpoints=True)
+            ctx.save_for_backward(ck, screens)
+        ctx.plan, ctx.seed, ctx.t, ctx.reversible = plan, seed, t, reversible
         ctx.shared = u_in.dim() == 2
-        ctx.save_for_backward(ck, screens)
         return u_out
 
     @staticmethod
     def backward(ctx, grad_out):
-        ck, screens = ctx.saved_tensors
+        saved, screens = ctx.saved_tensors
         plan = ctx.plan
         want_in = ctx.needs_input_grad[0]
         want_phi = ctx.needs_input_grad[1] or screens is None
-        g_in, g_phi = plan.propagate_backward(grad_out.contiguous(), ck, ctx.seed, ctx.t, screens=screens,
-                                              want_input=want_in, want_screens=want_phi and screens is not None)
+        kw = {"u_out": saved} if ctx.reversible else {}
+        g_in, g_phi = plan.propagate_backward(grad_out.contiguous(), None if ctx.reversible else saved, ctx.seed,
+                                              ctx.t, screens=screens, want_input=want_in,
+                                              want_screens=want_phi and screens is not None, **kw)
         if g_in is not None and ctx.shared:
             g_in = g_in.sum(dim=0)
-        return g_in, (g_phi if screens is not None and ctx.needs_input_grad[1] else None), None, None, None
+        return g_in, (g_phi if screens is not None and ctx.needs_input_grad[1] else None), None, None, None, None

@@ -17,12 +17,13 @@ CN2_UNIFORM, CN2_HUFNAGEL_VALLEY, CN2_TABLE = 0, 1, 2
 TF_FRESNEL, TF_ANGULAR_SPECTRUM = 0, 1
 SCREENS_SYNTH, SCREENS_MATERIALIZED, SCREENS_SPECTRA = 0, 1, 2
 ALLOW_ALIASING = 1
-OP_SCREEN_GENERATE, OP_PROPAGATE, OP_PROPAGATE_BACKWARD, OP_EVOLVE = range(4)
+OP_SCREEN_GENERATE, OP_PROPAGATE, OP_PROPAGATE_BACKWARD, OP_EVOLVE, OP_PROPAGATE_BACKWARD_REVERSIBLE = range(5)
 
 # Every symbol the header declares (checked by the CPU tests).
 EXPORTS = [
     "turpy_version", "turpy_last_error", "turpy_plan_create", "turpy_plan_destroy", "turpy_workspace_size",
-    "turpy_screen_generate", "turpy_propagate", "turpy_evolve", "turpy_propagate_backward", "turpy_stats",
+    "turpy_screen_generate", "turpy_propagate", "turpy_evolve", "turpy_propagate_backward",
+    "turpy_propagate_backward_reversible", "turpy_stats",
     "turpy_receiver_workspace_size", "turpy_receiver", "turpy_receiver_backward", "turpy_profile",
     "turpy_profile_only", "turpy_profile_read", "turpy_place_screens", "turpy_state_size",
 ]
@@ -85,6 +86,9 @@ def lib():
                                    c_size_t, c_void_p]
         L.turpy_propagate_backward.argtypes = [c_void_p, c_uint64, c_int64, c_void_p, c_void_p, c_int32, c_void_p,
                                                c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]
+        L.turpy_propagate_backward_reversible.argtypes = [c_void_p, c_uint64, c_int64, c_void_p, c_void_p, c_int32,
+                                                          c_void_p, c_void_p, c_void_p, c_void_p, c_size_t,
+                                                          c_void_p]
         L.turpy_stats.argtypes = [c_int32, c_double, c_int64, c_void_p, c_void_p, c_int64, c_int32, c_void_p,
                                   c_void_p, c_void_p]
         L.turpy_receiver_workspace_size.argtypes = [c_int32, c_int64, POINTER(c_size_t)]
@@ -171,6 +175,12 @@ def propagate_backward(handle, seed, t, gout_ptr, ckpt_ptr, src, screens_ptr, gi
                        ws_bytes, stream):
     check(lib().turpy_propagate_backward(handle, seed, t, gout_ptr, ckpt_ptr, src, screens_ptr, gin_ptr,
                                          gscreens_ptr, ws_ptr, ws_bytes, stream))
+
+
+def propagate_backward_reversible(handle, seed, t, gout_ptr, uout_ptr, src, screens_ptr, gin_ptr, gscreens_ptr,
+                                  ws_ptr, ws_bytes, stream):
+    check(lib().turpy_propagate_backward_reversible(handle, seed, t, gout_ptr, uout_ptr, src, screens_ptr, gin_ptr,
+                                                    gscreens_ptr, ws_ptr, ws_bytes, stream))
 
 
 def stats(n, dx, batch, u_ptr, moments_ptr, count, finalize, si_ptr, summary_ptr, stream):

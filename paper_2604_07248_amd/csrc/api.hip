@@ -158,6 +158,9 @@ struct turpy_plan {
   size_t off_gbuf() const { return off_src() + align_up(plane_bytes()); }
   size_t ws_forward() const { return off_gbuf(); }
   size_t ws_backward() const { return off_gbuf() + align_up(static_cast<size_t>(R) * plane_bytes()); }
+  // reversible adjoint: also the rebuilt forward field and its value at the current screen
+  size_t off_ubuf() const { return ws_backward(); }
+  size_t ws_reversible() const { return ws_backward() + 2 * align_up(static_cast<size_t>(R) * plane_bytes()); }
 };
 
 extern "C" {
@@ -367,6 +370,7 @@ turpy_status turpy_workspace_size(const turpy_plan* pl, int32_t op, size_t* byte
     case TURPY_OP_PROPAGATE: *bytes = pl->ws_forward(); return TURPY_OK;
     case TURPY_OP_PROPAGATE_BACKWARD: *bytes = pl->ws_backward(); return TURPY_OK;
     case TURPY_OP_EVOLVE: *bytes = 0; return TURPY_OK;
+    case TURPY_OP_PROPAGATE_BACKWARD_REVERSIBLE: *bytes = pl->ws_reversible(); return TURPY_OK;
     default: return fail(TURPY_E_INVALID, "workspace_size: unknown op %d", op);
   }
 }
@@ -802,6 +806,109 @@ turpy_status turpy_propagate_backward(turpy_plan* pl, uint64_t seed, int64_t t, 
     TURPY_HIP(timed(row_family(a), st, [&] { return launch_row(n, a, pl->P, st); }), "propagate_backward: last row pass");
   } else if (M == 0) {
     TURPY_HIP(timed("copy", st, [&] { return launch_copy(gout, plane, g, plane, pl->R, st); }), "propagate_backward: copy");
+  }
+  return TURPY_OK;
+}
+
+turpy_status turpy_propagate_backward_reversible(turpy_plan* pl, uint64_t seed, int64_t t, const void* grad_u_out,
+                                                 const void* u_out, int32_t src, const void* screens_or_spectra,
+                                                 void* grad_u_in, float* grad_screens, void* ws, size_t ws_bytes,
+                                                 void* stream) {
+  if (!pl || !grad_u_out) return fail(TURPY_E_INVALID, "propagate_backward_reversible: NULL argument");
+  if (turpy_status s_ = check_t(t)) return s_;
+  if (turpy_status s_ = check_device(pl)) return s_;
+  if (turpy_status s_ = check_src(pl, src, screens_or_spectra)) return s_;
+  const int n = pl->n, M = pl->M;
+  if (M == 0)  // nothing to rebuild: the plain adjoint needs no checkpoints
+    return turpy_propagate_backward(pl, seed, t, grad_u_out, nullptr, src, screens_or_spectra, grad_u_in,
+                                    grad_screens, ws, ws_bytes, stream);
+  if (!u_out) return fail(TURPY_E_INVALID, "propagate_backward_reversible: u_out is required");
+  if (!ws || ws_bytes < pl->ws_reversible())
+    return fail(TURPY_E_WORKSPACE, "propagate_backward_reversible: workspace %zu < %zu bytes", ws_bytes,
+                pl->ws_reversible());
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const Ws w = carve(pl, ws);
+  const int64_t plane = static_cast<int64_t>(n) * n;
+  const float inv_n = 1.0f / n;
+  float2* g = grad_u_in ? static_cast<float2*>(grad_u_in) : w.gbuf;
+  float2* ub = reinterpret_cast<float2*>(static_cast<char*>(ws) + pl->off_ubuf());
+  float2* wb = ub + static_cast<size_t>(pl->R) * plane;
+  const float2* gout = static_cast<const float2*>(grad_u_out);
+  const float2* uo = static_cast<const float2*>(u_out);
+  const float2* spectra = src == TURPY_SCREENS_SPECTRA ? static_cast<const float2*>(screens_or_spectra) : nullptr;
+  const bool synth = src != TURPY_SCREENS_MATERIALIZED;
+  const uint32_t tt = static_cast<uint32_t>(t);
+
+  if (src == TURPY_SCREENS_SYNTH && pl->sh_levels > 0)
+    TURPY_HIP(enqueue_sh(pl, seed, tt, w, st), "propagate_backward_reversible: sh");
+
+  // The adjoint chain applied to u_out runs the forward chain backwards (each
+  // step is unitary): right before exp(-i phi_s) of screen s it holds the
+  // forward field after screen s, which the gradient of that screen needs.
+  const float2* gc = gout;
+  const float2* uc = uo;
+  bool spectral = false;
+  if (pl->dz[M] > 0) {
+    for (int chain = 0; chain < 2; ++chain) {
+      RowArgs a = base_row(pl);  // adjoint of the final (1/N) inverse row transform
+      a.in = chain == 0 ? gout : uo;
+      a.in_stride = plane;
+      a.out = chain == 0 ? g : ub;
+      a.out_spectral = 1;
+      a.scale = inv_n;
+      TURPY_HIP(timed(row_family(a), st, [&] { return launch_row(n, a, pl->P, st); }),
+                "propagate_backward_reversible: first row pass");
+      TURPY_HIP(enqueue_col(pl, M, a.out, plane, a.out, true, -1, seed, tt, spectra, w, st),
+                "propagate_backward_reversible: column pass");
+    }
+    gc = g;
+    uc = ub;
+    spectral = true;
+  }
+  for (int s = M - 1; s >= 0; --s) {
+    if (synth) TURPY_HIP(enqueue_screen_col(pl, seed, tt, s, spectra, w, st), "propagate_backward_reversible: screen");
+    const bool out_spec = pl->dz[s] > 0;
+    for (int chain = 1; chain >= 0; --chain) {  // the field first, then the gradient that reads it
+      RowArgs a = base_row(pl);
+      a.in = chain == 0 ? gc : uc;
+      a.in_stride = plane;
+      a.out = chain == 0 ? g : ub;
+      a.in_spectral = spectral ? 1 : 0;
+      a.pre = spectral ? pl->d_row + static_cast<size_t>(s + 1) * n : nullptr;
+      a.conj_tables = 1;
+      // the field's own continuation past screen 0 is never read
+      const bool cont = out_spec && (chain == 0 || s > 0);
+      a.out_spectral = cont ? 1 : 0;
+      a.scale = cont ? inv_n : 1.0f;
+      screen_fields(pl, src, screens_or_spectra, w, s, &a);
+      a.backward = 1;
+      a.ckpt_single = 1;
+      if (chain == 1) {
+        a.ckpt_out = wb;
+      } else {
+        a.ckpt_in = wb;
+        a.grad_screens = grad_screens;
+      }
+      TURPY_HIP(timed(row_family(a), st, [&] { return launch_row(n, a, pl->P, st); }),
+                "propagate_backward_reversible: row pass");
+      if (cont)
+        TURPY_HIP(enqueue_col(pl, s, a.out, plane, a.out, true, -1, seed, tt, spectra, w, st),
+                  "propagate_backward_reversible: column pass");
+    }
+    gc = g;
+    uc = ub;
+    spectral = out_spec;
+  }
+  if (spectral) {
+    RowArgs a = base_row(pl);  // adjoint of the source row transform: conj h_0, unnormalised inverse
+    a.in = g;
+    a.in_stride = plane;
+    a.out = g;
+    a.in_spectral = 1;
+    a.pre = pl->d_row;
+    a.conj_tables = 1;
+    TURPY_HIP(timed(row_family(a), st, [&] { return launch_row(n, a, pl->P, st); }),
+              "propagate_backward_reversible: last row pass");
   }
   return TURPY_OK;
 }

@@ -135,6 +135,7 @@ void row_pass_kernel(RowArgs a) {
     const float* ph = b ? pb : pa;
     if constexpr (SCREEN != ROW_NO_SCREEN) {
       const size_t ck = (static_cast<size_t>(r) * a.M + a.screen) * plane + row_off;
+      const size_t cw = a.ckpt_single ? static_cast<size_t>(r) * plane + row_off : ck;
       if constexpr (!BWD) {
 #pragma unroll
         for (int m = 0; m < kE; ++m) {
@@ -144,13 +145,17 @@ void row_pass_kernel(RowArgs a) {
         }
         if (a.ckpt_out) {
 #pragma unroll
-          for (int m = 0; m < kE; ++m) a.ckpt_out[ck + t + T * m] = x[m];
+          for (int m = 0; m < kE; ++m) a.ckpt_out[cw + t + T * m] = x[m];
         }
       } else {
+        if (a.ckpt_out) {  // the forward field at this screen, rebuilt by the adjoint chain
+#pragma unroll
+          for (int m = 0; m < kE; ++m) a.ckpt_out[cw + t + T * m] = x[m];
+        }
         if (a.grad_screens) {
 #pragma unroll
           for (int m = 0; m < kE; ++m) {
-            const float2 w = a.ckpt_in[ck + t + T * m];
+            const float2 w = a.ckpt_in[cw + t + T * m];
             a.grad_screens[ck + t + T * m] = w.x * x[m].y - w.y * x[m].x;  // Im(conj(W) g)
           }
         }
@@ -302,6 +307,7 @@ void row_pair_kernel(RowArgs a) {
   // the pointwise step of Eq. 1 (or its adjoint) and the forward transform
   auto finish = [&]() {
     const size_t ck = (static_cast<size_t>(r) * a.M + a.screen) * plane + row_off;
+    const size_t cw = a.ckpt_single ? static_cast<size_t>(r) * plane + row_off : ck;
     if constexpr (!BWD) {
 #pragma unroll
       for (int m = 0; m < kE; ++m) {
@@ -311,13 +317,17 @@ void row_pair_kernel(RowArgs a) {
       }
       if (a.ckpt_out && writes) {
 #pragma unroll
-        for (int m = 0; m < kE; ++m) a.ckpt_out[ck + t + T * m] = x[m];
+        for (int m = 0; m < kE; ++m) a.ckpt_out[cw + t + T * m] = x[m];
       }
     } else {
+      if (a.ckpt_out && writes) {  // the forward field at this screen, rebuilt by the adjoint chain
+#pragma unroll
+        for (int m = 0; m < kE; ++m) a.ckpt_out[cw + t + T * m] = x[m];
+      }
       if (a.grad_screens && writes) {
 #pragma unroll
         for (int m = 0; m < kE; ++m) {
-          const float2 w = a.ckpt_in[ck + t + T * m];
+          const float2 w = a.ckpt_in[cw + t + T * m];
           a.grad_screens[ck + t + T * m] = w.x * x[m].y - w.y * x[m].x;  // Im(conj(W) g)
         }
       }

@@ -38,8 +38,9 @@ struct RowArgs {
   float sh_scale;           // to revolutions: 1 (synthesised) or 1/(2 pi) (AR state, radians)
   const float2* sh_phasor;  // [3][N] exp(2 pi i (i - N/2) / (N 3^p))
   int backward;             // 0: W = U e^{i phi}; 1: adjoint (read checkpoint, write dL/dphi, e^{-i phi})
-  float2* ckpt_out;         // forward: [R][M][N][N] field after the screen, or NULL
+  float2* ckpt_out;         // [R][M][N][N] field after the screen, or NULL (backward: as rebuilt)
   const float2* ckpt_in;    // backward: same layout
+  int ckpt_single;          // 1: ckpt_out / ckpt_in hold this screen only, [R][N][N]
   float* grad_screens;      // backward: [R][M][N][N] dL/dphi, or NULL
   float* phase_out;         // [R][M][N][N] radians: write the screens themselves, or NULL
 };

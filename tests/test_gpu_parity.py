@@ -347,3 +347,63 @@ def test_library_loaded_by_host_call_before_gpu_work():
     r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=240)
     say(r.stdout.strip(), r.stderr.strip()[-500:])
     assert r.returncode == 0 and r.stdout.startswith("ok")
+
+
+@pytest.mark.parametrize("case", ["synth", "materialized", "spectra", "angular_edges", "first_zero", "long"])
+def test_reversible_backward(api, case):
+    """The checkpoint-free adjoint rebuilds the screen-plane fields from the
+    forward output (every step is unitary); its gradients equal the
+    checkpointed adjoint's up to FP32 rounding and the oracle's to 1e-4."""
+    r = 3
+    path = sized_path(256, realizations=r, m=3, sh=3 if case in ("synth", "spectra") else 0)
+    if case == "angular_edges":
+        path = path.with_(tf_kind=1, dz=(0.0,) + path.dz[1:-1] + (0.0,))
+    elif case == "first_zero":
+        path = path.with_(dz=(0.0,) + path.dz[1:])
+    elif case == "long":
+        path = sized_path(512, realizations=4, m=8)
+        r = 4
+    say(f"[reversible] {case} n={path.n} M={path.num_screens}")
+    plan = api.Plan(path)
+    u0 = gaussian(path).astype(np.complex64)
+    rng = np.random.default_rng(6)
+    g = (rng.standard_normal((r, path.n, path.n)) + 1j * rng.standard_normal((r, path.n, path.n))).astype(np.complex64)
+    kw = {}
+    if case == "materialized":
+        kw["screens"] = plan.screens(seed=17)
+    elif case == "spectra":
+        spec = plan.init_spectra(seed=17)
+        plan.evolve(spec, seed=17, t=1, alpha=0.95, shift_x=0.4, shift_y=0.2)
+        kw["spectra"] = spec
+    out, ck = plan.propagate(c64(u0), seed=17, checkpoints=True, **kw)
+    a_in, a_phi = plan.propagate_backward(c64(g), ck, seed=17, **kw)
+    b_in, b_phi = plan.propagate_backward(c64(g), None, seed=17, u_out=out, **kw)
+    d_in = rel_l2(b_in.cpu().numpy(), a_in.cpu().numpy())
+    d_phi = rel_l2(b_phi.cpu().numpy(), a_phi.cpu().numpy())
+    if case == "spectra":
+        phi = oev.screens_from_state(oev.evolve(oev.initial_spectra(path, 17), path, 17, 1, 0.95, 0.4, 0.2),
+                                     oev.evolve_sh(oev.initial_sh(path, 17), path, 17, 1, 0.95, 0.4, 0.2), path, r)
+    elif case == "materialized":
+        phi = kw["screens"].cpu().numpy().astype(np.float64)
+    else:
+        phi = oracle_screens(path, 17, range(r))
+    ref_out, ref_ck = opr.propagate(u0.astype(np.complex128), path, phi)
+    ref_in, ref_phi = opr.propagate_adjoint(g.astype(np.complex128), path, phi, ref_ck)
+    e_in, e_phi = rel_l2(b_in.cpu().numpy(), ref_in), rel_l2(b_phi.cpu().numpy(), ref_phi)
+    say(f"[reversible] {case}: vs checkpointed {d_in:.2e} / {d_phi:.2e}; vs oracle {e_in:.2e} / {e_phi:.2e}")
+    assert d_in < 2e-5 and d_phi < 2e-5
+    assert e_in < TOL and e_phi < TOL
+
+
+def test_reversible_autograd_matches_checkpointed(api):
+    path = sized_path(128, realizations=2, m=3)
+    plan = api.Plan(path)
+    u0 = c64(gaussian(path)).requires_grad_(True)
+    phi = plan.screens(seed=5).requires_grad_(True)
+    grads = []
+    for reversible in (False, True):
+        out = api.Propagate.apply(u0, phi, plan, 5, 0, reversible)
+        loss = (out.abs() ** 2 * torch.linspace(0, 1, path.n, device="cuda")[None, None, :]).sum()
+        gu, gp = torch.autograd.grad(loss, (u0, phi))
+        grads.append((gu.cpu().numpy(), gp.cpu().numpy()))
+    assert rel_l2(grads[1][0], grads[0][0]) < 2e-5 and rel_l2(grads[1][1], grads[0][1]) < 2e-5
