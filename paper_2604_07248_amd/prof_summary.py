@@ -4,6 +4,8 @@
         Markdown table of a `--kernel-trace --stats --output-format csv` run.
     python -m paper_2604_07248_amd.prof_summary pmc DIR [DIR ...]
         Per-kernel average of every counter of `--pmc ... --output-format csv` runs.
+    python -m paper_2604_07248_amd.prof_summary report --bench BENCH_JSON [--out profiles]
+        All committed summaries of the standard profiling runs under gpurun_out/.
     python -m paper_2604_07248_amd.prof_summary traffic --fetch DIR --write DIR
             --copy-fetch DIR --copy-write DIR --copy-bytes B --leg NAME
         HBM bytes per launch of each kernel family: FETCH_SIZE and WRITE_SIZE
@@ -161,6 +163,94 @@ def load_traffic(profiles_dir, leg):
     return {}
 
 
+PRE = "cd /tmp && export TMPDIR=/tmp && R=<repository root>"
+
+
+def _ev(fams, tab):
+    return ", ".join(f"{f} {tab[f]['avg_us']:.1f} us" for f in fams if f in tab)
+
+
+def report(out_dir, bench_json, root="gpurun_out"):
+    """Write the committed summaries of the standard profiling runs (the
+    commands are printed in each file) into out_dir."""
+    with open(bench_json) as fh:
+        b = json.load(fh)
+    j = lambda *a: os.path.join(root, *a)
+    # forward kernel trace
+    rows = stats_table(j("prof_fwd"))
+    fwd_row = next(r for r in rows[2:] if "| row_fwd |" in r)
+    d = b["roofline"]
+    lines = ["# Kernel trace: forward headline workload (N=1024, R=64, M=8, fresh screens)", "",
+             "Command (one MI355X; the profiler writes its temporary files under /tmp):", "", f"    {PRE}",
+             "    rocprofv3 --kernel-trace --stats --output-format csv -d $R/gpurun_out/prof_fwd -o fwd -- \\",
+             "        python $R/bench.py --only fwd --steps 10 --warmup 2", "",
+             "Summary: `python -m paper_2604_07248_amd.prof_summary stats gpurun_out/prof_fwd`.  The run covers",
+             "22 forward steps: 2 warm-up, 10 with every family bracketed by events, 10 timed.  Durations in",
+             "microseconds.", ""] + rows + [
+             "", "HIP-event averages measured inside `bench.py` (default run: 5 warm-up, 50 profiled and 50 timed "
+             "steps): " + _ev(["row_fwd", "col", "synth", "row_plain", "stats"], b["kernels"]) + ".", "",
+             f"Roofline line of that run: dominant family `{d['kernel']}`, {d['bytes_per_launch']:.0f} algorithmic "
+             f"bytes per launch over {d['avg_us']:.1f} us = {d['achieved']:.0f} GB/s = {100 * d['frac']:.1f} % of "
+             f"8 TB/s; the trace's average for that kernel is {fwd_row.split('|')[5].strip()} us."]
+    _write(out_dir, "fwd_h1_n1024_r64_m8_kernel_stats.md", lines)
+    # forward + adjoint kernel trace
+    lines = ["# Kernel trace: forward + adjoint, headline workload (N=1024, R=64, M=8, checkpoints)", "",
+             "Command:", "", f"    {PRE}",
+             "    rocprofv3 --kernel-trace --stats --output-format csv -d $R/gpurun_out/prof_fwdbwd -o fwdbwd -- \\",
+             "        python $R/bench.py --only fwdbwd --steps 5 --warmup 2", "",
+             "Summary: `python -m paper_2604_07248_amd.prof_summary stats gpurun_out/prof_fwdbwd`.", ""]
+    lines += stats_table(j("prof_fwdbwd")) + [
+        "", "HIP-event averages inside `bench.py` (default run): " +
+        _ev(["row_fwd", "row_bwd", "col", "synth", "row_plain"], b["fwd_bwd"]["kernels"]) + "."]
+    _write(out_dir, "fwdbwd_h1_n1024_r64_m8_kernel_stats.md", lines)
+    # HBM traffic
+    lines = ["# HBM traffic per launch: forward headline workload (N=1024, R=64, M=8)", "",
+             "Commands (one counter per run; the copy runs calibrate the counters with the library's copy",
+             "kernel moving 512 MiB each way per launch):", "", f"    {PRE}"]
+    for c in ("FETCH_SIZE", "WRITE_SIZE"):
+        for leg in ("fwd", "copy"):
+            lines.append(f"    timeout -s KILL 120 rocprofv3 --pmc {c} --output-format csv "
+                         f"-d $R/gpurun_out/pmc_{c}_{leg} -o p -- \\")
+            lines.append(f"        python $R/bench.py --only {leg} --steps 3 --warmup 1")
+    lines += ["", "Summary: `python -m paper_2604_07248_amd.prof_summary traffic --fetch gpurun_out/pmc_FETCH_SIZE_fwd "
+              "--write gpurun_out/pmc_WRITE_SIZE_fwd --copy-fetch gpurun_out/pmc_FETCH_SIZE_copy --copy-write "
+              "gpurun_out/pmc_WRITE_SIZE_copy --copy-bytes 536870912 --leg fwd`.", "",
+              "Averages over every launch of a family (the column family includes the one-plane pass 0, the",
+              "row-plain family the one-plane source transform).  On gfx950 almost every read is a 128-byte",
+              "request, which the FETCH_SIZE expression counts as 64 bytes (TCC_BUBBLE stays 0): the copy",
+              "calibration gives 2.0 KiB per FETCH_SIZE unit and 1.0 KiB per WRITE_SIZE unit.", ""]
+    lines += traffic(j("pmc_FETCH_SIZE_fwd"), j("pmc_WRITE_SIZE_fwd"), j("pmc_FETCH_SIZE_copy"),
+                     j("pmc_WRITE_SIZE_copy"), 536870912, "fwd")
+    _write(out_dir, "fwd_h1_n1024_r64_m8_hbm_traffic.md", lines)
+    # SQ counters
+    sq = pmc_by_kernel(j("pmc_sq_fwd"))
+    lines = ["# Wave and VALU counters: forward headline workload (N=1024, R=64, M=8)", "", "Command:", "",
+             f"    {PRE}",
+             "    timeout -s KILL 120 rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_BUSY_CYCLES \\",
+             "        SQ_WAVE_CYCLES SQ_INSTS_LDS GRBM_GUI_ACTIVE --output-format csv -d $R/gpurun_out/pmc_sq_fwd "
+             "-o p -- \\", "        python $R/bench.py --only fwd --steps 3 --warmup 1", "",
+             "Summary: `python -m paper_2604_07248_amd.prof_summary pmc gpurun_out/pmc_sq_fwd` (per-dispatch",
+             "averages).  VALU busy = SQ_INSTS_VALU x 4 cycles (a wave64 FP32 instruction on a 16-lane SIMD) /",
+             "(1024 SIMDs x GRBM_GUI_ACTIVE / 8 XCDs).", "",
+             "| family | waves | VALU instr per wave | LDS instr per wave | kernel cycles | VALU busy |",
+             "|---|---:|---:|---:|---:|---:|"]
+    for name, cs in sorted(sq.items(), key=lambda kv: family(kv[0]) or "z"):
+        fam = family(name)
+        if not fam:
+            continue
+        waves, valu, lds = cs["SQ_WAVES"][0], cs["SQ_INSTS_VALU"][0], cs["SQ_INSTS_LDS"][0]
+        cyc = cs["GRBM_GUI_ACTIVE"][0] / 8
+        lines.append(f"| {fam} | {waves:.0f} | {valu / waves:.0f} | {lds / waves:.0f} | {cyc:.0f} | "
+                     f"{100 * valu * 4 / (1024 * cyc):.0f} % |")
+    lines += ["", "Full table:", ""] + pmc_table([j("pmc_sq_fwd")])
+    _write(out_dir, "fwd_h1_n1024_r64_m8_sq_counters.md", lines)
+
+
+def _write(out_dir, name, lines):
+    with open(os.path.join(out_dir, name), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -173,7 +263,14 @@ def main(argv=None):
         t.add_argument("--" + k.replace("_", "-"), required=True)
     t.add_argument("--copy-bytes", type=float, required=True)
     t.add_argument("--leg", required=True)
+    r = sub.add_parser("report", help="write the committed summaries of the standard runs")
+    r.add_argument("--bench", required=True, help="bench.py JSON of the same sources")
+    r.add_argument("--out", default="profiles")
+    r.add_argument("--root", default="gpurun_out")
     a = ap.parse_args(argv)
+    if a.cmd == "report":
+        report(a.out, a.bench, a.root)
+        return
     if a.cmd == "stats":
         lines = stats_table(a.dir)
     elif a.cmd == "pmc":
