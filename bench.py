@@ -41,7 +41,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--realizations", type=int, default=64)
-    ap.add_argument("--only", choices=["all", "fwd", "fwdbwd", "fwdbwd_rev", "ar", "plain", "copy", "fwd_as"],
+    ap.add_argument("--only", choices=["all", "fwd", "fwdbwd", "fwdbwd_rev", "ar", "plain", "copy", "fwd_as",
+                                       "uneven"],
                     default="all",
                     help="run one leg (profiling runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -305,6 +306,44 @@ def main():
                         "path_effective_GBps": sum(step_bytes(p3, "ar").values()) / sec / 1e9}
         plan3.close()
         del spec
+
+    if args.only in ("all", "uneven"):
+        # serving mix: the first 64 instances of the uneven workload (N = 256..2048,
+        # 5-20 screens, three subharmonic levels, one realization each) in one
+        # batch call, against the same instances run one plan after another
+        inst = [x.path for x in workloads.uneven_batch()[:64]]
+        batch = api.Batch(inst)
+        srcs = [torch.from_numpy(workloads.gaussian_source(p.n, p.dx, p.n * p.dx / 8).astype(np.complex64))[None]
+                for p in inst]
+        ub = batch.pack(srcs)
+        uo = torch.empty_like(ub)
+        plans = [api.Plan(p) for p in inst]
+        srcs = [x.to(dev) for x in srcs]
+        outs = batch.unpack(uo)
+        ss_u = sum(p.num_screens for p in inst)
+
+        def one_call(i):
+            batch.propagate(ub, seed=5, t=i, out=uo)
+
+        def one_by_one(i):
+            for k, pl in enumerate(plans):
+                pl.propagate(srcs[k], seed=api.Batch.instance_seed(5, k), t=i, out=outs[k])
+
+        res = {}
+        for name, fn in (("batch", one_call), ("sequential", one_by_one)):
+            run_steps(torch, fn, 0, 2)
+            k = max(3, args.steps // 10)
+            t0 = time.perf_counter()
+            run_steps(torch, fn, 2, k)
+            res[name] = (time.perf_counter() - t0) / k
+        result["uneven_batch"] = {
+            "value": ss_u / res["batch"], "unit": "screen-steps/s", "instances": len(inst),
+            "instances_per_s": len(inst) / res["batch"], "ms_per_call": 1e3 * res["batch"],
+            "sequential_ms": 1e3 * res["sequential"], "speedup_vs_sequential": res["sequential"] / res["batch"],
+            "workload": "first 64 serving-mix instances (N 256-2048, 5-20 screens, 3 subharmonic levels, R=1)"}
+        for pl in plans:
+            pl.close()
+        batch.close()
 
     if args.only in ("all", "plain"):
         H = fresnel_tables(torch, np, path, dev)

@@ -219,6 +219,42 @@ turpy_status turpy_receiver_backward(int32_t n, double dx, double aperture_diame
                                      float* grad_theta2, void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Uneven batches: many path instances, each with its own grid size, screen
+ * count, wavelength and distances, propagated by one call on the caller's
+ * stream.  Instances are spread over a few internal streams of default
+ * priority (longest processing time first, cost R N^2 (M + 1)), forked from
+ * and joined back to the caller's stream with events; nothing is allocated and
+ * no memset is issued, so the calls can be captured in a HIP graph.  Screens
+ * are synthesised (Eq. S16, Eq. 2-3); instance i draws its noise with the key
+ * seed + i * 0x9E3779B97F4A7C15 (mod 2^64), otherwise exactly as
+ * turpy_propagate with its own plan.  Not thread-safe (one call at a time per
+ * batch).
+ * ------------------------------------------------------------------------- */
+typedef struct turpy_batch turpy_batch;
+
+/* paths [num_paths] as for turpy_plan_create (the dz / cn2dz arrays are read
+ * here only); field_offsets [num_paths]: element (complex64) offset of
+ * instance i's fields [R_i][N_i][N_i] in the packed field buffers; the fields
+ * of different instances must not overlap (TURPY_E_INVALID).  A path that
+ * fails turpy_plan_create's validation fails the batch with its status. */
+turpy_status turpy_batch_create(turpy_batch** out, const turpy_path* paths, const int64_t* field_offsets,
+                                int32_t num_paths, uint32_t flags);
+turpy_status turpy_batch_destroy(turpy_batch* batch);
+/* op: TURPY_OP_PROPAGATE or TURPY_OP_PROPAGATE_BACKWARD. */
+turpy_status turpy_batch_workspace_size(const turpy_batch* batch, int32_t op, size_t* bytes);
+/* u_in / u_out: packed fields (instance i at field_offsets[i], one source
+ * plane per realization; u_in == u_out allowed).  checkpoints (NULL = none):
+ * packed instance after instance, [R_i][M_i][N_i][N_i] each, in order i. */
+turpy_status turpy_batch_propagate(turpy_batch* batch, uint64_t seed, int64_t t, const void* u_in, void* u_out,
+                                   void* checkpoints, void* ws, size_t ws_bytes, void* stream);
+/* The adjoint of turpy_batch_propagate: grad_u_out / grad_u_in packed like
+ * the fields, checkpoints and grad_screens (float) packed like the
+ * checkpoints; grad_u_in or grad_screens may be NULL. */
+turpy_status turpy_batch_propagate_backward(turpy_batch* batch, uint64_t seed, int64_t t, const void* grad_u_out,
+                                            const void* checkpoints, void* grad_u_in, float* grad_screens,
+                                            void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Screen placement (Sec. 2.4; App. C Eq. S18-S21).  Host arithmetic only: no
  * device memory, no stream and no GPU are involved.
  * ------------------------------------------------------------------------- */

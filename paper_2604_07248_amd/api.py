@@ -167,6 +167,85 @@ class Plan:
         return g_in, g_phi
 
 
+SEED_STEP = 0x9E3779B97F4A7C15
+
+
+class Batch:
+    """An uneven batch of path instances (turpy_batch_*): every instance has
+    its own grid size, screen count and distances; their fields live in one
+    packed complex64 buffer (instance i at offsets[i], [R_i][N_i][N_i]).
+    Instance i draws the noise of a single plan keyed (seed + i * SEED_STEP)
+    mod 2^64."""
+
+    def __init__(self, paths, flags=0, device=None):
+        self.paths = list(paths)
+        sizes = [p.realizations * p.n * p.n for p in self.paths]
+        self.offsets = [0]
+        for sz in sizes[:-1]:
+            self.offsets.append(self.offsets[-1] + sz)
+        self.total = sum(sizes)
+        ck = [p.realizations * len(p.cn2dz) * p.n * p.n for p in self.paths]
+        self.ck_offsets = [0]
+        for c in ck[:-1]:
+            self.ck_offsets.append(self.ck_offsets[-1] + c)
+        self.ck_total = sum(ck)
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        with torch.cuda.device(self.device):
+            self.handle = B.batch_create(self.paths, self.offsets, flags)
+        self._ws = {}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            B.batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def instance_seed(seed, i):
+        return (seed + i * SEED_STEP) % (1 << 64)
+
+    def pack(self, fields):
+        """Packed buffer from per-instance complex64 tensors [R_i][N_i][N_i]."""
+        return torch.cat([f.reshape(-1) for f in fields]).to(self.device)
+
+    def unpack(self, flat):
+        """Per-instance views [R_i][N_i][N_i] of a packed buffer."""
+        return [flat[o:o + p.realizations * p.n * p.n].view(p.realizations, p.n, p.n)
+                for o, p in zip(self.offsets, self.paths)]
+
+    def _workspace(self, op):
+        size = B.batch_workspace_size(self.handle, op)
+        buf = self._ws.get(op)
+        if buf is None or buf.numel() < size:
+            buf = torch.empty(max(size, 256), dtype=torch.uint8, device=self.device)
+            self._ws[op] = buf
+        return buf, size
+
+    def propagate(self, u_in, seed=0, t=0, checkpoints=False, out=None):
+        _need(u_in, torch.complex64, (self.total,), "u_in")
+        out = torch.empty_like(u_in) if out is None else out
+        _need(out, torch.complex64, (self.total,), "out")
+        ck = torch.empty(self.ck_total, dtype=torch.complex64, device=self.device) if checkpoints else None
+        ws, size = self._workspace(B.OP_PROPAGATE)
+        B.batch_propagate(self.handle, seed, t, _ptr(u_in), _ptr(out), _ptr(ck), _ptr(ws), size, _stream())
+        return (out, ck) if checkpoints else out
+
+    def propagate_backward(self, grad_out, checkpoints, seed=0, t=0):
+        _need(grad_out, torch.complex64, (self.total,), "grad_out")
+        _need(checkpoints, torch.complex64, (self.ck_total,), "checkpoints")
+        g_in = torch.empty_like(grad_out)
+        g_phi = torch.empty(self.ck_total, dtype=torch.float32, device=self.device)
+        ws, size = self._workspace(B.OP_PROPAGATE_BACKWARD)
+        B.batch_propagate_backward(self.handle, seed, t, _ptr(grad_out), _ptr(checkpoints), _ptr(g_in), _ptr(g_phi),
+                                   _ptr(ws), size, _stream())
+        return g_in, g_phi
+
+
 class Moments:
     """Running ensemble moments of |U|^2 on the GPU (turpy_stats)."""
 

@@ -1,0 +1,227 @@
+// Uneven batches: many path instances (grid sizes, screen counts,
+// wavelengths and distances of their own) propagated by one call.  Each
+// instance has its own plan; instances are spread over a few internal
+// streams (longest processing time first, cost R N^2 (M + 1)), forked from
+// and joined back to the caller's stream with events, each stream with its own
+// slice of the workspace.  Built on the public entry points only.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <numeric>
+#include <vector>
+
+#include "report.hpp"
+#include "turpy.h"
+
+namespace {
+
+constexpr int kLanes = 4;  // internal streams (the device's hardware queues)
+constexpr size_t kAlign = 256;
+constexpr uint64_t kSeedStep = 0x9E3779B97F4A7C15ull;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+}  // namespace
+
+struct turpy_batch {
+  int device = 0;
+  std::vector<turpy_plan*> plans;
+  std::vector<turpy_path> paths;
+  std::vector<int64_t> offsets;      // field offsets (complex elements)
+  std::vector<int64_t> ck_offsets;   // checkpoint offsets (complex elements)
+  std::vector<std::vector<int>> lanes;
+  std::vector<size_t> lane_ws[2];    // workspace bytes per lane: forward, backward
+  std::vector<hipStream_t> streams;
+  std::vector<hipEvent_t> done;
+  hipEvent_t fork = nullptr;
+};
+
+namespace {
+
+turpy_status fail_hip(hipError_t e, const char* where) {
+  return turpy::report(TURPY_E_HIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+size_t total_ws(const turpy_batch* b, int which) {
+  size_t s = 0;
+  for (size_t v : b->lane_ws[which]) s += align_up(v);
+  return s;
+}
+
+// Fork the lanes from the caller's stream, run `fn(instance, lane stream,
+// lane workspace)` for every instance, join the lanes back.
+template <class Fn>
+turpy_status run(turpy_batch* b, void* ws, int which, void* stream, Fn&& fn) {
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = hipEventRecord(b->fork, st);
+  if (e != hipSuccess) return fail_hip(e, "batch: fork");
+  char* base = static_cast<char*>(ws);
+  turpy_status status = TURPY_OK;
+  for (size_t l = 0; l < b->lanes.size(); ++l) {
+    e = hipStreamWaitEvent(b->streams[l], b->fork, 0);
+    if (e != hipSuccess) return fail_hip(e, "batch: fork");
+    for (int i : b->lanes[l]) {
+      status = fn(i, b->streams[l], base, b->lane_ws[which][l]);
+      if (status != TURPY_OK) break;
+    }
+    e = hipEventRecord(b->done[l], b->streams[l]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, b->done[l], 0);
+    if (e != hipSuccess) return fail_hip(e, "batch: join");
+    if (status != TURPY_OK) return status;
+    base += align_up(b->lane_ws[which][l]);
+  }
+  return TURPY_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+turpy_status turpy_batch_destroy(turpy_batch* b) {
+  if (!b) return TURPY_OK;
+  for (hipStream_t s : b->streams) (void)hipStreamSynchronize(s);
+  for (turpy_plan* p : b->plans) turpy_plan_destroy(p);
+  for (hipEvent_t e : b->done) (void)hipEventDestroy(e);
+  if (b->fork) (void)hipEventDestroy(b->fork);
+  for (hipStream_t s : b->streams) (void)hipStreamDestroy(s);
+  delete b;
+  return TURPY_OK;
+}
+
+turpy_status turpy_batch_create(turpy_batch** out, const turpy_path* paths, const int64_t* field_offsets,
+                                int32_t num_paths, uint32_t flags) {
+  if (!out || !paths || !field_offsets || num_paths < 1)
+    return turpy::report(TURPY_E_INVALID, "batch_create: NULL argument or num_paths < 1");
+  *out = nullptr;
+  turpy_batch* b = new turpy_batch;
+  if (hipGetDevice(&b->device) != hipSuccess) {
+    delete b;
+    return turpy::report(TURPY_E_HIP, "batch_create: no current device");
+  }
+  int64_t ck = 0;
+  for (int32_t i = 0; i < num_paths; ++i) {
+    if (field_offsets[i] < 0) {
+      turpy_batch_destroy(b);
+      return turpy::report(TURPY_E_INVALID, "batch_create: field_offsets[%d] < 0", i);
+    }
+    turpy_plan* p = nullptr;
+    if (turpy_status s = turpy_plan_create(&p, &paths[i], flags)) {
+      turpy_batch_destroy(b);
+      return s;  // the message names the path's problem
+    }
+    b->plans.push_back(p);
+    turpy_path q = paths[i];
+    q.dz = nullptr;  // the caller's arrays are not kept
+    q.cn2dz = nullptr;
+    b->paths.push_back(q);
+    b->offsets.push_back(field_offsets[i]);
+    b->ck_offsets.push_back(ck);
+    ck += paths[i].realizations * paths[i].num_screens * static_cast<int64_t>(paths[i].n) * paths[i].n;
+  }
+  // fields of different instances must not overlap
+  std::vector<int> order(num_paths);
+  std::iota(order.begin(), order.end(), 0);
+  std::sort(order.begin(), order.end(), [&](int a, int c) { return b->offsets[a] < b->offsets[c]; });
+  for (size_t k = 1; k < order.size(); ++k) {
+    const turpy_path& p = b->paths[order[k - 1]];
+    const int64_t end = b->offsets[order[k - 1]] + p.realizations * static_cast<int64_t>(p.n) * p.n;
+    if (end > b->offsets[order[k]]) {
+      turpy_batch_destroy(b);
+      return turpy::report(TURPY_E_INVALID, "batch_create: fields of instances %d and %d overlap",
+                           order[k - 1], order[k]);
+    }
+  }
+  // longest processing time first over the lanes
+  const int lanes = std::min<int>(kLanes, num_paths);
+  std::vector<double> cost(num_paths), load(lanes, 0.0);
+  for (int i = 0; i < num_paths; ++i)
+    cost[i] = static_cast<double>(b->paths[i].realizations) * b->paths[i].n * b->paths[i].n *
+              (b->paths[i].num_screens + 1);
+  std::sort(order.begin(), order.end(),
+            [&](int a, int c) { return cost[a] > cost[c] || (cost[a] == cost[c] && a < c); });
+  b->lanes.assign(lanes, {});
+  for (int i : order) {
+    const int l = static_cast<int>(std::min_element(load.begin(), load.end()) - load.begin());
+    b->lanes[l].push_back(i);
+    load[l] += cost[i];
+  }
+  for (int w = 0; w < 2; ++w) b->lane_ws[w].assign(lanes, 0);
+  for (int l = 0; l < lanes; ++l)
+    for (int i : b->lanes[l]) {
+      size_t f = 0, g = 0;
+      turpy_workspace_size(b->plans[i], TURPY_OP_PROPAGATE, &f);
+      turpy_workspace_size(b->plans[i], TURPY_OP_PROPAGATE_BACKWARD, &g);
+      b->lane_ws[0][l] = std::max(b->lane_ws[0][l], f);
+      b->lane_ws[1][l] = std::max(b->lane_ws[1][l], g);
+    }
+  hipError_t e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+  for (int l = 0; e == hipSuccess && l < lanes; ++l) {
+    hipStream_t s = nullptr;
+    e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e == hipSuccess) b->streams.push_back(s);
+    hipEvent_t ev = nullptr;
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e == hipSuccess) b->done.push_back(ev);
+  }
+  if (e != hipSuccess) {
+    turpy_batch_destroy(b);
+    return fail_hip(e, "batch_create: streams and events");
+  }
+  *out = b;
+  return TURPY_OK;
+}
+
+turpy_status turpy_batch_workspace_size(const turpy_batch* b, int32_t op, size_t* bytes) {
+  if (!b || !bytes) return turpy::report(TURPY_E_INVALID, "batch_workspace_size: NULL argument");
+  if (op == TURPY_OP_PROPAGATE) {
+    *bytes = total_ws(b, 0);
+  } else if (op == TURPY_OP_PROPAGATE_BACKWARD) {
+    *bytes = total_ws(b, 1);
+  } else {
+    return turpy::report(TURPY_E_INVALID, "batch_workspace_size: op %d is not available for batches", op);
+  }
+  return TURPY_OK;
+}
+
+turpy_status turpy_batch_propagate(turpy_batch* b, uint64_t seed, int64_t t, const void* u_in, void* u_out,
+                                   void* checkpoints, void* ws, size_t ws_bytes, void* stream) {
+  if (!b || !u_in || !u_out) return turpy::report(TURPY_E_INVALID, "batch_propagate: NULL argument");
+  if (t < 0 || t > 0xFFFFFFFFll) return turpy::report(TURPY_E_INVALID, "batch_propagate: t out of range");
+  if (!ws || ws_bytes < total_ws(b, 0))
+    return turpy::report(TURPY_E_WORKSPACE, "batch_propagate: workspace %zu < %zu bytes", ws_bytes,
+                         total_ws(b, 0));
+  const auto* in = static_cast<const char*>(u_in);
+  auto* out = static_cast<char*>(u_out);
+  auto* ck = static_cast<char*>(checkpoints);
+  return run(b, ws, 0, stream, [&](int i, hipStream_t st, char* lws, size_t lbytes) {
+    const int64_t plane = static_cast<int64_t>(b->paths[i].n) * b->paths[i].n;
+    const size_t off = static_cast<size_t>(b->offsets[i]) * 8;
+    return turpy_propagate(b->plans[i], seed + kSeedStep * static_cast<uint64_t>(i), t, in + off, plane,
+                           TURPY_SCREENS_SYNTH, nullptr, out + off,
+                           ck ? ck + static_cast<size_t>(b->ck_offsets[i]) * 8 : nullptr, lws, lbytes, st);
+  });
+}
+
+turpy_status turpy_batch_propagate_backward(turpy_batch* b, uint64_t seed, int64_t t, const void* grad_u_out,
+                                            const void* checkpoints, void* grad_u_in, float* grad_screens,
+                                            void* ws, size_t ws_bytes, void* stream) {
+  if (!b || !grad_u_out) return turpy::report(TURPY_E_INVALID, "batch_propagate_backward: NULL argument");
+  if (t < 0 || t > 0xFFFFFFFFll) return turpy::report(TURPY_E_INVALID, "batch_propagate_backward: t out of range");
+  if (!ws || ws_bytes < total_ws(b, 1))
+    return turpy::report(TURPY_E_WORKSPACE, "batch_propagate_backward: workspace %zu < %zu bytes", ws_bytes,
+                         total_ws(b, 1));
+  const auto* gout = static_cast<const char*>(grad_u_out);
+  const auto* ck = static_cast<const char*>(checkpoints);
+  auto* gin = static_cast<char*>(grad_u_in);
+  return run(b, ws, 1, stream, [&](int i, hipStream_t st, char* lws, size_t lbytes) {
+    const size_t off = static_cast<size_t>(b->offsets[i]) * 8;
+    const size_t co = static_cast<size_t>(b->ck_offsets[i]);
+    return turpy_propagate_backward(b->plans[i], seed + kSeedStep * static_cast<uint64_t>(i), t, gout + off,
+                                    ck ? ck + co * 8 : nullptr, TURPY_SCREENS_SYNTH, nullptr,
+                                    gin ? gin + off : nullptr, grad_screens ? grad_screens + co : nullptr, lws,
+                                    lbytes, st);
+  });
+}
+
+}  // extern "C"

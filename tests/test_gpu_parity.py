@@ -407,3 +407,49 @@ def test_reversible_autograd_matches_checkpointed(api):
         gu, gp = torch.autograd.grad(loss, (u0, phi))
         grads.append((gu.cpu().numpy(), gp.cpu().numpy()))
     assert rel_l2(grads[1][0], grads[0][0]) < 2e-5 and rel_l2(grads[1][1], grads[0][1]) < 2e-5
+
+
+def _uneven_sample(count=6, realizations=(1, 2)):
+    """Serving-mix instances of every grid size, the cheapest of each."""
+    if not _UNEVEN:
+        _UNEVEN.extend(workloads.uneven_batch())
+    out = []
+    for n in (256, 512, 1024, 2048, 256, 512)[:count]:
+        cands = sorted((x for x in _UNEVEN if x.path.n == n), key=lambda x: (x.path.num_screens, x.name))
+        w = cands[len(out) // 4]
+        out.append(w.path.with_(realizations=realizations[len(out) % len(realizations)]))
+    return out
+
+
+def test_uneven_batch_equals_single_plans(api):
+    """One batch call over instances of N = 256..2048 with their own screen
+    counts, wavelengths and distances: every instance's field and adjoint are
+    bitwise those of its own plan with the instance key, and one instance
+    matches the oracle."""
+    paths = _uneven_sample()
+    say("[batch] " + ", ".join(f"N={p.n} M={p.num_screens} R={p.realizations}" for p in paths))
+    batch = api.Batch(paths)
+    srcs = [c64(np.broadcast_to(workloads.gaussian_source(p.n, p.dx, p.n * p.dx / 8), (p.realizations, p.n, p.n)))
+            for p in paths]
+    u_in = batch.pack(srcs)
+    out, ck = batch.propagate(u_in, seed=7, t=2, checkpoints=True)
+    rng = np.random.default_rng(9)
+    g = (rng.standard_normal(batch.total) + 1j * rng.standard_normal(batch.total)).astype(np.complex64)
+    g_in, g_phi = batch.propagate_backward(c64(g), ck, seed=7, t=2)
+    outs, gins = batch.unpack(out), batch.unpack(g_in)
+    gs = batch.unpack(c64(g))
+    for i, p in enumerate(paths):
+        plan = api.Plan(p)
+        s_i = api.Batch.instance_seed(7, i)
+        o, c = plan.propagate(srcs[i], seed=s_i, t=2, checkpoints=True)
+        gi, gp = plan.propagate_backward(gs[i].contiguous(), c, seed=s_i, t=2)
+        assert torch.equal(outs[i], o) and torch.equal(gins[i], gi)
+        off, size = batch.ck_offsets[i], p.realizations * p.num_screens * p.n * p.n
+        assert torch.equal(g_phi[off:off + size].view_as(gp), gp)
+        plan.close()
+    p = paths[0]
+    ref, _ = oracle_propagate(p, api.Batch.instance_seed(7, 0), srcs[0].cpu().numpy(), t=2)
+    err = rel_l2(outs[0].cpu().numpy(), ref)
+    say(f"[batch] instance 0 vs oracle {err:.2e}")
+    assert err < TOL
+    batch.close()
