@@ -299,10 +299,30 @@ def main():
             m3.add(o3)
 
         sec, ktab, dom = measure(torch, ar, args.steps, args.warmup, binding, fams, p3, "ar")
+        # one AR step captured in a HIP graph, replayed with the time step in
+        # device memory (the evolution draws fresh innovations every replay)
+        t3 = torch.ones(1, dtype=torch.int32, device=dev)
+        plan3.bind_time(t3)
+        g3 = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g3):
+            ar(0)
+
+        def ar_replay(i):
+            t3.fill_(i + 1)
+            g3.replay()
+
+        run_steps(torch, ar_replay, 0, 2)
+        t0 = time.perf_counter()
+        run_steps(torch, ar_replay, 2, args.steps)
+        sec_graph = (time.perf_counter() - t0) / args.steps
+        plan3.bind_time(None)
+        del g3
         ss3 = p3.realizations * p3.num_screens
         result["ar"] = {"value": ss3 / sec, "unit": "screen-steps/s", "ms_per_step": 1e3 * sec,
                         "workload": w3.name + " (32 sequences, alpha=0.99, shift 0.5 px/step)",
                         "seconds_for_1000_steps": 1000 * sec, "kernels": ktab, "dominant": dom,
+                        "graph_replay_ms_per_step": 1e3 * sec_graph,
+                        "graph_seconds_for_1000_steps": 1000 * sec_graph,
                         "path_effective_GBps": sum(step_bytes(p3, "ar").values()) / sec / 1e9}
         plan3.close()
         del spec
@@ -336,10 +356,30 @@ def main():
             t0 = time.perf_counter()
             run_steps(torch, fn, 2, k)
             res[name] = (time.perf_counter() - t0) / k
+        # the same call captured once in a HIP graph, replayed with the time
+        # step read from device memory
+        t_dev = torch.zeros(1, dtype=torch.int32, device=dev)
+        batch.bind_time(t_dev)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            batch.propagate(ub, seed=5, t=0, out=uo)
+
+        def replay(i):
+            t_dev.fill_(i)
+            graph.replay()
+
+        run_steps(torch, replay, 0, 2)
+        k = max(3, args.steps // 10)
+        t0 = time.perf_counter()
+        run_steps(torch, replay, 2, k)
+        res["graph"] = (time.perf_counter() - t0) / k
+        batch.bind_time(None)
+        del graph
         result["uneven_batch"] = {
             "value": ss_u / res["batch"], "unit": "screen-steps/s", "instances": len(inst),
             "instances_per_s": len(inst) / res["batch"], "ms_per_call": 1e3 * res["batch"],
             "sequential_ms": 1e3 * res["sequential"], "speedup_vs_sequential": res["sequential"] / res["batch"],
+            "graph_replay_ms": 1e3 * res["graph"], "graph_instances_per_s": len(inst) / res["graph"],
             "workload": "first 64 serving-mix instances (N 256-2048, 5-20 screens, 3 subharmonic levels, R=1)"}
         for pl in plans:
             pl.close()

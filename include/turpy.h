@@ -152,6 +152,16 @@ turpy_status turpy_propagate(turpy_plan* plan, uint64_t seed, int64_t t, const v
 turpy_status turpy_evolve(turpy_plan* plan, uint64_t seed, int64_t t, double alpha, double shift_x,
                           double shift_y, void* spectra, void* ws, size_t ws_bytes, void* stream);
 
+/* Device-resident time step, for graph replays.  With dev_t set (a uint32
+ * in device memory, 4-byte aligned), every kernel of this plan that draws
+ * noise (screen synthesis, subharmonics, AR innovations) reads its time step
+ * from *dev_t when it runs, instead of the t passed to the call; a captured
+ * call then draws fresh noise on each replay after the caller updates *dev_t.
+ * turpy_evolve still decides initialisation (t == 0) from its t argument.
+ * NULL restores the argument.  The pointer is kept; the memory stays the
+ * caller's. */
+turpy_status turpy_plan_bind_time(turpy_plan* plan, const void* dev_t);
+
 /* Bytes of the plan's AR state (see turpy_evolve). */
 turpy_status turpy_state_size(const turpy_plan* plan, size_t* bytes);
 
@@ -240,6 +250,8 @@ typedef struct turpy_batch turpy_batch;
 turpy_status turpy_batch_create(turpy_batch** out, const turpy_path* paths, const int64_t* field_offsets,
                                 int32_t num_paths, uint32_t flags);
 turpy_status turpy_batch_destroy(turpy_batch* batch);
+/* turpy_plan_bind_time for every instance of the batch. */
+turpy_status turpy_batch_bind_time(turpy_batch* batch, const void* dev_t);
 /* op: TURPY_OP_PROPAGATE or TURPY_OP_PROPAGATE_BACKWARD. */
 turpy_status turpy_batch_workspace_size(const turpy_batch* batch, int32_t op, size_t* bytes);
 /* u_in / u_out: packed fields (instance i at field_offsets[i], one source

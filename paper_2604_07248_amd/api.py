@@ -49,6 +49,15 @@ class Plan:
         except Exception:
             pass
 
+    def bind_time(self, t_dev):
+        """Read the noise time step from a one-element int32/uint32 CUDA tensor
+        when the kernels run (graph replays); None restores the argument."""
+        if t_dev is not None:
+            if t_dev.numel() != 1 or t_dev.element_size() != 4 or not t_dev.is_cuda:
+                raise ValueError("bind_time: a one-element 4-byte integer tensor on the GPU")
+        self._t_dev = t_dev  # kept alive while bound
+        B.plan_bind_time(self.handle, _ptr(t_dev))
+
     def workspace(self, op):
         size = B.workspace_size(self.handle, op)
         buf = self._ws.get(op)
@@ -217,6 +226,13 @@ class Batch:
         """Per-instance views [R_i][N_i][N_i] of a packed buffer."""
         return [flat[o:o + p.realizations * p.n * p.n].view(p.realizations, p.n, p.n)
                 for o, p in zip(self.offsets, self.paths)]
+
+    def bind_time(self, t_dev):
+        """As Plan.bind_time, for every instance."""
+        if t_dev is not None and (t_dev.numel() != 1 or t_dev.element_size() != 4 or not t_dev.is_cuda):
+            raise ValueError("bind_time: a one-element 4-byte integer tensor on the GPU")
+        self._t_dev = t_dev
+        B.batch_bind_time(self.handle, _ptr(t_dev))
 
     def _workspace(self, op):
         size = B.batch_workspace_size(self.handle, op)

@@ -25,8 +25,9 @@ EXPORTS = [
     "turpy_screen_generate", "turpy_propagate", "turpy_evolve", "turpy_propagate_backward",
     "turpy_propagate_backward_reversible", "turpy_stats",
     "turpy_receiver_workspace_size", "turpy_receiver", "turpy_receiver_backward", "turpy_profile",
-    "turpy_profile_only", "turpy_profile_read", "turpy_place_screens", "turpy_state_size", "turpy_batch_create",
-    "turpy_batch_destroy", "turpy_batch_workspace_size", "turpy_batch_propagate", "turpy_batch_propagate_backward",
+    "turpy_profile_only", "turpy_profile_read", "turpy_place_screens", "turpy_state_size", "turpy_plan_bind_time",
+    "turpy_batch_create", "turpy_batch_destroy", "turpy_batch_bind_time", "turpy_batch_workspace_size",
+    "turpy_batch_propagate", "turpy_batch_propagate_backward",
 ]
 
 
@@ -101,8 +102,10 @@ def lib():
         L.turpy_profile_only.argtypes = [c_char_p]
         L.turpy_profile_read.argtypes = [c_char_p, POINTER(c_int64), POINTER(c_double)]
         L.turpy_state_size.argtypes = [c_void_p, POINTER(c_size_t)]
+        L.turpy_plan_bind_time.argtypes = [c_void_p, c_void_p]
         L.turpy_batch_create.argtypes = [POINTER(c_void_p), POINTER(CPath), POINTER(c_int64), c_int32, c_uint32]
         L.turpy_batch_destroy.argtypes = [c_void_p]
+        L.turpy_batch_bind_time.argtypes = [c_void_p, c_void_p]
         L.turpy_batch_workspace_size.argtypes = [c_void_p, c_int32, POINTER(c_size_t)]
         L.turpy_batch_propagate.argtypes = [c_void_p, c_uint64, c_int64, c_void_p, c_void_p, c_void_p, c_void_p,
                                             c_size_t, c_void_p]
@@ -161,6 +164,10 @@ def batch_destroy(handle):
     check(lib().turpy_batch_destroy(handle))
 
 
+def batch_bind_time(handle, dev_ptr):
+    check(lib().turpy_batch_bind_time(handle, dev_ptr))
+
+
 def batch_workspace_size(handle, op):
     b = c_size_t()
     check(lib().turpy_batch_workspace_size(handle, op, ctypes.byref(b)))
@@ -174,6 +181,10 @@ def batch_propagate(handle, seed, t, u_in_ptr, u_out_ptr, ckpt_ptr, ws_ptr, ws_b
 def batch_propagate_backward(handle, seed, t, gout_ptr, ckpt_ptr, gin_ptr, gscreens_ptr, ws_ptr, ws_bytes, stream):
     check(lib().turpy_batch_propagate_backward(handle, seed, t, gout_ptr, ckpt_ptr, gin_ptr, gscreens_ptr, ws_ptr,
                                                ws_bytes, stream))
+
+
+def plan_bind_time(handle, dev_ptr):
+    check(lib().turpy_plan_bind_time(handle, dev_ptr))
 
 
 def state_size(handle):

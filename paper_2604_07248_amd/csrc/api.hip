@@ -149,6 +149,7 @@ struct turpy_plan {
   float2* d_sh_phasor = nullptr; // [3][N]
   float* d_sh_amp = nullptr;     // [M][3][2]
   float* d_amp_rad = nullptr;    // [M]
+  const uint32_t* d_t = nullptr; // bound device time step (turpy_plan_bind_time), or NULL
 
   size_t plane_bytes() const { return static_cast<size_t>(n) * n * sizeof(float2); }
   size_t off_sh() const { return align_up(static_cast<size_t>(P) * plane_bytes()); }
@@ -447,6 +448,7 @@ SynthArgs synth_args(const turpy_plan* pl, uint64_t seed, uint32_t t, int s, con
   a.P = pl->P;
   key_of(seed, &a.key0, &a.key1);
   a.t = t;
+  a.t_dev = pl->d_t;
   a.screen = static_cast<uint32_t>(s);
   a.tag = TAG_MAIN;
   a.amp = pl->amp_rev[s];
@@ -495,6 +497,7 @@ ShArgs sh_args(const turpy_plan* pl, uint64_t seed, uint32_t t, float2* sh) {
   a.n = pl->n;
   key_of(seed, &a.key0, &a.key1);
   a.t = t;
+  a.t_dev = pl->d_t;
   a.tag = TAG_SH;
   a.amp = pl->d_sh_amp;
   a.scale = 1.0f;
@@ -930,6 +933,7 @@ turpy_status turpy_evolve(turpy_plan* pl, uint64_t seed, int64_t t, double alpha
   a.n = pl->n;
   key_of(seed, &a.key0, &a.key1);
   a.t = static_cast<uint32_t>(t);
+  a.t_dev = pl->d_t;
   a.init = t == 0 ? 1 : 0;
   a.tag = t == 0 ? TAG_MAIN : TAG_AR;
   a.alpha = alpha;
@@ -954,6 +958,13 @@ turpy_status turpy_evolve(turpy_plan* pl, uint64_t seed, int64_t t, double alpha
     b.sy = shift_y;
     TURPY_HIP(timed("sh", st, [&] { return launch_sh(b, st); }), "evolve: subharmonics");
   }
+  return TURPY_OK;
+}
+
+turpy_status turpy_plan_bind_time(turpy_plan* pl, const void* dev_t) {
+  if (!pl) return fail(TURPY_E_INVALID, "plan_bind_time: NULL plan");
+  if (reinterpret_cast<uintptr_t>(dev_t) % 4 != 0) return fail(TURPY_E_INVALID, "plan_bind_time: misaligned");
+  pl->d_t = static_cast<const uint32_t*>(dev_t);
   return TURPY_OK;
 }
 

@@ -172,6 +172,13 @@ turpy_status turpy_batch_create(turpy_batch** out, const turpy_path* paths, cons
   return TURPY_OK;
 }
 
+turpy_status turpy_batch_bind_time(turpy_batch* b, const void* dev_t) {
+  if (!b) return turpy::report(TURPY_E_INVALID, "batch_bind_time: NULL batch");
+  for (turpy_plan* p : b->plans)
+    if (turpy_status s = turpy_plan_bind_time(p, dev_t)) return s;
+  return TURPY_OK;
+}
+
 turpy_status turpy_batch_workspace_size(const turpy_batch* b, int32_t op, size_t* bytes) {
   if (!b || !bytes) return turpy::report(TURPY_E_INVALID, "batch_workspace_size: NULL argument");
   if (op == TURPY_OP_PROPAGATE) {

@@ -33,6 +33,13 @@ __device__ __forceinline__ float psd_amp(int q, float amp, float df2, float inne
 
 __device__ __forceinline__ int signed_bin(int k, int n) { return k < (n >> 1) ? k : k - n; }
 
+// The noise time step of a launch: its argument, or, for plans bound to a
+// device-resident time step (graph replays), the value there when it runs.
+template <class Args>
+__device__ __forceinline__ uint32_t time_step(const Args& a) {
+  return a.t_dev ? *a.t_dev : a.t;
+}
+
 // ---------------------------------------------------------------------------
 // Row pass.
 // ---------------------------------------------------------------------------
@@ -487,7 +494,7 @@ void synth_col_kernel(SynthArgs a) {
     for (int m = 0; m < kE / 2; ++m) {
       const int k0 = t + T * m;  // < N/2
       const uint32_t e = static_cast<uint32_t>(k0) * N + k1;
-      const uint4 v = philox4x32_10(noise_counter(e, a.t, static_cast<uint32_t>(j), a.tag, a.screen), a.key0,
+      const uint4 v = philox4x32_10(noise_counter(e, time_step(a), static_cast<uint32_t>(j), a.tag, a.screen), a.key0,
                                     a.key1);
       const int ky_lo = k0;             // signed bin of k0 (< N/2)
       const int ky_hi = k0 - N / 2;     // signed bin of k0 + N/2
@@ -526,7 +533,7 @@ __device__ __forceinline__ void synth_column(float2 (&z)[kE], const SynthArgs& a
     for (int m = 0; m < kE / 2; ++m) {
       const int k0 = t + T * m;  // < N/2
       const uint32_t e = static_cast<uint32_t>(k0) * N + k1;
-      const uint4 v = philox4x32_10(noise_counter(e, a.t, static_cast<uint32_t>(j), a.tag, a.screen), a.key0,
+      const uint4 v = philox4x32_10(noise_counter(e, time_step(a), static_cast<uint32_t>(j), a.tag, a.screen), a.key0,
                                     a.key1);
       const int ky_hi = k0 - N / 2;
       const float w_lo = psd_amp(k0 * k0 + kx * kx, a.amp, a.df2, a.inner, a.f02, a.q);
@@ -616,7 +623,7 @@ __global__ __launch_bounds__(64) void sh_kernel(ShArgs a) {
   float2* out = a.sh + (static_cast<size_t>(j) * a.M + s) * 32;
   if (l < 4 * a.levels) {
     const int p = l / 4;
-    const uint4 v = philox4x32_10(noise_counter(static_cast<uint32_t>(l), a.t, static_cast<uint32_t>(j), a.tag,
+    const uint4 v = philox4x32_10(noise_counter(static_cast<uint32_t>(l), time_step(a), static_cast<uint32_t>(j), a.tag,
                                                 static_cast<uint32_t>(s)),
                                   a.key0, a.key1);
     const float* amp = a.amp + (static_cast<size_t>(s) * 3 + p) * 2;
@@ -679,7 +686,7 @@ __global__ __launch_bounds__(256) void evolve_kernel(EvolveArgs a) {
   const int64_t j = js / a.M;
   const int s = static_cast<int>(js % a.M);
   const uint4 v = philox4x32_10(
-      noise_counter(static_cast<uint32_t>(rem), a.t, static_cast<uint32_t>(j), a.tag, static_cast<uint32_t>(s)),
+      noise_counter(static_cast<uint32_t>(rem), time_step(a), static_cast<uint32_t>(j), a.tag, static_cast<uint32_t>(s)),
       a.key0, a.key1);
   float2* base = a.spectra + js * static_cast<int64_t>(n) * n;
   const float amp = a.amp[s];

@@ -65,6 +65,7 @@ struct SynthArgs {
   int64_t P;                // realization pairs
   uint32_t key0, key1;      // Philox key (seed)
   uint32_t t;               // time step
+  const uint32_t* t_dev;    // or, when set, read here at run time
   uint32_t screen;
   uint32_t tag;
   float amp;                // sqrt(0.023) r0^(-5/6) df / (2 pi): revolutions
@@ -84,6 +85,7 @@ struct ShArgs {
   int levels;
   int n;                    // grid size (translation phase of an AR step)
   uint32_t key0, key1, t, tag;
+  const uint32_t* t_dev;    // time step read at run time when set
   const float* amp;         // [M][3][2] amplitude (revolutions) for |offset|^2 = 1, 2
   float scale;              // output units per revolution: 1, or 2 pi for radians
   int ar;                   // 0: fresh coefficients; 1: Eq. 4 + Eq. 5 step of the stored ones
@@ -97,6 +99,7 @@ struct EvolveArgs {
   int M;
   int n;
   uint32_t key0, key1, t, tag;
+  const uint32_t* t_dev;    // time step read at run time when set
   double alpha;
   double sx, sy;            // shift in pixels
   int init;                 // 1: overwrite with fresh spectra (t = 0)

@@ -453,3 +453,52 @@ def test_uneven_batch_equals_single_plans(api):
     say(f"[batch] instance 0 vs oracle {err:.2e}")
     assert err < TOL
     batch.close()
+
+
+def test_graph_replay_reads_device_time(api):
+    """One forward step (synthesised screens with subharmonics) captured in a
+    HIP graph and replayed with the time step read from device memory: every
+    replay, with eager work and synchronisations between replays, equals the
+    eager call at that time step bit for bit.  The same for an uneven batch
+    (internal streams forked and joined inside the capture)."""
+    path = sized_path(256, realizations=4, m=3, sh=3)
+    plan, ref = api.Plan(path), api.Plan(path)
+    u0 = c64(gaussian(path))
+    out = torch.empty((4, path.n, path.n), dtype=torch.complex64, device="cuda")
+    t_dev = torch.zeros(1, dtype=torch.int32, device="cuda")
+    plan.bind_time(t_dev)
+    plan.propagate(u0, seed=3, t=0, out=out)  # allocates the workspace before the capture
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        plan.propagate(u0, seed=3, t=0, out=out)
+    for t in (4, 1, 9, 1, 0):
+        t_dev.fill_(t)
+        graph.replay()
+        torch.cuda.synchronize()
+        got = out.clone()
+        want = ref.propagate(u0, seed=3, t=t)
+        torch.cuda.synchronize()
+        assert torch.equal(got, want), t
+    say("[graph] plan: 5 replays equal the eager calls")
+    paths = _uneven_sample(4, realizations=(1,))
+    batch, eager = api.Batch(paths), api.Batch(paths)
+    srcs = [c64(workloads.gaussian_source(p.n, p.dx, p.n * p.dx / 8)[None]) for p in paths]
+    ub = batch.pack(srcs)
+    ob = torch.empty_like(ub)
+    batch.bind_time(t_dev)
+    batch.propagate(ub, seed=5, t=0, out=ob)
+    torch.cuda.synchronize()
+    gb = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(gb):
+        batch.propagate(ub, seed=5, t=0, out=ob)
+    for t in (2, 7, 2):
+        t_dev.fill_(t)
+        gb.replay()
+        torch.cuda.synchronize()
+        got = ob.clone()
+        want = eager.propagate(ub, seed=5, t=t)
+        torch.cuda.synchronize()
+        assert torch.equal(got, want), t
+    say("[graph] batch: 3 replays equal the eager calls")
+    plan.bind_time(None)
