@@ -467,10 +467,10 @@ void col_pass_kernel(ColArgs a) {
 // stored spectrum, then the unnormalised inverse transform along y.
 // ---------------------------------------------------------------------------
 template <int N>
-__global__ __launch_bounds__(col_block<N>()) __attribute__((amdgpu_waves_per_eu(TURPY_COL_WAVES, 0)))
+__global__ __launch_bounds__(synth_block<N>()) __attribute__((amdgpu_waves_per_eu(TURPY_COL_WAVES, 0)))
 void synth_col_kernel(SynthArgs a) {
   constexpr int T = N / kE;
-  constexpr int K = col_width<N>();
+  constexpr int K = synth_width<N>();
   constexpr int STRIPS = N / K;
   __shared__ float2 smem[ColLds<K>::words(N)];
   const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
@@ -910,9 +910,9 @@ hipError_t col_pair_launch(const ColArgs& a, const SynthArgs& syn, int do_synth,
 
 template <int N>
 hipError_t synth_launch(const SynthArgs& a, hipStream_t s) {
-  constexpr int K = col_width<N>();
+  constexpr int K = synth_width<N>();
   const uint64_t blocks = static_cast<uint64_t>(N / K) * a.P;
-  hipLaunchKernelGGL(synth_col_kernel<N>, dim3(static_cast<uint32_t>(blocks)), dim3(col_block<N>()), 0, s, a);
+  hipLaunchKernelGGL(synth_col_kernel<N>, dim3(static_cast<uint32_t>(blocks)), dim3(synth_block<N>()), 0, s, a);
   return hipGetLastError();
 }
 

@@ -15,9 +15,6 @@ constexpr int row_groups() {  // rows per block of the row kernels
 }
 template <int N>
 constexpr int row_block() { return row_groups<N>() * (N / kE); }
-#ifndef TURPY_COL_K
-#define TURPY_COL_K 8
-#endif
 #ifndef TURPY_ROW_WAVES
 #define TURPY_ROW_WAVES 0
 #endif
@@ -36,12 +33,21 @@ constexpr int row_block() { return row_groups<N>() * (N / kE); }
 #ifndef TURPY_COL_WAVES
 #define TURPY_COL_WAVES 0
 #endif
+// Columns per block of the column pass and of the screen synthesis, per grid
+// size: the fastest of 4, 8 and 16 measured on MI355X at constant R N^2
+// (column pass: 16 up to N = 512, 8 above; synthesis, whose VALU load per
+// element is higher, 4 from N = 1024).  At N = 2048 a 16-column strip does
+// not fit one block.
 template <int N>
 constexpr int col_width() {
-  return N >= 2048 ? (TURPY_COL_K < 8 ? TURPY_COL_K : 8) : (N < TURPY_COL_K ? N : TURPY_COL_K);
+  return N >= 1024 ? 8 : (N >= 256 ? 16 : (N < 8 ? N : 8));
 }
 template <int N>
 constexpr int col_block() { return col_width<N>() * (N / kE); }
+template <int N>
+constexpr int synth_width() { return N >= 1024 ? 4 : col_width<N>(); }
+template <int N>
+constexpr int synth_block() { return synth_width<N>() * (N / kE); }
 
 // Row-pair pass: each half of a block (whole waves for N >= 64) carries one
 // realization of a pair over `pair_rows` rows.
