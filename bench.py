@@ -17,8 +17,10 @@ of the whole path over one batch:
   plain:   the same forward physics as one PyTorch op per kernel
            (torch.fft, elementwise exp and multiplies), screens materialised.
 
-Prints one JSON line.  Inputs are seeded and synthetic and already resident in
-HBM when the timed region starts.
+Before any timed step each plan's column-pass and synthesis strip widths are
+measured by turpy_plan_tune (or taken from --tune-cache); `config.strip_widths`
+and `tuning` report them.  Prints one JSON line.  Inputs are seeded and
+synthetic and already resident in HBM when the timed region starts.
 """
 
 import argparse
@@ -45,6 +47,9 @@ def parse():
                                        "uneven"],
                     default="all",
                     help="run one leg (profiling runs)")
+    ap.add_argument("--tune-cache", default=None,
+                    help="JSON strip-width cache: read when the file exists (its widths are then used without "
+                         "measuring), written at the end")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-pairs", type=int, default=16, help="realization pairs in the oracle sample (about 20 s of CPU work)")
     return ap.parse_args()
@@ -216,9 +221,16 @@ def main():
     binding.lib()
     fams = ["row_fwd", "row_bwd", "row_plain", "col", "synth", "sh", "evolve", "stats", "finalize", "copy"]
 
+    if args.tune_cache and os.path.exists(args.tune_cache):
+        api.tune_cache_load(args.tune_cache)
     w = workloads.headline(args.realizations)
     path = w.path
     plan = api.Plan(path)
+    # strip widths of the column pass and the synthesis: measured (or cached)
+    # before any timed step
+    t_tune = time.perf_counter()
+    widths = plan.tune()
+    t_tune = time.perf_counter() - t_tune
     u0 = torch.from_numpy(w.source_field().astype(np.complex64)).to(dev)
     u_out = torch.empty((path.realizations, path.n, path.n), dtype=torch.complex64, device=dev)
     moments = api.Moments(path.n, path.dx)
@@ -229,7 +241,7 @@ def main():
               "config": {"workload": w.name + " (N=1024 over 1 m, 1064 nm, 1.5 km, Cn2=2e-14, l0=5 mm, L0=20 m, "
                                               "8 fresh screens per step, W0=5 cm)",
                          "n": path.n, "realizations": path.realizations, "screens": path.num_screens,
-                         "screen_steps_per_step": ss_per_step}}
+                         "screen_steps_per_step": ss_per_step, "strip_widths": widths}}
 
     def fwd(i):
         plan.propagate(u0, seed=w.seed, t=i, out=u_out)
@@ -248,6 +260,7 @@ def main():
         # the same forward step with the angular-spectrum transfer function (Sec. 2.1)
         pas = path.with_(tf_kind=workloads.TF_ANGULAR_SPECTRUM)
         plan_as = api.Plan(pas)
+        plan_as.tune()
 
         def fwd_as(i):
             plan_as.propagate(u0, seed=w.seed, t=i, out=u_out)
@@ -287,6 +300,7 @@ def main():
         w3 = workloads.config3()
         p3 = w3.path
         plan3 = api.Plan(p3)
+        plan3.tune()
         spec = plan3.init_spectra(w3.seed)
         u3 = torch.from_numpy(w3.source_field().astype(np.complex64)).to(dev)
         o3 = torch.empty((p3.realizations, p3.n, p3.n), dtype=torch.complex64, device=dev)
@@ -333,6 +347,9 @@ def main():
         # batch call, against the same instances run one plan after another
         inst = [x.path for x in workloads.uneven_batch()[:64]]
         batch = api.Batch(inst)
+        t_bt = time.perf_counter()
+        batch.tune()  # one measurement per (N, batch class); the plans below start from the cache
+        t_bt = time.perf_counter() - t_bt
         srcs = [torch.from_numpy(workloads.gaussian_source(p.n, p.dx, p.n * p.dx / 8).astype(np.complex64))[None]
                 for p in inst]
         ub = batch.pack(srcs)
@@ -380,7 +397,8 @@ def main():
             "instances_per_s": len(inst) / res["batch"], "ms_per_call": 1e3 * res["batch"],
             "sequential_ms": 1e3 * res["sequential"], "speedup_vs_sequential": res["sequential"] / res["batch"],
             "graph_replay_ms": 1e3 * res["graph"], "graph_instances_per_s": len(inst) / res["graph"],
-            "workload": "first 64 serving-mix instances (N 256-2048, 5-20 screens, 3 subharmonic levels, R=1)"}
+            "workload": "first 64 serving-mix instances (N 256-2048, 5-20 screens, 3 subharmonic levels, R=1)",
+            "tune_seconds": t_bt}
         for pl in plans:
             pl.close()
         batch.close()
@@ -420,6 +438,9 @@ def main():
         result["copy"] = ktab
         result["value"] = 0.0
 
+    result["tuning"] = {"headline_seconds": t_tune, "cache": api.tune_cache()}
+    if args.tune_cache:
+        api.tune_cache_save(args.tune_cache)
     if args.only == "all" and not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(w, args.cpu_pairs)
 

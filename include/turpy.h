@@ -89,7 +89,8 @@ typedef enum {
   TURPY_OP_PROPAGATE = 1,
   TURPY_OP_PROPAGATE_BACKWARD = 2,
   TURPY_OP_EVOLVE = 3,
-  TURPY_OP_PROPAGATE_BACKWARD_REVERSIBLE = 4
+  TURPY_OP_PROPAGATE_BACKWARD_REVERSIBLE = 4,
+  TURPY_OP_TUNE = 5
 } turpy_op;
 
 /* Library version string (static storage). */
@@ -252,7 +253,7 @@ turpy_status turpy_batch_create(turpy_batch** out, const turpy_path* paths, cons
 turpy_status turpy_batch_destroy(turpy_batch* batch);
 /* turpy_plan_bind_time for every instance of the batch. */
 turpy_status turpy_batch_bind_time(turpy_batch* batch, const void* dev_t);
-/* op: TURPY_OP_PROPAGATE or TURPY_OP_PROPAGATE_BACKWARD. */
+/* op: TURPY_OP_PROPAGATE, TURPY_OP_PROPAGATE_BACKWARD or TURPY_OP_TUNE. */
 turpy_status turpy_batch_workspace_size(const turpy_batch* batch, int32_t op, size_t* bytes);
 /* u_in / u_out: packed fields (instance i at field_offsets[i], one source
  * plane per realization; u_in == u_out allowed).  checkpoints (NULL = none):
@@ -312,6 +313,73 @@ typedef struct turpy_cn2_profile {
 turpy_status turpy_place_screens(const turpy_cn2_profile* profile, double length, double wavelength, double n0,
                                  int32_t n, double dx, double rytov_limit, int32_t initial, int32_t max_screens,
                                  int32_t* num_screens, double* dz, double* cn2dz, double* rytov);
+
+/* ---------------------------------------------------------------------------
+ * Launch-shape tuning.  The column pass (FFT along y, transfer function,
+ * inverse FFT; Sec. 2.1) and the column half of the screen synthesis (Eq.
+ * S16) each run one block per strip of K adjacent columns of a plane, K in
+ * {4, 8, 16} (K N / 16 threads per block, at most 1024, and K N complex words
+ * of LDS; at N = 2048 K = 16 does not fit).  K sets the block size, the
+ * occupancy and the width of each memory segment the pass touches; it does
+ * not change the arithmetic: every K gives bit-identical results.  A plan
+ * starts from a built-in choice per N (measured on MI355X), or from the
+ * process-wide cache when it holds an entry for the plan's key:
+ *   (device architecture, kernel, N, batch class = bit length of the number
+ *    of planes one launch covers: R for the column pass, ceil(R/2) for the
+ *    synthesis).
+ * ------------------------------------------------------------------------- */
+typedef enum {
+  TURPY_TUNE_COL_FRESNEL = 0,   /* column pass, Fresnel transfer function            */
+  TURPY_TUNE_COL_ANGULAR = 1,   /* column pass, angular spectrum, every bin propagating */
+  TURPY_TUNE_COL_AS_TABLE = 2,  /* column pass, angular spectrum with evanescent bins */
+  TURPY_TUNE_SYNTH = 3          /* column half of the screen synthesis               */
+} turpy_tune_kernel;
+
+#define TURPY_TUNE_FORCE 1u     /* measure even when the cache holds the key */
+
+typedef struct turpy_tune_entry {
+  char arch[32];                /* device architecture, e.g. "gfx950" (NUL-terminated)     */
+  int32_t kernel;               /* turpy_tune_kernel                                        */
+  int32_t n;                    /* grid size                                                */
+  int32_t batch_class;          /* bit length of the planes per launch                      */
+  int32_t width;                /* chosen columns per block: 4, 8 or 16                     */
+  float us[3];                  /* measured microseconds per launch at K = 4, 8, 16 (0: K
+                                   not built for N); kept as given by turpy_tune_cache_put  */
+} turpy_tune_entry;
+
+/* Time every strip width of the plan's column pass (its transfer-function
+ * kind, distance 0, all R planes in place) and, when the plan has screens, of
+ * its synthesis (all ceil(R/2) scratch planes), with HIP events on `stream`,
+ * and keep the fastest of each in the plan and in the cache.  A key already
+ * in the cache is applied without measuring unless flags has
+ * TURPY_TUNE_FORCE.  Each width: one launch, then 3 repetitions of a loop of
+ * launches lasting about 2 ms; the minimum per-launch time counts.
+ * ws: turpy_workspace_size(TURPY_OP_TUNE) bytes of device memory, zeroed and
+ * overwritten here (no caller data is touched).  Synchronises `stream`: it
+ * cannot be captured in a graph (TURPY_E_INVALID while the stream captures).
+ * col_width / synth_width (may be NULL) receive the widths now in the plan. */
+turpy_status turpy_plan_tune(turpy_plan* plan, uint32_t flags, void* ws, size_t ws_bytes, void* stream,
+                             int32_t* col_width, int32_t* synth_width);
+/* The strip widths the plan's launches use now. */
+turpy_status turpy_plan_widths(const turpy_plan* plan, int32_t* col_width, int32_t* synth_width);
+/* Set the strip widths directly: 0 restores the built-in choice; any other
+ * value must be a width built for the plan's N (TURPY_E_INVALID otherwise,
+ * and the plan is unchanged). */
+turpy_status turpy_plan_set_widths(turpy_plan* plan, int32_t col_width, int32_t synth_width);
+/* The cache (host memory, process-wide, guarded by a lock): get copies up to
+ * `capacity` entries in key order and sets *count to the number held (so a
+ * call with capacity 0 sizes the array); put inserts or replaces entries by
+ * key (TURPY_E_INVALID for a width not built for the entry's n or an unknown
+ * kernel; entries before the bad one are kept); clear empties it.  Plans
+ * created afterwards start from the cached widths; existing plans keep theirs.
+ * These three calls touch no device. */
+turpy_status turpy_tune_cache_get(turpy_tune_entry* entries, int32_t capacity, int32_t* count);
+turpy_status turpy_tune_cache_put(const turpy_tune_entry* entries, int32_t count);
+turpy_status turpy_tune_cache_clear(void);
+/* turpy_plan_tune for every instance of the batch (each distinct key is
+ * measured once; later instances take it from the cache).  ws:
+ * turpy_batch_workspace_size(TURPY_OP_TUNE) bytes; synchronises `stream`. */
+turpy_status turpy_batch_tune(turpy_batch* batch, uint32_t flags, void* ws, size_t ws_bytes, void* stream);
 
 /* Per-kernel timing for benchmarking.  turpy_profile(1) clears the record and
  * starts bracketing every kernel the library enqueues with a pair of HIP events

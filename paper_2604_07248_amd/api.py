@@ -6,6 +6,7 @@ HIP stream.
 """
 
 import ctypes
+import json
 
 import torch
 
@@ -65,6 +66,27 @@ class Plan:
             buf = torch.empty(max(size, 256), dtype=torch.uint8, device=self.device)
             self._ws[op] = buf
         return buf, size
+
+    # -- launch shapes -------------------------------------------------------
+    def tune(self, force=False):
+        """Time the strip widths of the column pass and of the synthesis
+        (turpy_plan_tune; synchronises) and keep the fastest, or take them
+        from the tuning cache.  Returns {"col": K, "synth": K}."""
+        size = B.workspace_size(self.handle, B.OP_TUNE)
+        ws = torch.empty(max(size, 256), dtype=torch.uint8, device=self.device)
+        col, syn = B.plan_tune(self.handle, B.TUNE_FORCE if force else 0, _ptr(ws), size, _stream())
+        del ws
+        return {"col": col, "synth": syn}
+
+    @property
+    def widths(self):
+        """The strip widths the plan's launches use: {"col": K, "synth": K}."""
+        col, syn = B.plan_widths(self.handle)
+        return {"col": col, "synth": syn}
+
+    def set_widths(self, col=0, synth=0):
+        """Set the strip widths (0: the built-in choice for N)."""
+        B.plan_set_widths(self.handle, col, synth)
 
     # -- screens -------------------------------------------------------------
     def screens(self, seed, t=0, out=None):
@@ -242,6 +264,13 @@ class Batch:
             self._ws[op] = buf
         return buf, size
 
+    def tune(self, force=False):
+        """Plan.tune for every instance; each distinct key is measured once."""
+        size = B.batch_workspace_size(self.handle, B.OP_TUNE)
+        ws = torch.empty(max(size, 256), dtype=torch.uint8, device=self.device)
+        B.batch_tune(self.handle, B.TUNE_FORCE if force else 0, _ptr(ws), size, _stream())
+        del ws
+
     def propagate(self, u_in, seed=0, t=0, checkpoints=False, out=None):
         _need(u_in, torch.complex64, (self.total,), "u_in")
         out = torch.empty_like(u_in) if out is None else out
@@ -260,6 +289,35 @@ class Batch:
         B.batch_propagate_backward(self.handle, seed, t, _ptr(grad_out), _ptr(checkpoints), _ptr(g_in), _ptr(g_phi),
                                    _ptr(ws), size, _stream())
         return g_in, g_phi
+
+
+TUNE_CACHE_FORMAT = "turpy-tune-cache"
+
+
+def tune_cache():
+    """Entries of the process-wide tuning cache (list of dicts)."""
+    return B.tune_cache_get()
+
+
+def tune_cache_save(path):
+    """Write the tuning cache as JSON."""
+    with open(path, "w") as f:
+        json.dump({"format": TUNE_CACHE_FORMAT, "version": 1, "entries": B.tune_cache_get()}, f, indent=1)
+
+
+def tune_cache_load(path):
+    """Merge a JSON file written by tune_cache_save into the cache; returns
+    the number of entries read.  Plans created afterwards use them."""
+    with open(path) as f:
+        doc = json.load(f)
+    if doc.get("format") != TUNE_CACHE_FORMAT or doc.get("version") != 1:
+        raise ValueError(f"{path}: not a version-1 {TUNE_CACHE_FORMAT} file")
+    B.tune_cache_put(doc["entries"])
+    return len(doc["entries"])
+
+
+def tune_cache_clear():
+    B.tune_cache_clear()
 
 
 class Moments:

@@ -17,7 +17,10 @@ CN2_UNIFORM, CN2_HUFNAGEL_VALLEY, CN2_TABLE = 0, 1, 2
 TF_FRESNEL, TF_ANGULAR_SPECTRUM = 0, 1
 SCREENS_SYNTH, SCREENS_MATERIALIZED, SCREENS_SPECTRA = 0, 1, 2
 ALLOW_ALIASING = 1
-OP_SCREEN_GENERATE, OP_PROPAGATE, OP_PROPAGATE_BACKWARD, OP_EVOLVE, OP_PROPAGATE_BACKWARD_REVERSIBLE = range(5)
+OP_SCREEN_GENERATE, OP_PROPAGATE, OP_PROPAGATE_BACKWARD, OP_EVOLVE, OP_PROPAGATE_BACKWARD_REVERSIBLE, OP_TUNE = range(6)
+TUNE_COL_FRESNEL, TUNE_COL_ANGULAR, TUNE_COL_AS_TABLE, TUNE_SYNTH = range(4)
+TUNE_KERNELS = ("col_fresnel", "col_angular", "col_as_table", "synth")
+TUNE_FORCE = 1
 
 # Every symbol the header declares (checked by the CPU tests).
 EXPORTS = [
@@ -27,7 +30,9 @@ EXPORTS = [
     "turpy_receiver_workspace_size", "turpy_receiver", "turpy_receiver_backward", "turpy_profile",
     "turpy_profile_only", "turpy_profile_read", "turpy_place_screens", "turpy_state_size", "turpy_plan_bind_time",
     "turpy_batch_create", "turpy_batch_destroy", "turpy_batch_bind_time", "turpy_batch_workspace_size",
-    "turpy_batch_propagate", "turpy_batch_propagate_backward",
+    "turpy_batch_propagate", "turpy_batch_propagate_backward", "turpy_plan_tune", "turpy_plan_widths",
+    "turpy_plan_set_widths", "turpy_tune_cache_get", "turpy_tune_cache_put", "turpy_tune_cache_clear",
+    "turpy_batch_tune",
 ]
 
 
@@ -43,6 +48,13 @@ class CPath(ctypes.Structure):
         ("dz", POINTER(c_double)), ("cn2dz", POINTER(c_double)), ("l0", c_double), ("L0", c_double),
         ("sh_levels", c_int32), ("tf_kind", c_int32), ("inner_scale_conv", c_int32), ("realizations", c_int64),
         ("psd_alpha", c_double),
+    ]
+
+
+class CTuneEntry(ctypes.Structure):
+    _fields_ = [
+        ("arch", ctypes.c_char * 32), ("kernel", c_int32), ("n", c_int32), ("batch_class", c_int32),
+        ("width", c_int32), ("us", c_float * 3),
     ]
 
 
@@ -114,6 +126,14 @@ def lib():
         L.turpy_place_screens.argtypes = [POINTER(CCn2Profile), c_double, c_double, c_double, c_int32, c_double,
                                           c_double, c_int32, c_int32, POINTER(c_int32), POINTER(c_double),
                                           POINTER(c_double), POINTER(c_double)]
+        L.turpy_plan_tune.argtypes = [c_void_p, c_uint32, c_void_p, c_size_t, c_void_p, POINTER(c_int32),
+                                      POINTER(c_int32)]
+        L.turpy_plan_widths.argtypes = [c_void_p, POINTER(c_int32), POINTER(c_int32)]
+        L.turpy_plan_set_widths.argtypes = [c_void_p, c_int32, c_int32]
+        L.turpy_tune_cache_get.argtypes = [POINTER(CTuneEntry), c_int32, POINTER(c_int32)]
+        L.turpy_tune_cache_put.argtypes = [POINTER(CTuneEntry), c_int32]
+        L.turpy_tune_cache_clear.argtypes = []
+        L.turpy_batch_tune.argtypes = [c_void_p, c_uint32, c_void_p, c_size_t, c_void_p]
         for name in EXPORTS:
             if name not in ("turpy_version", "turpy_last_error"):
                 getattr(L, name).restype = c_int32
@@ -263,6 +283,56 @@ def profile_read(family):
     n, ms = c_int64(), c_double()
     check(lib().turpy_profile_read(family.encode(), ctypes.byref(n), ctypes.byref(ms)))
     return n.value, ms.value
+
+
+def plan_tune(handle, flags, ws_ptr, ws_bytes, stream):
+    col, syn = c_int32(), c_int32()
+    check(lib().turpy_plan_tune(handle, flags, ws_ptr, ws_bytes, stream, ctypes.byref(col), ctypes.byref(syn)))
+    return col.value, syn.value
+
+
+def plan_widths(handle):
+    col, syn = c_int32(), c_int32()
+    check(lib().turpy_plan_widths(handle, ctypes.byref(col), ctypes.byref(syn)))
+    return col.value, syn.value
+
+
+def plan_set_widths(handle, col_width, synth_width):
+    check(lib().turpy_plan_set_widths(handle, col_width, synth_width))
+
+
+def batch_tune(handle, flags, ws_ptr, ws_bytes, stream):
+    check(lib().turpy_batch_tune(handle, flags, ws_ptr, ws_bytes, stream))
+
+
+def tune_cache_get():
+    """The tuning cache as a list of dicts (arch, kernel name, n, batch_class, width, us)."""
+    count = c_int32()
+    check(lib().turpy_tune_cache_get(None, 0, ctypes.byref(count)))
+    arr = (CTuneEntry * max(count.value, 1))()
+    check(lib().turpy_tune_cache_get(arr, count.value, ctypes.byref(count)))
+    return [{"arch": e.arch.decode(), "kernel": TUNE_KERNELS[e.kernel], "n": e.n, "batch_class": e.batch_class,
+             "width": e.width, "us": [float(v) for v in e.us]} for e in arr[:count.value]]
+
+
+def tune_cache_put(entries):
+    """Insert dicts in the form tune_cache_get returns (us optional)."""
+    arr = (CTuneEntry * max(len(entries), 1))()
+    for i, d in enumerate(entries):
+        arch = d["arch"].encode()
+        if len(arch) >= 32:
+            raise ValueError(f"arch name too long: {d['arch']!r}")
+        kernel = d["kernel"]
+        arr[i].arch = arch
+        arr[i].kernel = TUNE_KERNELS.index(kernel) if isinstance(kernel, str) else int(kernel)
+        arr[i].n, arr[i].batch_class, arr[i].width = int(d["n"]), int(d["batch_class"]), int(d["width"])
+        for j, v in enumerate(d.get("us", [0.0, 0.0, 0.0])):
+            arr[i].us[j] = float(v)
+    check(lib().turpy_tune_cache_put(arr, len(entries)))
+
+
+def tune_cache_clear():
+    check(lib().turpy_tune_cache_clear())
 
 
 def make_cn2_profile(kind, cn2=0.0, A=0.0, V=0.0, z=None, values=None):

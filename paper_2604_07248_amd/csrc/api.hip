@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "kernels.hpp"
+#include "layout.hpp"
 #include "report.hpp"
 #include "turpy.h"
 
@@ -150,6 +151,9 @@ struct turpy_plan {
   float* d_sh_amp = nullptr;     // [M][3][2]
   float* d_amp_rad = nullptr;    // [M]
   const uint32_t* d_t = nullptr; // bound device time step (turpy_plan_bind_time), or NULL
+  // strip widths of the column pass and the synthesis (0: built-in choice for n)
+  int col_width = 0, synth_width = 0;
+  std::string arch;              // device architecture (tuning-cache key)
 
   size_t plane_bytes() const { return static_cast<size_t>(n) * n * sizeof(float2); }
   size_t off_sh() const { return align_up(static_cast<size_t>(P) * plane_bytes()); }
@@ -162,7 +166,14 @@ struct turpy_plan {
   // reversible adjoint: also the rebuilt forward field and its value at the current screen
   size_t off_ubuf() const { return ws_backward(); }
   size_t ws_reversible() const { return ws_backward() + 2 * align_up(static_cast<size_t>(R) * plane_bytes()); }
+  // tuning: the scratch planes (synthesis) and the R-plane buffer (column pass)
+  size_t ws_tune() const { return ws_backward(); }
 };
+
+namespace {
+void apply_cached_widths(turpy_plan* pl);
+std::string device_arch(int device);
+}  // namespace
 
 extern "C" {
 
@@ -347,6 +358,8 @@ turpy_status turpy_plan_create(turpy_plan** out, const turpy_path* p, uint32_t f
     turpy_plan_destroy(pl);
     return hip_fail(e, "plan_create: table upload");
   }
+  pl->arch = device_arch(pl->device);
+  apply_cached_widths(pl);
   *out = pl;
   return TURPY_OK;
 }
@@ -372,6 +385,7 @@ turpy_status turpy_workspace_size(const turpy_plan* pl, int32_t op, size_t* byte
     case TURPY_OP_PROPAGATE_BACKWARD: *bytes = pl->ws_backward(); return TURPY_OK;
     case TURPY_OP_EVOLVE: *bytes = 0; return TURPY_OK;
     case TURPY_OP_PROPAGATE_BACKWARD_REVERSIBLE: *bytes = pl->ws_reversible(); return TURPY_OK;
+    case TURPY_OP_TUNE: *bytes = pl->ws_tune(); return TURPY_OK;
     default: return fail(TURPY_E_INVALID, "workspace_size: unknown op %d", op);
   }
 }
@@ -429,6 +443,7 @@ ColArgs col_args(const turpy_plan* pl, int step, const float2* in, int64_t in_st
   c.R = R;
   c.table = pl->d_col + static_cast<size_t>(step) * pl->n;
   c.conj_table = adjoint ? 1 : 0;
+  c.width = pl->col_width;
   c.angular = pl->tf_kind == TURPY_TF_ANGULAR_SPECTRUM ? 1 : 0;
   if (c.angular) {
     if (pl->d_as)
@@ -458,6 +473,7 @@ SynthArgs synth_args(const turpy_plan* pl, uint64_t seed, uint32_t t, int s, con
   a.q = pl->qexp;
   a.spectra = spectra;
   a.M = pl->M;
+  a.width = pl->synth_width;
   return a;
 }
 
@@ -1124,6 +1140,235 @@ turpy_status turpy_receiver_backward(int32_t n, double dx, double aperture_diame
   if (grad_theta1)
     TURPY_HIP(timed("recv_reduce", st, [&] { return launch_recv_reduce(a, grad_theta1, 0, st); }),
               "receiver_backward: theta1 reduce");
+  return TURPY_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Strip-width tuning and its process-wide cache.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int kWidths[3] = {4, 8, 16};
+
+struct TuneKey {
+  std::string arch;
+  int kernel, n, batch_class;
+  bool operator<(const TuneKey& o) const {
+    if (arch != o.arch) return arch < o.arch;
+    if (kernel != o.kernel) return kernel < o.kernel;
+    if (n != o.n) return n < o.n;
+    return batch_class < o.batch_class;
+  }
+};
+
+std::mutex g_tune_mu;
+std::map<TuneKey, turpy_tune_entry> g_tune;
+
+int bit_length(int64_t v) {
+  int b = 0;
+  for (; v > 0; v >>= 1) ++b;
+  return b;
+}
+
+std::string device_arch(int device) {
+  static std::mutex mu;
+  static std::map<int, std::string> known;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = known.find(device);
+  if (it != known.end()) return it->second;
+  hipDeviceProp_t prop;
+  std::string a = "unknown";
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+    a = prop.gcnArchName;
+    const size_t colon = a.find(':');
+    if (colon != std::string::npos) a.resize(colon);
+  }
+  known[device] = a;
+  return a;
+}
+
+int col_kernel_id(const turpy_plan* pl) {
+  if (pl->tf_kind != TURPY_TF_ANGULAR_SPECTRUM) return TURPY_TUNE_COL_FRESNEL;
+  return pl->d_as ? TURPY_TUNE_COL_AS_TABLE : TURPY_TUNE_COL_ANGULAR;
+}
+
+TuneKey col_key(const turpy_plan* pl) { return TuneKey{pl->arch, col_kernel_id(pl), pl->n, bit_length(pl->R)}; }
+TuneKey synth_key(const turpy_plan* pl) { return TuneKey{pl->arch, TURPY_TUNE_SYNTH, pl->n, bit_length(pl->P)}; }
+
+bool cached_width(const TuneKey& k, int* width) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  auto it = g_tune.find(k);
+  if (it == g_tune.end()) return false;
+  *width = it->second.width;
+  return true;
+}
+
+void store(const TuneKey& k, int width, const float us[3]) {
+  turpy_tune_entry e{};
+  std::snprintf(e.arch, sizeof(e.arch), "%s", k.arch.c_str());
+  e.kernel = k.kernel;
+  e.n = k.n;
+  e.batch_class = k.batch_class;
+  e.width = width;
+  for (int i = 0; i < 3; ++i) e.us[i] = us ? us[i] : 0.0f;
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  g_tune[k] = e;
+}
+
+void apply_cached_widths(turpy_plan* pl) {
+  int w = 0;
+  if (cached_width(col_key(pl), &w)) pl->col_width = w;
+  if (cached_width(synth_key(pl), &w)) pl->synth_width = w;
+}
+
+// Microseconds per launch of `launch(K)` for each width built for n (0 for
+// the others): one launch, then three loops of about 2 ms, minimum per launch.
+template <class Launch>
+turpy_status time_widths(int n, hipStream_t st, float us[3], Launch&& launch) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  for (int i = 0; e == hipSuccess && i < 3; ++i) {
+    us[i] = 0.0f;
+    if (!strip_fits_rt(n, kWidths[i])) continue;
+    float ms = 0.0f;
+    e = hipEventRecord(e0, st);
+    if (e == hipSuccess) e = launch(kWidths[i]);
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    const int reps = std::min(50, std::max(2, static_cast<int>(2.0f / std::max(ms, 1e-3f))));
+    float best = 0.0f;
+    for (int rep = 0; e == hipSuccess && rep < 3; ++rep) {
+      e = hipEventRecord(e0, st);
+      for (int k = 0; e == hipSuccess && k < reps; ++k) e = launch(kWidths[i]);
+      if (e == hipSuccess) e = hipEventRecord(e1, st);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      const float per = 1000.0f * ms / reps;
+      if (e == hipSuccess && (rep == 0 || per < best)) best = per;
+    }
+    us[i] = best;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  return e == hipSuccess ? TURPY_OK : hip_fail(e, "plan_tune: timed launch");
+}
+
+int fastest(const float us[3]) {
+  int best = 0;
+  for (int i = 0; i < 3; ++i)
+    if (us[i] > 0 && (best == 0 || us[i] < us[best - 1])) best = i + 1;
+  return best ? kWidths[best - 1] : 0;
+}
+
+}  // namespace
+
+std::string turpy::tune_signature(const turpy_plan* pl) {
+  const TuneKey c = col_key(pl), s = synth_key(pl);
+  char buf[96];
+  std::snprintf(buf, sizeof(buf), "%s/%d/%d/%d/%d/%d", c.arch.c_str(), c.kernel, c.n, c.batch_class,
+                pl->M > 0 ? s.batch_class : 0, pl->M > 0 ? 1 : 0);
+  return buf;
+}
+
+extern "C" {
+
+turpy_status turpy_plan_tune(turpy_plan* pl, uint32_t flags, void* ws, size_t ws_bytes, void* stream,
+                             int32_t* col_width, int32_t* synth_width) {
+  if (!pl) return fail(TURPY_E_INVALID, "plan_tune: NULL plan");
+  if (!ws || ws_bytes < pl->ws_tune())
+    return fail(TURPY_E_WORKSPACE, "plan_tune: workspace %zu < %zu bytes", ws_bytes, pl->ws_tune());
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  TURPY_HIP(hipStreamIsCapturing(st, &cap), "plan_tune: stream state");
+  if (cap != hipStreamCaptureStatusNone) return fail(TURPY_E_INVALID, "plan_tune: the stream is capturing");
+  const bool force = (flags & TURPY_TUNE_FORCE) != 0;
+  const TuneKey ck = col_key(pl), sk = synth_key(pl);
+  int w = 0;
+  const bool need_col = force || !cached_width(ck, &w);
+  const bool need_synth = pl->M > 0 && (force || !cached_width(sk, &w));
+  if (need_col || need_synth) TURPY_HIP(hipMemsetAsync(ws, 0, pl->ws_tune(), st), "plan_tune: clear workspace");
+  const Ws wsp = carve(pl, ws);
+  float us[3];
+  if (need_col) {
+    const int64_t plane = static_cast<int64_t>(pl->n) * pl->n;
+    ColArgs c = col_args(pl, 0, wsp.gbuf, plane, wsp.gbuf, pl->R, false);
+    if (turpy_status s = time_widths(pl->n, st, us, [&](int k) {
+          c.width = k;
+          return launch_col(pl->n, c, st);
+        }))
+      return s;
+    store(ck, fastest(us), us);
+  }
+  if (need_synth) {
+    SynthArgs a = synth_args(pl, 0, 0, 0, nullptr, wsp);
+    a.t_dev = nullptr;
+    if (turpy_status s = time_widths(pl->n, st, us, [&](int k) {
+          a.width = k;
+          return launch_synth(pl->n, a, st);
+        }))
+      return s;
+    store(sk, fastest(us), us);
+  }
+  if (cached_width(ck, &w)) pl->col_width = w;
+  if (pl->M > 0 && cached_width(sk, &w)) pl->synth_width = w;
+  return turpy_plan_widths(pl, col_width, synth_width);
+}
+
+turpy_status turpy_plan_widths(const turpy_plan* pl, int32_t* col_width, int32_t* synth_width) {
+  if (!pl) return fail(TURPY_E_INVALID, "plan_widths: NULL plan");
+  if (col_width) *col_width = pl->col_width ? pl->col_width : default_col_width(pl->n);
+  if (synth_width) *synth_width = pl->synth_width ? pl->synth_width : default_synth_width(pl->n);
+  return TURPY_OK;
+}
+
+turpy_status turpy_plan_set_widths(turpy_plan* pl, int32_t col_width, int32_t synth_width) {
+  if (!pl) return fail(TURPY_E_INVALID, "plan_set_widths: NULL plan");
+  for (int32_t k : {col_width, synth_width})
+    if (k != 0 && !strip_fits_rt(pl->n, k))
+      return fail(TURPY_E_INVALID, "plan_set_widths: %d columns per block is not built for n=%d", k, pl->n);
+  pl->col_width = col_width;
+  pl->synth_width = synth_width;
+  return TURPY_OK;
+}
+
+turpy_status turpy_tune_cache_get(turpy_tune_entry* entries, int32_t capacity, int32_t* count) {
+  if (!count || capacity < 0 || (capacity > 0 && !entries))
+    return fail(TURPY_E_INVALID, "tune_cache_get: NULL argument or negative capacity");
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  int32_t i = 0;
+  for (const auto& kv : g_tune) {
+    if (i < capacity) entries[i] = kv.second;
+    ++i;
+  }
+  *count = i;
+  return TURPY_OK;
+}
+
+turpy_status turpy_tune_cache_put(const turpy_tune_entry* entries, int32_t count) {
+  if (count < 0 || (count > 0 && !entries)) return fail(TURPY_E_INVALID, "tune_cache_put: NULL entries");
+  for (int32_t i = 0; i < count; ++i) {
+    const turpy_tune_entry& e = entries[i];
+    if (e.kernel < TURPY_TUNE_COL_FRESNEL || e.kernel > TURPY_TUNE_SYNTH)
+      return fail(TURPY_E_INVALID, "tune_cache_put: entry %d has unknown kernel %d", i, e.kernel);
+    if (!strip_fits_rt(e.n, e.width) || e.n < 16 || e.n > 2048 || !pow2(e.n))
+      return fail(TURPY_E_INVALID, "tune_cache_put: entry %d: width %d is not built for n=%d", i, e.width, e.n);
+    if (e.batch_class < 1 || e.batch_class > 63)
+      return fail(TURPY_E_INVALID, "tune_cache_put: entry %d has batch class %d", i, e.batch_class);
+    if (strnlen(e.arch, sizeof(e.arch)) == sizeof(e.arch))
+      return fail(TURPY_E_INVALID, "tune_cache_put: entry %d: arch is not NUL-terminated", i);
+    const TuneKey k{std::string(e.arch), e.kernel, e.n, e.batch_class};
+    store(k, e.width, e.us);
+  }
+  return TURPY_OK;
+}
+
+turpy_status turpy_tune_cache_clear(void) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  g_tune.clear();
   return TURPY_OK;
 }
 

@@ -9,6 +9,8 @@
 #include <algorithm>
 #include <cstdint>
 #include <numeric>
+#include <set>
+#include <string>
 #include <vector>
 
 #include "report.hpp"
@@ -185,8 +187,28 @@ turpy_status turpy_batch_workspace_size(const turpy_batch* b, int32_t op, size_t
     *bytes = total_ws(b, 0);
   } else if (op == TURPY_OP_PROPAGATE_BACKWARD) {
     *bytes = total_ws(b, 1);
+  } else if (op == TURPY_OP_TUNE) {
+    size_t m = 0;
+    for (const turpy_plan* p : b->plans) {
+      size_t v = 0;
+      turpy_workspace_size(p, TURPY_OP_TUNE, &v);
+      m = std::max(m, v);
+    }
+    *bytes = m;
   } else {
     return turpy::report(TURPY_E_INVALID, "batch_workspace_size: op %d is not available for batches", op);
+  }
+  return TURPY_OK;
+}
+
+turpy_status turpy_batch_tune(turpy_batch* b, uint32_t flags, void* ws, size_t ws_bytes, void* stream) {
+  if (!b) return turpy::report(TURPY_E_INVALID, "batch_tune: NULL batch");
+  std::set<std::string> done;  // keys measured by this call
+  for (turpy_plan* p : b->plans) {
+    const std::string key = turpy::tune_signature(p);
+    const uint32_t f = done.count(key) ? (flags & ~TURPY_TUNE_FORCE) : flags;
+    if (turpy_status s = turpy_plan_tune(p, f, ws, ws_bytes, stream, nullptr, nullptr)) return s;
+    done.insert(key);
   }
   return TURPY_OK;
 }

@@ -421,11 +421,10 @@ __device__ __forceinline__ float2 angular_correction(const ColArgs& a, int k0, i
   }
 }
 
-template <int N, int ANGULAR>
-__global__ __launch_bounds__(col_block<N>()) __attribute__((amdgpu_waves_per_eu(TURPY_COL_WAVES, 0)))
+template <int N, int ANGULAR, int K>
+__global__ __launch_bounds__(K * (N / kE)) __attribute__((amdgpu_waves_per_eu(TURPY_COL_WAVES, 0)))
 void col_pass_kernel(ColArgs a) {
   constexpr int T = N / kE;
-  constexpr int K = col_width<N>();
   constexpr int STRIPS = N / K;
   __shared__ float2 smem[ColLds<K>::words(N)];
   const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
@@ -466,11 +465,10 @@ void col_pass_kernel(ColArgs a) {
 // Column half of the screen synthesis: noise x PSD weight (Eq. S16/S17), or a
 // stored spectrum, then the unnormalised inverse transform along y.
 // ---------------------------------------------------------------------------
-template <int N>
-__global__ __launch_bounds__(synth_block<N>()) __attribute__((amdgpu_waves_per_eu(TURPY_COL_WAVES, 0)))
+template <int N, int K>
+__global__ __launch_bounds__(K * (N / kE)) __attribute__((amdgpu_waves_per_eu(TURPY_COL_WAVES, 0)))
 void synth_col_kernel(SynthArgs a) {
   constexpr int T = N / kE;
-  constexpr int K = synth_width<N>();
   constexpr int STRIPS = N / K;
   __shared__ float2 smem[ColLds<K>::words(N)];
   const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
@@ -875,18 +873,33 @@ hipError_t row_launch(const RowArgs& a, int64_t pairs, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <int N, int K>
+hipError_t col_launch_k(const ColArgs& a, hipStream_t s) {
+  if constexpr (!strip_fits<N, K>()) {
+    return hipErrorInvalidValue;
+  } else {
+    const uint64_t blocks = static_cast<uint64_t>(N / K) * a.R;
+    const dim3 grid(static_cast<uint32_t>(blocks)), block(K * (N / kE));
+    if (!a.angular)
+      hipLaunchKernelGGL((col_pass_kernel<N, TF_FRESNEL_ONLY, K>), grid, block, 0, s, a);
+    else if (a.as_table)
+      hipLaunchKernelGGL((col_pass_kernel<N, TF_AS_TABLE, K>), grid, block, 0, s, a);
+    else
+      hipLaunchKernelGGL((col_pass_kernel<N, TF_AS_FP32, K>), grid, block, 0, s, a);
+    return hipGetLastError();
+  }
+}
+
+// Strip width a.width (4, 8 or 16 columns per block), or the built-in choice
+// for N when a.width is 0.
 template <int N>
 hipError_t col_launch(const ColArgs& a, hipStream_t s) {
-  constexpr int K = col_width<N>();
-  const uint64_t blocks = static_cast<uint64_t>(N / K) * a.R;
-  const dim3 grid(static_cast<uint32_t>(blocks)), block(col_block<N>());
-  if (!a.angular)
-    hipLaunchKernelGGL((col_pass_kernel<N, TF_FRESNEL_ONLY>), grid, block, 0, s, a);
-  else if (a.as_table)
-    hipLaunchKernelGGL((col_pass_kernel<N, TF_AS_TABLE>), grid, block, 0, s, a);
-  else
-    hipLaunchKernelGGL((col_pass_kernel<N, TF_AS_FP32>), grid, block, 0, s, a);
-  return hipGetLastError();
+  switch (a.width ? a.width : col_width<N>()) {
+    case 4: return col_launch_k<N, 4>(a, s);
+    case 8: return col_launch_k<N, 8>(a, s);
+    case 16: return col_launch_k<N, 16>(a, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 template <int N>
@@ -908,12 +921,25 @@ hipError_t col_pair_launch(const ColArgs& a, const SynthArgs& syn, int do_synth,
   return hipGetLastError();
 }
 
+template <int N, int K>
+hipError_t synth_launch_k(const SynthArgs& a, hipStream_t s) {
+  if constexpr (!strip_fits<N, K>()) {
+    return hipErrorInvalidValue;
+  } else {
+    const uint64_t blocks = static_cast<uint64_t>(N / K) * a.P;
+    hipLaunchKernelGGL((synth_col_kernel<N, K>), dim3(static_cast<uint32_t>(blocks)), dim3(K * (N / kE)), 0, s, a);
+    return hipGetLastError();
+  }
+}
+
 template <int N>
 hipError_t synth_launch(const SynthArgs& a, hipStream_t s) {
-  constexpr int K = synth_width<N>();
-  const uint64_t blocks = static_cast<uint64_t>(N / K) * a.P;
-  hipLaunchKernelGGL(synth_col_kernel<N>, dim3(static_cast<uint32_t>(blocks)), dim3(synth_block<N>()), 0, s, a);
-  return hipGetLastError();
+  switch (a.width ? a.width : synth_width<N>()) {
+    case 4: return synth_launch_k<N, 4>(a, s);
+    case 8: return synth_launch_k<N, 8>(a, s);
+    case 16: return synth_launch_k<N, 16>(a, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace

@@ -57,6 +57,7 @@ struct ColArgs {
   const float2* as_table;   // [N^2/2 + 1]: H_as / H_fresnel at q = k0^2 + k1^2 (signed bins), or NULL
   float as_b;               // (2 pi df)^2 / k^2: kappa^2 / k^2 per unit of q
   float as_c;               // -dz (2 pi df)^4 / (4 pi k^3): revolutions per q^2 / (1 + sqrt(1 - B q))^2
+  int width;                // columns per block (4, 8, 16), 0: the built-in choice for N
 };
 
 struct SynthArgs {
@@ -76,6 +77,7 @@ struct SynthArgs {
   // spectra source (ROW_SCRATCH from stored spectra) instead of noise
   const float2* spectra;    // [P][M][N][N] radians, or NULL for synthesis
   int M;
+  int width;                // columns per block (4, 8, 16), 0: the built-in choice for N
 };
 
 struct ShArgs {

@@ -34,20 +34,30 @@ constexpr int row_block() { return row_groups<N>() * (N / kE); }
 #define TURPY_COL_WAVES 0
 #endif
 // Columns per block of the column pass and of the screen synthesis, per grid
-// size: the fastest of 4, 8 and 16 measured on MI355X at constant R N^2
-// (column pass: 16 up to N = 512, 8 above; synthesis, whose VALU load per
-// element is higher, 4 from N = 1024).  At N = 2048 a 16-column strip does
-// not fit one block.
+// size, when no tuned choice is set: the fastest of 4, 8 and 16 measured on
+// MI355X at constant R N^2 (column pass: 16 up to N = 512, 8 above;
+// synthesis, whose VALU load per element is higher, 4 from N = 1024).
+constexpr int default_col_width(int n) { return n >= 1024 ? 8 : (n >= 256 ? 16 : 8); }
+constexpr int default_synth_width(int n) { return n >= 1024 ? 4 : default_col_width(n); }
 template <int N>
-constexpr int col_width() {
-  return N >= 1024 ? 8 : (N >= 256 ? 16 : (N < 8 ? N : 8));
-}
+constexpr int col_width() { return default_col_width(N); }
 template <int N>
 constexpr int col_block() { return col_width<N>() * (N / kE); }
 template <int N>
-constexpr int synth_width() { return N >= 1024 ? 4 : col_width<N>(); }
-template <int N>
-constexpr int synth_block() { return synth_width<N>() * (N / kE); }
+constexpr int synth_width() { return default_synth_width(N); }
+
+// A strip of K columns is built for grid size N when its block (K N / 16
+// threads) stays within 1024 threads and its LDS (K N complex words beside
+// the N-entry twiddle and chirp tables) within the 160 KiB of a CU.  At
+// N = 2048 this excludes 16 columns.
+template <int N, int K>
+constexpr bool strip_fits() {
+  return K <= N && K * (N / kE) <= 1024 && (static_cast<long>(K) * N + 2L * N) * 8 <= 160L * 1024;
+}
+constexpr bool strip_fits_rt(int n, int k) {
+  return (k == 4 || k == 8 || k == 16) && k <= n && k * (n / kE) <= 1024 &&
+         (static_cast<long>(k) * n + 2L * n) * 8 <= 160L * 1024;
+}
 
 // Row-pair pass: each half of a block (whole waves for N >= 64) carries one
 // realization of a pair over `pair_rows` rows.

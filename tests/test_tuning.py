@@ -1,0 +1,94 @@
+"""The strip-width tuning cache of the C-ABI library (host memory only: no
+GPU is touched): entries go in and come out by key, invalid ones are refused,
+and the JSON file form round-trips."""
+import json
+import os
+
+import pytest
+
+from paper_2604_07248_amd import binding as B
+
+
+@pytest.fixture
+def cache():
+    if not os.path.exists(B.LIB_PATH):
+        pytest.fail("libturpy.so is not built (run __graft_entry__.build())")
+    from paper_2604_07248_amd import api
+    api.tune_cache_clear()
+    yield api
+    api.tune_cache_clear()
+
+
+def entry(kernel="col_fresnel", n=1024, batch_class=7, width=8, arch="gfx950", us=(300.0, 240.0, 280.0)):
+    return {"arch": arch, "kernel": kernel, "n": n, "batch_class": batch_class, "width": width, "us": list(us)}
+
+
+def test_put_get_in_key_order_and_replace(cache):
+    assert cache.tune_cache() == []
+    es = [entry("synth", 1024, 6, 4, us=(87.0, 92.0, 126.0)), entry(), entry("col_angular", 256, 3, 16)]
+    B.tune_cache_put(es)
+    got = cache.tune_cache()
+    assert len(got) == 3
+    # key order: arch, kernel, n, batch class
+    assert [(g["kernel"], g["n"]) for g in got] == [("col_fresnel", 1024), ("col_angular", 256), ("synth", 1024)]
+    for g in got:
+        ref = next(e for e in es if e["kernel"] == g["kernel"])
+        assert g["width"] == ref["width"] and g["batch_class"] == ref["batch_class"] and g["arch"] == "gfx950"
+        assert g["us"] == pytest.approx(ref["us"])
+    # same key: replaced, not added
+    B.tune_cache_put([entry(width=4, us=(1.0, 2.0, 3.0))])
+    got = cache.tune_cache()
+    assert len(got) == 3 and got[0]["width"] == 4
+    # another architecture or batch class is another key
+    B.tune_cache_put([entry(arch="gfx942"), entry(batch_class=5)])
+    assert len(cache.tune_cache()) == 5
+
+
+@pytest.mark.parametrize("bad,needle", [
+    (dict(n=2048, width=16), "not built"),   # 16 columns of 2048 rows exceed one block
+    (dict(width=5), "not built"),
+    (dict(n=100), "not built"),
+    (dict(n=4096, width=4), "not built"),
+    (dict(kernel=9), "unknown kernel"),
+    (dict(batch_class=0), "batch class"),
+])
+def test_invalid_entries_refused(cache, bad, needle):
+    B.tune_cache_put([entry(batch_class=3)])
+    with pytest.raises(B.TurpyError) as e:
+        B.tune_cache_put([entry(**bad)])
+    assert e.value.status == B.E_INVALID and needle in str(e.value)
+    assert len(cache.tune_cache()) == 1
+    with pytest.raises(ValueError):
+        B.tune_cache_put([entry(arch="x" * 40)])
+
+
+def test_widths_built_per_grid_size(cache):
+    """Every width is accepted where it fits and refused where it does not:
+    K N / 16 threads <= 1024 and (K N + 2 N) complex words <= 160 KiB."""
+    for n in (16, 32, 64, 128, 256, 512, 1024, 2048):
+        for k in (4, 8, 16):
+            fits = k <= n and k * n // 16 <= 1024 and (k * n + 2 * n) * 8 <= 160 * 1024
+            if fits:
+                B.tune_cache_put([entry(n=n, width=k)])
+            else:
+                with pytest.raises(B.TurpyError):
+                    B.tune_cache_put([entry(n=n, width=k)])
+    assert len(cache.tune_cache()) == 8  # one key per n
+
+
+def test_json_round_trip(cache, tmp_path):
+    es = [entry(), entry("synth", 2048, 2, 4, us=(98.0, 129.0, 0.0)), entry("col_as_table", 64, 2, 16)]
+    B.tune_cache_put(es)
+    path = tmp_path / "tune.json"
+    cache.tune_cache_save(str(path))
+    doc = json.loads(path.read_text())
+    assert doc["format"] == "turpy-tune-cache" and doc["version"] == 1 and len(doc["entries"]) == 3
+    before = cache.tune_cache()
+    cache.tune_cache_clear()
+    assert cache.tune_cache() == []
+    assert cache.tune_cache_load(str(path)) == 3
+    assert cache.tune_cache() == before
+    bad = tmp_path / "bad.json"
+    bad.write_text(json.dumps({"format": "other", "version": 1, "entries": []}))
+    with pytest.raises(ValueError):
+        cache.tune_cache_load(str(bad))
