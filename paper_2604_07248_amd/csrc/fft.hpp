@@ -109,11 +109,18 @@ __device__ __forceinline__ void dft(float2* v) {
 }
 
 // LDS addressing of one row transform: one pad slot per 16 elements keeps the
-// stride-16 Stockham scatters free of bank conflicts.
+// stride-16 Stockham scatters free of bank conflicts.  For a group of T
+// threads (T a multiple of 16) element t + T m sits at strided(t)[m * step],
+// one base address and immediate offsets.
 struct RowLds {
   float2* base;
   __device__ __forceinline__ float2& operator[](int i) const { return base[i + (i >> 4)]; }
   static constexpr int words(int n) { return n + n / 16; }
+  template <int T>
+  static constexpr bool strided_ok() { return T % 16 == 0; }
+  template <int T>
+  static constexpr int step() { return T + T / 16; }
+  __device__ __forceinline__ float2* strided(int t) const { return base + t + (t >> 4); }
 };
 
 // LDS addressing of a strip of K columns transformed along the row index:
@@ -124,7 +131,25 @@ struct ColLds {
   int c;
   __device__ __forceinline__ float2& operator[](int i) const { return base[i * K + c]; }
   static constexpr int words(int n) { return n * K; }
+  template <int T>
+  static constexpr bool strided_ok() { return true; }
+  template <int T>
+  static constexpr int step() { return T * K; }
+  __device__ __forceinline__ float2* strided(int t) const { return base + t * K + c; }
 };
+
+// Read the strided layout x[m] = element t + T m back from LDS.
+template <int T, int E, class Lds>
+__device__ __forceinline__ void lds_gather(float2 (&x)[E], const Lds& lds, int t) {
+  if constexpr (Lds::template strided_ok<T>()) {
+    const float2* p = lds.strided(t);
+#pragma unroll
+    for (int m = 0; m < E; ++m) x[m] = p[m * Lds::template step<T>()];
+  } else {
+#pragma unroll
+    for (int m = 0; m < E; ++m) x[m] = lds[t + T * m];
+  }
+}
 
 // Ordering of an LDS exchange.  A transform whose T threads sit inside one
 // wavefront (T <= 64, groups aligned to the wave) needs no block barrier: the
@@ -192,8 +217,7 @@ __device__ __forceinline__ void stockham_pass_tw(float2 (&x)[E], const Lds& lds,
   }
   if constexpr (!LAST) {
     lds_sync<WAVE>();
-#pragma unroll
-    for (int m = 0; m < E; ++m) x[m] = lds[t + T * m];
+    lds_gather<T>(x, lds, t);
     lds_sync<WAVE>();
   }
 }
@@ -234,8 +258,7 @@ __device__ __forceinline__ void stockham_pass(float2 (&x)[E], const Lds& lds, in
   }
   if constexpr (!LAST) {
     lds_sync<WAVE>();
-#pragma unroll
-    for (int m = 0; m < E; ++m) x[m] = lds[t + T * m];
+    lds_gather<T>(x, lds, t);
     lds_sync<WAVE>();
   }
 }

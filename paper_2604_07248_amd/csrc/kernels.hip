@@ -65,7 +65,7 @@ void row_pass_kernel(RowArgs a) {
     float2 z[kE];
     const float2* src = a.scratch + j * plane + row_off;
 #pragma unroll
-    for (int m = 0; m < kE; ++m) z[m] = src[t + T * m];
+    for (int m = 0; m < kE; ++m) z[m] = (src + t)[T * m];
     fft<N, kE, true, WV>(z, lds, t, tw);
     if (a.sh_levels > 0) {
       const float2* c = a.sh + (static_cast<size_t>(j) * a.M + a.screen) * 32;
@@ -85,7 +85,7 @@ void row_pass_kernel(RowArgs a) {
         const float2 sb = c_sub(dp, dm);
 #pragma unroll
         for (int m = 0; m < kE; ++m) {
-          const float2 ex = ph[t + T * m];
+          const float2 ex = (ph + t)[T * m];
           z[m].x += d0.x + sa.x * ex.x - sb.y * ex.y;
           z[m].y += d0.y + sa.y * ex.x + sb.x * ex.y;
         }
@@ -101,11 +101,11 @@ void row_pass_kernel(RowArgs a) {
     const int64_t ra = 2 * j, rb = 2 * j + 1;
     const float* sa = a.screens + (static_cast<size_t>(ra) * a.M + a.screen) * plane + row_off;
 #pragma unroll
-    for (int m = 0; m < kE; ++m) pa[m] = sa[t + T * m] * inv2pi;
+    for (int m = 0; m < kE; ++m) pa[m] = (sa + t)[T * m] * inv2pi;
     if (rb < a.R) {
       const float* sb = a.screens + (static_cast<size_t>(rb) * a.M + a.screen) * plane + row_off;
 #pragma unroll
-      for (int m = 0; m < kE; ++m) pb[m] = sb[t + T * m] * inv2pi;
+      for (int m = 0; m < kE; ++m) pb[m] = (sb + t)[T * m] * inv2pi;
     }
   }
 
@@ -117,7 +117,7 @@ void row_pass_kernel(RowArgs a) {
       float* dst = a.phase_out + (static_cast<size_t>(r) * a.M + a.screen) * plane + row_off;
       const float* ph = b ? pb : pa;
 #pragma unroll
-      for (int m = 0; m < kE; ++m) dst[t + T * m] = ph[m] * two_pi;
+      for (int m = 0; m < kE; ++m) (dst + t)[T * m] = ph[m] * two_pi;
     }
   }
   if (!a.in) return;  // uniform over the block
@@ -128,12 +128,12 @@ void row_pass_kernel(RowArgs a) {
     float2 x[kE];
     const float2* src = a.in + r * a.in_stride + row_off;
 #pragma unroll
-    for (int m = 0; m < kE; ++m) x[m] = src[t + T * m];
+    for (int m = 0; m < kE; ++m) x[m] = (src + t)[T * m];
     if (a.in_spectral) {
       if (a.pre) {
 #pragma unroll
         for (int m = 0; m < kE; ++m) {
-          const float2 h = a.pre[t + T * m];
+          const float2 h = (a.pre + t)[T * m];
           x[m] = a.conj_tables ? c_mulc(x[m], h) : c_mul(x[m], h);
         }
       }
@@ -152,18 +152,18 @@ void row_pass_kernel(RowArgs a) {
         }
         if (a.ckpt_out) {
 #pragma unroll
-          for (int m = 0; m < kE; ++m) a.ckpt_out[cw + t + T * m] = x[m];
+          for (int m = 0; m < kE; ++m) (a.ckpt_out + cw + t)[T * m] = x[m];
         }
       } else {
         if (a.ckpt_out) {  // the forward field at this screen, rebuilt by the adjoint chain
 #pragma unroll
-          for (int m = 0; m < kE; ++m) a.ckpt_out[cw + t + T * m] = x[m];
+          for (int m = 0; m < kE; ++m) (a.ckpt_out + cw + t)[T * m] = x[m];
         }
         if (a.grad_screens) {
 #pragma unroll
           for (int m = 0; m < kE; ++m) {
-            const float2 w = a.ckpt_in[cw + t + T * m];
-            a.grad_screens[ck + t + T * m] = w.x * x[m].y - w.y * x[m].x;  // Im(conj(W) g)
+            const float2 w = (a.ckpt_in + cw + t)[T * m];
+            (a.grad_screens + ck + t)[T * m] = w.x * x[m].y - w.y * x[m].x;  // Im(conj(W) g)
           }
         }
 #pragma unroll
@@ -184,14 +184,14 @@ void row_pass_kernel(RowArgs a) {
       if (a.post) {
 #pragma unroll
         for (int m = 0; m < kE; ++m) {
-          const float2 h = a.post[t + T * m];
+          const float2 h = (a.post + t)[T * m];
           x[m] = a.conj_tables ? c_mulc(x[m], h) : c_mul(x[m], h);
         }
       }
     }
     float2* dst = a.out + r * plane + row_off;
 #pragma unroll
-    for (int m = 0; m < kE; ++m) dst[t + T * m] = x[m];
+    for (int m = 0; m < kE; ++m) (dst + t)[T * m] = x[m];
   }
 }
 
@@ -230,29 +230,35 @@ void row_pair_kernel(RowArgs a) {
 
   float ph[kE];
   float2 x[kE];
+  float2 y[kE];  // half A's field row, fetched with its screen row (scratch mode)
   // stage 1: A -> screen row (scratch) or its phases (materialised); B -> its field row
   if (role == 0) {
     if constexpr (SCREEN == ROW_SCRATCH) {
       const float2* src = a.scratch + j * plane + row_off;
 #pragma unroll
-      for (int m = 0; m < kE; ++m) x[m] = src[t + T * m];
+      for (int m = 0; m < kE; ++m) x[m] = (src + t)[T * m];
+      if (TURPY_ROW_PREFETCH) {
+        const float2* fa = a.in + r * a.in_stride + row_off;
+#pragma unroll
+        for (int m = 0; m < kE; ++m) y[m] = (fa + t)[T * m];
+      }
       fft<N, kE, true, WV>(x, lds, t, tw);
     } else {
       constexpr float inv2pi = 0.15915494309189535f;
       const float* sa = a.screens + (static_cast<size_t>(r) * a.M + a.screen) * plane + row_off;
 #pragma unroll
-      for (int m = 0; m < kE; ++m) ph[m] = sa[t + T * m] * inv2pi;
+      for (int m = 0; m < kE; ++m) ph[m] = (sa + t)[T * m] * inv2pi;
       if (in_spec) idle_fft<N, WV>();
     }
   } else {
     const float2* src = a.in + r * a.in_stride + row_off;
 #pragma unroll
-    for (int m = 0; m < kE; ++m) x[m] = src[t + T * m];
+    for (int m = 0; m < kE; ++m) x[m] = (src + t)[T * m];
     if (in_spec) {
       if (a.pre) {
 #pragma unroll
         for (int m = 0; m < kE; ++m) {
-          const float2 h = a.pre[t + T * m];
+          const float2 h = (a.pre + t)[T * m];
           x[m] = a.conj_tables ? c_mulc(x[m], h) : c_mul(x[m], h);
         }
       }
@@ -284,7 +290,7 @@ void row_pair_kernel(RowArgs a) {
           const float2 sb = c_sub(dp, dm);
 #pragma unroll
           for (int m = 0; m < kE; ++m) {
-            const float2 ex = phs[t + T * m];
+            const float2 ex = (phs + t)[T * m];
             x[m].x += d0.x + sa.x * ex.x - sb.y * ex.y;
             x[m].y += d0.y + sa.y * ex.x + sb.x * ex.y;
           }
@@ -293,13 +299,13 @@ void row_pair_kernel(RowArgs a) {
 #pragma unroll
       for (int m = 0; m < kE; ++m) {
         ph[m] = x[m].x;
-        handoff[t + T * m] = x[m].y;
+        (handoff + t)[T * m] = x[m].y;
       }
     }
     __syncthreads();
     if (role == 1) {
 #pragma unroll
-      for (int m = 0; m < kE; ++m) ph[m] = handoff[t + T * m];
+      for (int m = 0; m < kE; ++m) ph[m] = (handoff + t)[T * m];
     }
     __syncthreads();
   } else {
@@ -307,7 +313,7 @@ void row_pair_kernel(RowArgs a) {
       constexpr float inv2pi = 0.15915494309189535f;
       const float* sb = a.screens + (static_cast<size_t>(r) * a.M + a.screen) * plane + row_off;
 #pragma unroll
-      for (int m = 0; m < kE; ++m) ph[m] = sb[t + T * m] * inv2pi;
+      for (int m = 0; m < kE; ++m) ph[m] = (sb + t)[T * m] * inv2pi;
     }
   }
 
@@ -324,18 +330,18 @@ void row_pair_kernel(RowArgs a) {
       }
       if (a.ckpt_out && writes) {
 #pragma unroll
-        for (int m = 0; m < kE; ++m) a.ckpt_out[cw + t + T * m] = x[m];
+        for (int m = 0; m < kE; ++m) (a.ckpt_out + cw + t)[T * m] = x[m];
       }
     } else {
       if (a.ckpt_out && writes) {  // the forward field at this screen, rebuilt by the adjoint chain
 #pragma unroll
-        for (int m = 0; m < kE; ++m) a.ckpt_out[cw + t + T * m] = x[m];
+        for (int m = 0; m < kE; ++m) (a.ckpt_out + cw + t)[T * m] = x[m];
       }
       if (a.grad_screens && writes) {
 #pragma unroll
         for (int m = 0; m < kE; ++m) {
-          const float2 w = a.ckpt_in[cw + t + T * m];
-          a.grad_screens[ck + t + T * m] = w.x * x[m].y - w.y * x[m].x;  // Im(conj(W) g)
+          const float2 w = (a.ckpt_in + cw + t)[T * m];
+          (a.grad_screens + ck + t)[T * m] = w.x * x[m].y - w.y * x[m].x;  // Im(conj(W) g)
         }
       }
 #pragma unroll
@@ -350,7 +356,7 @@ void row_pair_kernel(RowArgs a) {
       if (a.post) {
 #pragma unroll
         for (int m = 0; m < kE; ++m) {
-          const float2 h = a.post[t + T * m];
+          const float2 h = (a.post + t)[T * m];
           x[m] = a.conj_tables ? c_mulc(x[m], h) : c_mul(x[m], h);
         }
       }
@@ -358,20 +364,25 @@ void row_pair_kernel(RowArgs a) {
     if (writes) {
       float2* dst = a.out + r * static_cast<int64_t>(plane) + row_off;
 #pragma unroll
-      for (int m = 0; m < kE; ++m) dst[t + T * m] = x[m];
+      for (int m = 0; m < kE; ++m) (dst + t)[T * m] = x[m];
     }
   };
 
   // stage 3: A loads / inverse-transforms its field; B finishes
   if (role == 0) {
-    const float2* src = a.in + r * a.in_stride + row_off;
+    if (SCREEN == ROW_SCRATCH && TURPY_ROW_PREFETCH) {
 #pragma unroll
-    for (int m = 0; m < kE; ++m) x[m] = src[t + T * m];
+      for (int m = 0; m < kE; ++m) x[m] = y[m];
+    } else {
+      const float2* src = a.in + r * a.in_stride + row_off;
+#pragma unroll
+      for (int m = 0; m < kE; ++m) x[m] = (src + t)[T * m];
+    }
     if (in_spec) {
       if (a.pre) {
 #pragma unroll
         for (int m = 0; m < kE; ++m) {
-          const float2 h = a.pre[t + T * m];
+          const float2 h = (a.pre + t)[T * m];
           x[m] = a.conj_tables ? c_mulc(x[m], h) : c_mul(x[m], h);
         }
       }
@@ -446,7 +457,7 @@ void col_pass_kernel(ColArgs a) {
   const float2* src = a.in + r * a.in_stride + k1;
   float2 x[kE];
 #pragma unroll
-  for (int m = 0; m < kE; ++m) x[m] = src[static_cast<size_t>(t + T * m) * N];
+  for (int m = 0; m < kE; ++m) x[m] = (src + static_cast<size_t>(t) * N)[static_cast<size_t>(T * m) * N];
   fft<N, kE, false>(x, lds, t, tw);
 #pragma unroll
   for (int m = 0; m < kE; ++m) {
@@ -458,7 +469,7 @@ void col_pass_kernel(ColArgs a) {
   fft<N, kE, true>(x, lds, t, tw);
   float2* dst = a.out + r * static_cast<int64_t>(N) * N + k1;
 #pragma unroll
-  for (int m = 0; m < kE; ++m) dst[static_cast<size_t>(t + T * m) * N] = x[m];
+  for (int m = 0; m < kE; ++m) (dst + static_cast<size_t>(t) * N)[static_cast<size_t>(T * m) * N] = x[m];
 }
 
 // ---------------------------------------------------------------------------
@@ -485,7 +496,7 @@ void synth_col_kernel(SynthArgs a) {
     constexpr float inv2pi = 0.15915494309189535f;
     const float2* src = a.spectra + (static_cast<size_t>(j) * a.M + a.screen) * N * N + k1;
 #pragma unroll
-    for (int m = 0; m < kE; ++m) x[m] = c_scale(src[static_cast<size_t>(t + T * m) * N], inv2pi);
+    for (int m = 0; m < kE; ++m) x[m] = c_scale((src + static_cast<size_t>(t) * N)[static_cast<size_t>(T * m) * N], inv2pi);
   } else {
     const int kx = signed_bin(k1, N);
 #pragma unroll
@@ -505,7 +516,7 @@ void synth_col_kernel(SynthArgs a) {
   fft<N, kE, true>(x, lds, t, tw);
   float2* dst = a.scratch + j * static_cast<int64_t>(N) * N + k1;
 #pragma unroll
-  for (int m = 0; m < kE; ++m) dst[static_cast<size_t>(t + T * m) * N] = x[m];
+  for (int m = 0; m < kE; ++m) (dst + static_cast<size_t>(t) * N)[static_cast<size_t>(T * m) * N] = x[m];
 }
 
 // ---------------------------------------------------------------------------
@@ -524,7 +535,7 @@ __device__ __forceinline__ void synth_column(float2 (&z)[kE], const SynthArgs& a
     constexpr float inv2pi = 0.15915494309189535f;
     const float2* src = a.spectra + (static_cast<size_t>(j) * a.M + a.screen) * N * N + k1;
 #pragma unroll
-    for (int m = 0; m < kE; ++m) z[m] = c_scale(src[static_cast<size_t>(t + T * m) * N], inv2pi);
+    for (int m = 0; m < kE; ++m) z[m] = c_scale((src + static_cast<size_t>(t) * N)[static_cast<size_t>(T * m) * N], inv2pi);
   } else {
     const int kx = signed_bin(k1, N);
 #pragma unroll
@@ -577,7 +588,7 @@ void col_pair_kernel(ColArgs a, SynthArgs syn) {
   const float2* sa = a.in + ra * a.in_stride + k1;
 #if TURPY_COL_PREFETCH
 #pragma unroll
-  for (int m = 0; m < kE; ++m) x[m] = sa[static_cast<size_t>(t + T * m) * N];
+  for (int m = 0; m < kE; ++m) x[m] = (sa + static_cast<size_t>(t) * N)[static_cast<size_t>(T * m) * N];
 #endif
   if constexpr (SYNTH) {
     float2 z[kE];
@@ -585,28 +596,28 @@ void col_pair_kernel(ColArgs a, SynthArgs syn) {
     fft<N, kE, true>(z, lds, t, tw);
     float2* dz = syn.scratch + j * static_cast<int64_t>(plane) + k1;
 #pragma unroll
-    for (int m = 0; m < kE; ++m) dz[static_cast<size_t>(t + T * m) * N] = z[m];
+    for (int m = 0; m < kE; ++m) (dz + static_cast<size_t>(t) * N)[static_cast<size_t>(T * m) * N] = z[m];
   }
 #if !TURPY_COL_PREFETCH
 #pragma unroll
-  for (int m = 0; m < kE; ++m) x[m] = sa[static_cast<size_t>(t + T * m) * N];
+  for (int m = 0; m < kE; ++m) x[m] = (sa + static_cast<size_t>(t) * N)[static_cast<size_t>(T * m) * N];
 #endif
   fft<N, kE, false>(x, lds, t, tw);
   col_transfer<N, ANGULAR>(x, a, k1, t);
   fft<N, kE, true>(x, lds, t, tw);
   float2* da = a.out + ra * static_cast<int64_t>(plane) + k1;
 #pragma unroll
-  for (int m = 0; m < kE; ++m) da[static_cast<size_t>(t + T * m) * N] = x[m];
+  for (int m = 0; m < kE; ++m) (da + static_cast<size_t>(t) * N)[static_cast<size_t>(T * m) * N] = x[m];
   if (rb < a.R) {  // uniform over the block
     const float2* sb = a.in + rb * a.in_stride + k1;
 #pragma unroll
-    for (int m = 0; m < kE; ++m) x[m] = sb[static_cast<size_t>(t + T * m) * N];
+    for (int m = 0; m < kE; ++m) x[m] = (sb + static_cast<size_t>(t) * N)[static_cast<size_t>(T * m) * N];
     fft<N, kE, false>(x, lds, t, tw);
     col_transfer<N, ANGULAR>(x, a, k1, t);
     fft<N, kE, true>(x, lds, t, tw);
     float2* db = a.out + rb * static_cast<int64_t>(plane) + k1;
 #pragma unroll
-    for (int m = 0; m < kE; ++m) db[static_cast<size_t>(t + T * m) * N] = x[m];
+    for (int m = 0; m < kE; ++m) (db + static_cast<size_t>(t) * N)[static_cast<size_t>(T * m) * N] = x[m];
   }
 }
 

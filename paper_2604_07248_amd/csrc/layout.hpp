@@ -27,6 +27,9 @@ constexpr int row_block() { return row_groups<N>() * (N / kE); }
 #ifndef TURPY_CHIRP_LDS
 #define TURPY_CHIRP_LDS 1
 #endif
+#ifndef TURPY_ROW_PREFETCH
+#define TURPY_ROW_PREFETCH 1
+#endif
 #ifndef TURPY_COL_PREFETCH
 #define TURPY_COL_PREFETCH 1
 #endif

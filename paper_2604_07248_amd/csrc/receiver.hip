@@ -54,7 +54,7 @@ __global__ __launch_bounds__(row_block<N>()) void recv_row_in_kernel(RecvArgs a)
   fft<N, kE, false>(x, lds, t, tw);
   float2* dst = a.out + b * static_cast<int64_t>(N) * N + row;
 #pragma unroll
-  for (int m = 0; m < kE; ++m) dst[t + T * m] = x[m];
+  for (int m = 0; m < kE; ++m) (dst + t)[T * m] = x[m];
 }
 
 template <int N>
@@ -75,7 +75,7 @@ __global__ __launch_bounds__(col_block<N>()) void recv_col_kernel(RecvArgs a) {
   const float2* src = a.in + b * plane + k1;
   float2 x[kE];
 #pragma unroll
-  for (int m = 0; m < kE; ++m) x[m] = src[static_cast<size_t>(t + T * m) * N];
+  for (int m = 0; m < kE; ++m) x[m] = (src + static_cast<size_t>(t) * N)[static_cast<size_t>(T * m) * N];
   fft<N, kE, false>(x, lds, t, tw);
   constexpr float inv_n = 1.0f / N;
 #pragma unroll
@@ -88,7 +88,7 @@ __global__ __launch_bounds__(col_block<N>()) void recv_col_kernel(RecvArgs a) {
   fft<N, kE, true>(x, lds, t, tw);
   float2* dst = a.out + b * plane + k1;
 #pragma unroll
-  for (int m = 0; m < kE; ++m) dst[static_cast<size_t>(t + T * m) * N] = x[m];
+  for (int m = 0; m < kE; ++m) (dst + static_cast<size_t>(t) * N)[static_cast<size_t>(T * m) * N] = x[m];
 }
 
 // Column half of the adjoint.  in = row-FFT of U1 (X after the column FFT),
@@ -124,10 +124,10 @@ __global__ __launch_bounds__(col_block<N>()) void recv_col_grad_kernel(RecvArgs 
     const float2* sx = a.in + b * plane + k1;
     const float2* sg = a.in2 + b * plane + k1;
 #pragma unroll
-    for (int m = 0; m < kE; ++m) x[m] = sx[static_cast<size_t>(t + T * m) * N];
+    for (int m = 0; m < kE; ++m) x[m] = (sx + static_cast<size_t>(t) * N)[static_cast<size_t>(T * m) * N];
     fft<N, kE, false>(x, lds, t, tw);
 #pragma unroll
-    for (int m = 0; m < kE; ++m) gg[m] = sg[static_cast<size_t>(t + T * m) * N];
+    for (int m = 0; m < kE; ++m) gg[m] = (sg + static_cast<size_t>(t) * N)[static_cast<size_t>(T * m) * N];
     fft<N, kE, false>(gg, lds, t, tw);
 #pragma unroll
     for (int m = 0; m < kE; ++m) {
@@ -138,11 +138,11 @@ __global__ __launch_bounds__(col_block<N>()) void recv_col_grad_kernel(RecvArgs 
     fft<N, kE, true>(gg, lds, t, tw);
     float2* dst = a.out + b * plane + k1;
 #pragma unroll
-    for (int m = 0; m < kE; ++m) dst[static_cast<size_t>(t + T * m) * N] = gg[m];
+    for (int m = 0; m < kE; ++m) (dst + static_cast<size_t>(t) * N)[static_cast<size_t>(T * m) * N] = gg[m];
   }
   float* part = a.partial + static_cast<size_t>(chunk) * plane + k1;
 #pragma unroll
-  for (int m = 0; m < kE; ++m) part[static_cast<size_t>(t + T * m) * N] = acc[m];
+  for (int m = 0; m < kE; ++m) (part + static_cast<size_t>(t) * N)[static_cast<size_t>(T * m) * N] = acc[m];
 }
 
 // Row half of the adjoint.  in = output of recv_col_grad (row-spectral g path):
@@ -177,25 +177,25 @@ __global__ __launch_bounds__(row_block<N>()) void recv_row_grad_kernel(RecvArgs 
     float2 x[kE];
     const float2* src = a.in + b * plane + row;
 #pragma unroll
-    for (int m = 0; m < kE; ++m) x[m] = src[t + T * m];
+    for (int m = 0; m < kE; ++m) x[m] = (src + t)[T * m];
     fft<N, kE, true>(x, lds, t, tw);
     const float2* us = a.u + b * plane + row;
 #pragma unroll
     for (int m = 0; m < kE; ++m) {
       const float2 gu1 = c_scale(x[m], inv_n);
-      const float2 u1 = c_mul(us[t + T * m], w[m]);
+      const float2 u1 = c_mul((us + t)[T * m], w[m]);
       acc[m] += u1.x * gu1.y - u1.y * gu1.x;  // Im(conj(U1) g_U1)
       x[m] = c_mulc(gu1, w[m]);               // A exp(-i theta1) g_U1
     }
     if (a.out) {
       float2* dst = a.out + b * plane + row;
 #pragma unroll
-      for (int m = 0; m < kE; ++m) dst[t + T * m] = x[m];
+      for (int m = 0; m < kE; ++m) (dst + t)[T * m] = x[m];
     }
   }
   float* part = a.partial + static_cast<size_t>(chunk) * plane + row;
 #pragma unroll
-  for (int m = 0; m < kE; ++m) part[t + T * m] = acc[m];
+  for (int m = 0; m < kE; ++m) (part + t)[T * m] = acc[m];
 }
 
 __global__ __launch_bounds__(256) void recv_reduce_kernel(const float* partial, int chunks, int n, float* grad,
