@@ -952,7 +952,10 @@ turpy_status turpy_evolve(turpy_plan* pl, uint64_t seed, int64_t t, double alpha
   a.t_dev = pl->d_t;
   a.init = t == 0 ? 1 : 0;
   a.tag = t == 0 ? TAG_MAIN : TAG_AR;
-  a.alpha = alpha;
+  a.alpha_f = static_cast<float>(alpha);
+  a.blend = static_cast<float>(std::sqrt(1.0 - alpha * alpha));
+  a.log2n = 0;
+  while ((1 << a.log2n) < pl->n) ++a.log2n;
   a.sx = shift_x;
   a.sy = shift_y;
   a.amp = pl->d_amp_rad;

@@ -231,6 +231,20 @@ void row_pair_kernel(RowArgs a) {
   float ph[kE];
   float2 x[kE];
   float2 y[kE];  // half A's field row, fetched with its screen row (scratch mode)
+  // adjoint: the checkpointed forward field of this row, fetched before the
+  // transform that precedes its use in the screen gradient
+  float2 wck[kE];
+  const bool want_ck = BWD && a.grad_screens && writes;
+  const size_t ck_row = (static_cast<size_t>(r) * a.M + a.screen) * plane + row_off;
+  const size_t cw_row = a.ckpt_single ? static_cast<size_t>(r) * plane + row_off : ck_row;
+  auto fetch_ckpt = [&]() {
+    if constexpr (BWD) {
+      if (want_ck) {
+#pragma unroll
+        for (int m = 0; m < kE; ++m) wck[m] = (a.ckpt_in + cw_row + t)[T * m];
+      }
+    }
+  };
   // stage 1: A -> screen row (scratch) or its phases (materialised); B -> its field row
   if (role == 0) {
     if constexpr (SCREEN == ROW_SCRATCH) {
@@ -254,6 +268,7 @@ void row_pair_kernel(RowArgs a) {
     const float2* src = a.in + r * a.in_stride + row_off;
 #pragma unroll
     for (int m = 0; m < kE; ++m) x[m] = (src + t)[T * m];
+    fetch_ckpt();
     if (in_spec) {
       if (a.pre) {
 #pragma unroll
@@ -319,8 +334,7 @@ void row_pair_kernel(RowArgs a) {
 
   // the pointwise step of Eq. 1 (or its adjoint) and the forward transform
   auto finish = [&]() {
-    const size_t ck = (static_cast<size_t>(r) * a.M + a.screen) * plane + row_off;
-    const size_t cw = a.ckpt_single ? static_cast<size_t>(r) * plane + row_off : ck;
+    const size_t ck = ck_row, cw = cw_row;
     if constexpr (!BWD) {
 #pragma unroll
       for (int m = 0; m < kE; ++m) {
@@ -337,10 +351,10 @@ void row_pair_kernel(RowArgs a) {
 #pragma unroll
         for (int m = 0; m < kE; ++m) (a.ckpt_out + cw + t)[T * m] = x[m];
       }
-      if (a.grad_screens && writes) {
+      if (want_ck) {
 #pragma unroll
         for (int m = 0; m < kE; ++m) {
-          const float2 w = (a.ckpt_in + cw + t)[T * m];
+          const float2 w = wck[m];
           (a.grad_screens + ck + t)[T * m] = w.x * x[m].y - w.y * x[m].x;  // Im(conj(W) g)
         }
       }
@@ -378,6 +392,7 @@ void row_pair_kernel(RowArgs a) {
 #pragma unroll
       for (int m = 0; m < kE; ++m) x[m] = (src + t)[T * m];
     }
+    fetch_ckpt();
     if (in_spec) {
       if (a.pre) {
 #pragma unroll
@@ -684,23 +699,31 @@ __global__ __launch_bounds__(64) void sh_kernel(ShArgs a) {
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void evolve_kernel(EvolveArgs a) {
   const int n = a.n;
-  const int64_t half = static_cast<int64_t>(n / 2) * n;
+  const int64_t half = static_cast<int64_t>(n / 2) * n;  // a power of two
   const int64_t total = a.P * a.M * half;
   const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx >= total) return;
-  const int64_t js = idx / half;
-  const int64_t rem = idx % half;
-  const int k0 = static_cast<int>(rem / n);
-  const int k1 = static_cast<int>(rem % n);
-  const int64_t j = js / a.M;
-  const int s = static_cast<int>(js % a.M);
+  const int64_t js = idx >> (2 * a.log2n - 1);
+  const int64_t rem = idx & (half - 1);
+  const int k0 = static_cast<int>(rem >> a.log2n);
+  const int k1 = static_cast<int>(rem & (n - 1));
+  int64_t j;
+  int s;
+  if (js <= 0xFFFFFFFFll) {  // 32-bit division where it suffices
+    const uint32_t js32 = static_cast<uint32_t>(js), m32 = static_cast<uint32_t>(a.M);
+    j = js32 / m32;
+    s = static_cast<int>(js32 - static_cast<uint32_t>(j) * m32);
+  } else {
+    j = js / a.M;
+    s = static_cast<int>(js - j * a.M);
+  }
   const uint4 v = philox4x32_10(
       noise_counter(static_cast<uint32_t>(rem), time_step(a), static_cast<uint32_t>(j), a.tag, static_cast<uint32_t>(s)),
       a.key0, a.key1);
   float2* base = a.spectra + js * static_cast<int64_t>(n) * n;
   const float amp = a.amp[s];
   const int kx = signed_bin(k1, n);
-  const float blend = static_cast<float>(sqrt(1.0 - a.alpha * a.alpha));
+  const double inv_n = 1.0 / n;  // exact: n is a power of two
   for (int h = 0; h < 2; ++h) {
     const int kk0 = k0 + h * (n / 2);
     const int ky = signed_bin(kk0, n);
@@ -711,12 +734,11 @@ __global__ __launch_bounds__(256) void evolve_kernel(EvolveArgs a) {
     if (a.init) {
       out = c_scale(nc, w);
     } else {
-      double rev = -(static_cast<double>(kx) * a.sx + static_cast<double>(ky) * a.sy) / n;
+      double rev = -(static_cast<double>(kx) * a.sx + static_cast<double>(ky) * a.sy) * inv_n;
       rev -= rint(rev);
       float sn, cs;
       sincos_rev(static_cast<float>(rev), &sn, &cs);
-      const float al = static_cast<float>(a.alpha);
-      out = c_add(c_scale(c_mul(*p, make_float2(cs, sn)), al), c_scale(nc, blend * w));
+      out = c_add(c_scale(c_mul(*p, make_float2(cs, sn)), a.alpha_f), c_scale(nc, a.blend * w));
     }
     if (kk0 == 0 && k1 == 0) out = make_float2(0.0f, 0.0f);
     *p = out;

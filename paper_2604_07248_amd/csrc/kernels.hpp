@@ -100,9 +100,11 @@ struct EvolveArgs {
   int64_t P;
   int M;
   int n;
+  int log2n;
   uint32_t key0, key1, t, tag;
   const uint32_t* t_dev;    // time step read at run time when set
-  double alpha;
+  float alpha_f;            // alpha and sqrt(1 - alpha^2), rounded from FP64
+  float blend;
   double sx, sy;            // shift in pixels
   int init;                 // 1: overwrite with fresh spectra (t = 0)
   const float* amp;         // [M] sqrt(0.023) r0^(-5/6) df: radians
