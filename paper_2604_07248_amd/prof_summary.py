@@ -164,6 +164,7 @@ def load_traffic(profiles_dir, leg):
 
 
 PRE = "cd /tmp && export TMPDIR=/tmp && R=<repository root>"
+TUNE = "--tune-cache $R/gpurun_out/tune.json"
 
 
 def _ev(fams, tab):
@@ -181,9 +182,12 @@ def report(out_dir, bench_json, root="gpurun_out"):
     fwd_row = next(r for r in rows[2:] if "| row_fwd |" in r)
     d = b["roofline"]
     lines = ["# Kernel trace: forward headline workload (N=1024, R=64, M=8, fresh screens)", "",
-             "Command (one MI355X; the profiler writes its temporary files under /tmp):", "", f"    {PRE}",
+             "Commands (one MI355X; the profiler writes its temporary files under /tmp).  The first, the",
+             "default benchmark run, also writes the strip widths its tuner chose; the profiled runs read",
+             "them back, so that their traces hold no tuning launches:", "",
+             "    python bench.py --tune-cache gpurun_out/tune.json > gpurun_out/bench.json", f"    {PRE}",
              "    rocprofv3 --kernel-trace --stats --output-format csv -d $R/gpurun_out/prof_fwd -o fwd -- \\",
-             "        python $R/bench.py --only fwd --steps 10 --warmup 2", "",
+             f"        python $R/bench.py --only fwd --steps 10 --warmup 2 {TUNE}", "",
              "Summary: `python -m paper_2604_07248_amd.prof_summary stats gpurun_out/prof_fwd`.  The run covers",
              "22 forward steps: 2 warm-up, 10 with every family bracketed by events, 10 timed.  Durations in",
              "microseconds.", ""] + rows + [
@@ -197,7 +201,7 @@ def report(out_dir, bench_json, root="gpurun_out"):
     lines = ["# Kernel trace: forward + adjoint, headline workload (N=1024, R=64, M=8, checkpoints)", "",
              "Command:", "", f"    {PRE}",
              "    rocprofv3 --kernel-trace --stats --output-format csv -d $R/gpurun_out/prof_fwdbwd -o fwdbwd -- \\",
-             "        python $R/bench.py --only fwdbwd --steps 5 --warmup 2", "",
+             f"        python $R/bench.py --only fwdbwd --steps 5 --warmup 2 {TUNE}", "",
              "Summary: `python -m paper_2604_07248_amd.prof_summary stats gpurun_out/prof_fwdbwd`.", ""]
     lines += stats_table(j("prof_fwdbwd")) + [
         "", "HIP-event averages inside `bench.py` (default run): " +
@@ -211,7 +215,7 @@ def report(out_dir, bench_json, root="gpurun_out"):
         for leg in ("fwd", "copy"):
             lines.append(f"    timeout -s KILL 120 rocprofv3 --pmc {c} --output-format csv "
                          f"-d $R/gpurun_out/pmc_{c}_{leg} -o p -- \\")
-            lines.append(f"        python $R/bench.py --only {leg} --steps 3 --warmup 1")
+            lines.append(f"        python $R/bench.py --only {leg} --steps 3 --warmup 1 {TUNE}")
     lines += ["", "Summary: `python -m paper_2604_07248_amd.prof_summary traffic --fetch gpurun_out/pmc_FETCH_SIZE_fwd "
               "--write gpurun_out/pmc_WRITE_SIZE_fwd --copy-fetch gpurun_out/pmc_FETCH_SIZE_copy --copy-write "
               "gpurun_out/pmc_WRITE_SIZE_copy --copy-bytes 536870912 --leg fwd`.", "",
@@ -228,7 +232,7 @@ def report(out_dir, bench_json, root="gpurun_out"):
              f"    {PRE}",
              "    timeout -s KILL 120 rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_BUSY_CYCLES \\",
              "        SQ_WAVE_CYCLES SQ_INSTS_LDS GRBM_GUI_ACTIVE --output-format csv -d $R/gpurun_out/pmc_sq_fwd "
-             "-o p -- \\", "        python $R/bench.py --only fwd --steps 3 --warmup 1", "",
+             "-o p -- \\", f"        python $R/bench.py --only fwd --steps 3 --warmup 1 {TUNE}", "",
              "Summary: `python -m paper_2604_07248_amd.prof_summary pmc gpurun_out/pmc_sq_fwd` (per-dispatch",
              "averages).  VALU busy = SQ_INSTS_VALU x 4 cycles (a wave64 FP32 instruction on a 16-lane SIMD) /",
              "(1024 SIMDs x GRBM_GUI_ACTIVE / 8 XCDs).", "",
