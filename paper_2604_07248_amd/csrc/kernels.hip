@@ -418,6 +418,169 @@ void row_pair_kernel(RowArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Forward row pass over a realization pair with synthesised screens and no
+// checkpoint output, relay schedule.  A block holds two workers (whole waves)
+// and two row groups of pair j: group 0 = rows [i0, i0 + G), group 1 = rows
+// [i0 + G, i0 + 2G).  Each group needs five transforms: the inverse transform
+// of its screen rows (S), the inverse transforms of the field rows of
+// realizations 2j and 2j+1 (A, B), and their forward transforms after the
+// pointwise step (A', B'), which need S.  Worker 0 draws S of group 0,
+// worker 1 S of group 1, and five stages keep both workers busy (the pair
+// schedule above leaves one half idle in its last stage):
+//   stage 0: w0 S0    w1 B0
+//   stage 1: w0 A0    w1 B0'   (Im S0 handed from w0 to w1 through LDS)
+//   stage 2: w0 A0'   w1 S1
+//   stage 3: w0 B1    w1 A1
+//   stage 4: w0 B1'   w1 A1'   (Im S1 handed from w1 to w0)
+// Each worker fetches an A row together with the screen row before it.  Two
+// block barriers order the hand-offs.  Where the transforms use block
+// barriers a stage whose two transforms differ in kind passes the same
+// barriers on both sides (idle_fft).
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ __launch_bounds__(relay_block<N>()) __attribute__((amdgpu_waves_per_eu(TURPY_PAIR_WAVES, 0)))
+void row_relay_kernel(RowArgs a) {
+  constexpr int T = N / kE;
+  constexpr int G = relay_rows<N>();
+  constexpr int HALF = G * T;
+  constexpr bool WV = TURPY_WAVE_SYNC && T <= 64;  // each row's transform lives in one wavefront
+  static_assert(HALF % 64 == 0 && 2 * G <= N, "a relay worker is whole waves over half the block's rows");
+  __shared__ float2 smem[2 * G * RowLds::words(N)];
+  __shared__ float handoff_rows[G * N];
+  __shared__ float2 tw_lds[N];
+  const int w = threadIdx.x / HALF;
+  const int g = (threadIdx.x % HALF) / T;
+  const int t = threadIdx.x % T;
+  const int64_t j = blockIdx.y;
+  const bool has_b = 2 * j + 1 < a.R;
+  const int64_t ra = 2 * j, rb = has_b ? 2 * j + 1 : 2 * j;  // a missing B reads A's rows, writes nothing
+  const int row0 = blockIdx.x * 2 * G + g;  // this thread's row in group 0
+  const int row1 = row0 + G;                // and in group 1
+  const RowLds lds{smem + (w * G + g) * RowLds::words(N)};
+  float* hand = handoff_rows + g * N + t;
+  const float2* tw = stage_twiddles<N>(tw_lds, a.tw);
+  const size_t plane = static_cast<size_t>(N) * N;
+  const bool in_spec = a.in_spectral != 0, out_spec = a.out_spectral != 0;
+  const bool both = in_spec || out_spec;
+
+  float ph[kE];
+  float2 x[kE], y[kE];
+  auto load_field = [&](float2 (&v)[kE], int64_t r, int row) {
+    const float2* src = a.in + r * a.in_stride + static_cast<size_t>(row) * N + t;
+#pragma unroll
+    for (int m = 0; m < kE; ++m) v[m] = src[T * m];
+  };
+  // x (a loaded field row) to real space; slot: the other worker transforms
+  // in this stage
+  auto inverse = [&](bool slot) {
+    if (in_spec) {
+      fft<N, kE, true, WV>(x, lds, t, tw);
+    } else if (slot) {
+      idle_fft<N, WV>();
+    }
+  };
+  auto load_screen = [&](int row) {
+    const float2* src = a.scratch + j * plane + static_cast<size_t>(row) * N + t;
+#pragma unroll
+    for (int m = 0; m < kE; ++m) x[m] = src[T * m];
+  };
+  // screen row of pair j: inverse row transform of the scratch row, the
+  // subharmonics and the piston of Eq. 2-3; Re into ph, Im into the hand-off
+  auto screen = [&](int row) {
+    fft<N, kE, true, WV>(x, lds, t, tw);
+    if (a.sh_levels > 0) {
+      const float2* c = a.sh + (static_cast<size_t>(j) * a.M + a.screen) * 32;
+      const float2 mean = c_scale(c[24], a.sh_scale);
+#pragma unroll
+      for (int m = 0; m < kE; ++m) x[m] = c_sub(x[m], mean);
+      for (int p = 0; p < a.sh_levels; ++p) {
+        const float2* cp = c + 8 * p;
+        const float2* phs = a.sh_phasor + static_cast<size_t>(p) * N;
+        const float2 ey = phs[row];
+        const float2 eyc = make_float2(ey.x, -ey.y);
+        // offsets (m, n): 0 (-1,-1) 1 (-1,0) 2 (-1,1) 3 (0,-1) 4 (0,1) 5 (1,-1) 6 (1,0) 7 (1,1)
+        const float2 dm = c_scale(c_add(c_add(c_mul(cp[0], eyc), cp[3]), c_mul(cp[5], ey)), a.sh_scale);
+        const float2 d0 = c_scale(c_add(c_mul(cp[1], eyc), c_mul(cp[6], ey)), a.sh_scale);
+        const float2 dp = c_scale(c_add(c_add(c_mul(cp[2], eyc), cp[4]), c_mul(cp[7], ey)), a.sh_scale);
+        const float2 sa = c_add(dp, dm);
+        const float2 sb = c_sub(dp, dm);
+#pragma unroll
+        for (int m = 0; m < kE; ++m) {
+          const float2 ex = (phs + t)[T * m];
+          x[m].x += d0.x + sa.x * ex.x - sb.y * ex.y;
+          x[m].y += d0.y + sa.y * ex.x + sb.x * ex.y;
+        }
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < kE; ++m) {
+      ph[m] = x[m].x;
+      hand[T * m] = x[m].y;
+    }
+  };
+  // the pointwise step of Eq. 1, the forward transform and the store of
+  // realization r's row
+  auto finish = [&](int64_t r, int row, bool writes, bool slot) {
+#pragma unroll
+    for (int m = 0; m < kE; ++m) {
+      float s, c;
+      sincos_rev(ph[m], &s, &c);
+      x[m] = c_mul(x[m], make_float2(c * a.scale, s * a.scale));
+    }
+    if (out_spec) {
+      fft<N, kE, false, WV>(x, lds, t, tw);
+      if (a.post) {
+#pragma unroll
+        for (int m = 0; m < kE; ++m) x[m] = c_mul(x[m], (a.post + t)[T * m]);
+      }
+    } else if (slot) {
+      idle_fft<N, WV>();
+    }
+    if (writes) {
+      float2* dst = a.out + r * static_cast<int64_t>(plane) + static_cast<size_t>(row) * N + t;
+#pragma unroll
+      for (int m = 0; m < kE; ++m) dst[T * m] = x[m];
+    }
+  };
+
+  if (w == 0) {
+    load_screen(row0);                  // stage 0: S0, with A0's field row
+    load_field(y, ra, row0);
+    screen(row0);
+  } else {
+    load_field(x, rb, row0);            // stage 0: B0
+    inverse(true);
+  }
+  __syncthreads();  // Im S0 in the hand-off
+  if (w == 0) {
+#pragma unroll
+    for (int m = 0; m < kE; ++m) x[m] = y[m];
+    inverse(both);                      // stage 1: A0
+    finish(ra, row0, true, true);       // stage 2: A0'
+    load_field(x, rb, row1);            // stage 3: B1
+    inverse(false);
+  } else {
+#pragma unroll
+    for (int m = 0; m < kE; ++m) ph[m] = hand[T * m];
+    finish(rb, row0, has_b, both);      // stage 1: B0'
+    load_screen(row1);                  // stage 2: S1, with A1's field row
+    load_field(y, ra, row1);
+    screen(row1);
+#pragma unroll
+    for (int m = 0; m < kE; ++m) x[m] = y[m];
+    inverse(false);                     // stage 3: A1
+  }
+  __syncthreads();  // Im S1 in the hand-off
+  if (w == 0) {
+#pragma unroll
+    for (int m = 0; m < kE; ++m) ph[m] = hand[T * m];
+    finish(rb, row1, has_b, false);     // stage 4: B1'
+  } else {
+    finish(ra, row1, true, false);      // stage 4: A1'
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Column pass: FFT along y, x h(k0)/N (x angular-spectrum correction), IFFT.
 // ---------------------------------------------------------------------------
 // Transfer-function modes of the column pass: Fresnel chirp only, or the
@@ -873,6 +1036,22 @@ __global__ __launch_bounds__(256) void copy_kernel(const float2* in, int64_t in_
   out[idx] = in[r * in_stride + p];
 }
 
+// The relay kernel for forward passes with synthesised screens and no
+// checkpoint output, where its workers are whole waves and it keeps three
+// waves per SIMD (N <= 1024); false: not launched.  With checkpoint writes
+// and in the adjoint the pair schedule measured as fast or faster.
+template <int N>
+bool relay_launch(const RowArgs& a, int64_t pairs, hipStream_t s) {
+  if constexpr (!relay_fits<N>() || N > 1024 || !TURPY_ROW_RELAY) {
+    return false;
+  } else {
+    if (a.screen_mode != ROW_SCRATCH || a.backward || a.conj_tables || a.ckpt_out || a.pre) return false;
+    const dim3 grid(N / (2 * relay_rows<N>()), static_cast<uint32_t>(pairs));
+    hipLaunchKernelGGL((row_relay_kernel<N>), grid, dim3(relay_block<N>()), 0, s, a);
+    return true;
+  }
+}
+
 template <int N>
 hipError_t row_launch(const RowArgs& a, int64_t pairs, hipStream_t s) {
   constexpr int G = row_groups<N>();
@@ -890,6 +1069,8 @@ hipError_t row_launch(const RowArgs& a, int64_t pairs, hipStream_t s) {
       hipLaunchKernelGGL((row_pass_kernel<N, ROW_MATERIALIZED, false>), grid, block, 0, s, a);
     else
       hipLaunchKernelGGL((row_pass_kernel<N, ROW_MATERIALIZED, true>), grid, block, 0, s, a);
+  } else if (relay_launch<N>(a, pairs, s)) {
+    // synthesised screens on the relay schedule
   } else {
     constexpr int GP = pair_rows<N>();
     const dim3 pgrid(N / GP, static_cast<uint32_t>(pairs));

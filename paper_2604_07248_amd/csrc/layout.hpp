@@ -71,6 +71,18 @@ constexpr int pair_rows() {
 template <int N>
 constexpr int pair_block() { return 2 * pair_rows<N>() * (N / kE); }
 
+// Relay row pass: two workers of `relay_rows` rows each per block, over two
+// row groups (2 relay_rows <= N).  Used where a worker is whole waves.
+template <int N>
+constexpr int relay_rows() { return pair_rows<N>() < N / 2 ? pair_rows<N>() : N / 2; }
+template <int N>
+constexpr int relay_block() { return 2 * relay_rows<N>() * (N / kE); }
+template <int N>
+constexpr bool relay_fits() { return (relay_rows<N>() * (N / kE)) % 64 == 0; }
+#ifndef TURPY_ROW_RELAY
+#define TURPY_ROW_RELAY 1
+#endif
+
 // Spread a 1-D block index so that consecutive logical tiles land on the same
 // XCD (blocks are dealt round-robin over the 8 XCDs, each with its own L2).
 __device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t nb) {

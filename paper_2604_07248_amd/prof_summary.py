@@ -52,6 +52,8 @@ def family(kernel_name):
         if m.group(2) == "0":
             return "row_plain"
         return "row_bwd" if m.group(3) == "true" else "row_fwd"
+    if "row_relay_kernel" in n:
+        return "row_fwd"
     for key, fam in (("col_pair_kernel", "col_synth"), ("col_pass_kernel", "col"), ("synth_col_kernel", "synth"),
                      ("sh_kernel", "sh"), ("evolve_kernel", "evolve"), ("stats_kernel", "stats"),
                      ("finalize_kernel", "finalize"), ("copy_kernel", "copy"), ("recv_row_in", "recv_row"),
