@@ -5,7 +5,29 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+// Field, scratch and checkpoint rows read by the row passes with the
+// non-temporal cache policy (each row is read once).
+#ifndef TURPY_NT_ROW
+#define TURPY_NT_ROW 1
+#endif
+#ifndef TURPY_NT_PAIR
+#define TURPY_NT_PAIR 1
+#endif
+
 namespace turpy {
+
+// Global load of a complex value, with the non-temporal (nt) cache policy
+// when NT is set.
+typedef float float2_nt __attribute__((ext_vector_type(2)));
+template <bool NT>
+__device__ __forceinline__ float2 ld_s(const float2* p) {
+  if constexpr (NT) {
+    const float2_nt w = __builtin_nontemporal_load(reinterpret_cast<const float2_nt*>(p));
+    return make_float2(w.x, w.y);
+  } else {
+    return *p;
+  }
+}
 
 __device__ __forceinline__ float2 c_add(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 c_sub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }

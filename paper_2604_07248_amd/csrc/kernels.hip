@@ -241,7 +241,7 @@ void row_pair_kernel(RowArgs a) {
     if constexpr (BWD) {
       if (want_ck) {
 #pragma unroll
-        for (int m = 0; m < kE; ++m) wck[m] = (a.ckpt_in + cw_row + t)[T * m];
+        for (int m = 0; m < kE; ++m) wck[m] = ld_s<TURPY_NT_PAIR>(a.ckpt_in + cw_row + t + T * m);
       }
     }
   };
@@ -250,11 +250,11 @@ void row_pair_kernel(RowArgs a) {
     if constexpr (SCREEN == ROW_SCRATCH) {
       const float2* src = a.scratch + j * plane + row_off;
 #pragma unroll
-      for (int m = 0; m < kE; ++m) x[m] = (src + t)[T * m];
+      for (int m = 0; m < kE; ++m) x[m] = ld_s<TURPY_NT_PAIR>(src + t + T * m);
       if (TURPY_ROW_PREFETCH) {
         const float2* fa = a.in + r * a.in_stride + row_off;
 #pragma unroll
-        for (int m = 0; m < kE; ++m) y[m] = (fa + t)[T * m];
+        for (int m = 0; m < kE; ++m) y[m] = ld_s<TURPY_NT_PAIR>(fa + t + T * m);
       }
       fft<N, kE, true, WV>(x, lds, t, tw);
     } else {
@@ -267,7 +267,7 @@ void row_pair_kernel(RowArgs a) {
   } else {
     const float2* src = a.in + r * a.in_stride + row_off;
 #pragma unroll
-    for (int m = 0; m < kE; ++m) x[m] = (src + t)[T * m];
+    for (int m = 0; m < kE; ++m) x[m] = ld_s<TURPY_NT_PAIR>(src + t + T * m);
     fetch_ckpt();
     if (in_spec) {
       if (a.pre) {
@@ -390,7 +390,7 @@ void row_pair_kernel(RowArgs a) {
     } else {
       const float2* src = a.in + r * a.in_stride + row_off;
 #pragma unroll
-      for (int m = 0; m < kE; ++m) x[m] = (src + t)[T * m];
+      for (int m = 0; m < kE; ++m) x[m] = ld_s<TURPY_NT_PAIR>(src + t + T * m);
     }
     fetch_ckpt();
     if (in_spec) {
@@ -468,7 +468,7 @@ void row_relay_kernel(RowArgs a) {
   auto load_field = [&](float2 (&v)[kE], int64_t r, int row) {
     const float2* src = a.in + r * a.in_stride + static_cast<size_t>(row) * N + t;
 #pragma unroll
-    for (int m = 0; m < kE; ++m) v[m] = src[T * m];
+    for (int m = 0; m < kE; ++m) v[m] = ld_s<TURPY_NT_ROW>(src + T * m);
   };
   // x (a loaded field row) to real space; slot: the other worker transforms
   // in this stage
@@ -482,7 +482,7 @@ void row_relay_kernel(RowArgs a) {
   auto load_screen = [&](int row) {
     const float2* src = a.scratch + j * plane + static_cast<size_t>(row) * N + t;
 #pragma unroll
-    for (int m = 0; m < kE; ++m) x[m] = src[T * m];
+    for (int m = 0; m < kE; ++m) x[m] = ld_s<TURPY_NT_ROW>(src + T * m);
   };
   // screen row of pair j: inverse row transform of the scratch row, the
   // subharmonics and the piston of Eq. 2-3; Re into ph, Im into the hand-off
