@@ -5,13 +5,20 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-// Field, scratch and checkpoint rows read by the row passes with the
-// non-temporal cache policy (each row is read once).
+// Field, scratch and checkpoint rows read by the row passes, and the fields
+// read by the moments kernel, with the non-temporal cache policy (each is
+// read once); loads in flight per thread in the moments kernel.
 #ifndef TURPY_NT_ROW
 #define TURPY_NT_ROW 1
 #endif
 #ifndef TURPY_NT_PAIR
 #define TURPY_NT_PAIR 1
+#endif
+#ifndef TURPY_NT_STATS
+#define TURPY_NT_STATS 1
+#endif
+#ifndef TURPY_STATS_UNROLL
+#define TURPY_STATS_UNROLL 16
 #endif
 
 namespace turpy {

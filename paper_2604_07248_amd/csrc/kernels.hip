@@ -928,17 +928,17 @@ __global__ __launch_bounds__(256) void stats_kernel(StatsArgs a) {
     c2 = (tt - s2) - y;
     s2 = tt;
   };
-  // eight loads in flight per thread; the sums stay in batch order
-  constexpr int U = 8;
+  // U loads in flight per thread; the sums stay in batch order
+  constexpr int U = TURPY_STATS_UNROLL;
   int64_t b = 0;
   for (; b + U <= a.batch; b += U) {
     float2 u[U];
 #pragma unroll
-    for (int q = 0; q < U; ++q) u[q] = a.u[(b + q) * np + p];
+    for (int q = 0; q < U; ++q) u[q] = ld_s<TURPY_NT_STATS>(a.u + (b + q) * np + p);
 #pragma unroll
     for (int q = 0; q < U; ++q) add(u[q]);
   }
-  for (; b < a.batch; ++b) add(a.u[b * np + p]);
+  for (; b < a.batch; ++b) add(ld_s<TURPY_NT_STATS>(a.u + b * np + p));
   a.moments[p] = s1;
   a.moments[np + p] = c1;
   a.moments[2 * np + p] = s2;
