@@ -616,9 +616,9 @@ void col_pass_kernel(ColArgs a) {
   constexpr int T = N / kE;
   constexpr int STRIPS = N / K;
   __shared__ float2 smem[ColLds<K>::words(N)];
-  const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
-  const int strip = b % STRIPS;
-  const int64_t r = b / STRIPS;
+  int strip;
+  int64_t r;
+  col_tile(blockIdx.x, gridDim.x, STRIPS, a.R, &strip, &r);
   const int c = threadIdx.x % K;
   const int t = threadIdx.x / K;
   const int k1 = strip * K + c;

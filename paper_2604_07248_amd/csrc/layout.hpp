@@ -90,4 +90,27 @@ __device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t nb) {
   return (b % 8u) * (nb / 8u) + b / 8u;
 }
 
+#ifndef TURPY_COL_ORDER
+#define TURPY_COL_ORDER 1
+#endif
+// Strip and plane of block b of a column pass over R planes of `strips`
+// strips.  Order 1: plane-major, the planes from last to first, each XCD
+// taking one contiguous eighth of every plane's strips (neighbouring strips,
+// which share cache lines, stay on one XCD's L2).  The row passes run the
+// planes from first to last, so a column pass starts on the planes the row
+// pass before it wrote last, and the row pass after it on the planes it wrote
+// last.  Order 0: xcd_remap over (plane, strip).
+__device__ __forceinline__ void col_tile(uint32_t b, uint32_t nb, int strips, int64_t R, int* strip, int64_t* r) {
+  if (TURPY_COL_ORDER && strips % 8 == 0) {
+    const uint32_t x = b % 8u, i = b / 8u;
+    const int per = strips / 8;
+    *strip = static_cast<int>(x) * per + static_cast<int>(i % static_cast<uint32_t>(per));
+    *r = R - 1 - static_cast<int64_t>(i / static_cast<uint32_t>(per));
+  } else {
+    const uint32_t t = xcd_remap(b, nb);
+    *strip = static_cast<int>(t % static_cast<uint32_t>(strips));
+    *r = t / static_cast<uint32_t>(strips);
+  }
+}
+
 }  // namespace turpy

@@ -181,8 +181,8 @@ def report(out_dir, bench_json, root="gpurun_out"):
     j = lambda *a: os.path.join(root, *a)
     # forward kernel trace
     rows = stats_table(j("prof_fwd"))
-    fwd_row = next(r for r in rows[2:] if "| row_fwd |" in r)
     d = b["roofline"]
+    dom_rows = [r for r in rows[2:] if f"| {d['kernel']} |" in r]
     lines = ["# Kernel trace: forward headline workload (N=1024, R=64, M=8, fresh screens)", "",
              "Commands (one MI355X; the profiler writes its temporary files under /tmp).  The first, the",
              "default benchmark run, also writes the strip widths its tuner chose; the profiled runs read",
@@ -197,7 +197,8 @@ def report(out_dir, bench_json, root="gpurun_out"):
              "steps): " + _ev(["row_fwd", "col", "synth", "row_plain", "stats"], b["kernels"]) + ".", "",
              f"Roofline line of that run: dominant family `{d['kernel']}`, {d['bytes_per_launch']:.0f} algorithmic "
              f"bytes per launch over {d['avg_us']:.1f} us = {d['achieved']:.0f} GB/s = {100 * d['frac']:.1f} % of "
-             f"8 TB/s; the trace's average for that kernel is {fwd_row.split('|')[5].strip()} us."]
+             f"8 TB/s; the trace's average for that family is "
+             f"{' / '.join(r.split('|')[5].strip() for r in dom_rows)} us."]
     _write(out_dir, "fwd_h1_n1024_r64_m8_kernel_stats.md", lines)
     # forward + adjoint kernel trace
     lines = ["# Kernel trace: forward + adjoint, headline workload (N=1024, R=64, M=8, checkpoints)", "",
