@@ -13,6 +13,10 @@
 // (noise, PSD weighting, inverse FFT along y) writes one complex scratch plane
 // per pair; the row pass finishes it (inverse FFT along x, subharmonics,
 // piston) right before the modulation, so the real screens never touch HBM.
+//
+// Strided accesses are written (p + t)[T * m]: one address per row or column
+// for the thread, then compile-time offsets per element (the index form
+// p[t + T * m] made the compiler build a 64-bit address per element).
 #include "fft.hpp"
 #include "kernels.hpp"
 #include "layout.hpp"
