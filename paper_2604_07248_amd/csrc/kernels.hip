@@ -44,6 +44,20 @@ __device__ __forceinline__ uint32_t time_step(const Args& a) {
   return a.t_dev ? *a.t_dev : a.t;
 }
 
+// A field row in the strided layout, v[m] = p[T m]: with the non-temporal
+// policy (NT) when each realization reads its own row, plain when all of them
+// read one shared source plane (its rows are then re-read from L2).
+template <bool NT, int T>
+__device__ __forceinline__ void load_field_row(float2 (&v)[kE], const float2* p, bool shared) {
+  if (shared) {
+#pragma unroll
+    for (int m = 0; m < kE; ++m) v[m] = p[T * m];
+  } else {
+#pragma unroll
+    for (int m = 0; m < kE; ++m) v[m] = ld_s<NT>(p + T * m);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Row pass.
 // ---------------------------------------------------------------------------
@@ -257,8 +271,7 @@ void row_pair_kernel(RowArgs a) {
       for (int m = 0; m < kE; ++m) x[m] = ld_s<TURPY_NT_PAIR>(src + t + T * m);
       if (TURPY_ROW_PREFETCH) {
         const float2* fa = a.in + r * a.in_stride + row_off;
-#pragma unroll
-        for (int m = 0; m < kE; ++m) y[m] = ld_s<TURPY_NT_PAIR>(fa + t + T * m);
+        load_field_row<TURPY_NT_PAIR, T>(y, fa + t, a.in_stride == 0);
       }
       fft<N, kE, true, WV>(x, lds, t, tw);
     } else {
@@ -270,8 +283,7 @@ void row_pair_kernel(RowArgs a) {
     }
   } else {
     const float2* src = a.in + r * a.in_stride + row_off;
-#pragma unroll
-    for (int m = 0; m < kE; ++m) x[m] = ld_s<TURPY_NT_PAIR>(src + t + T * m);
+    load_field_row<TURPY_NT_PAIR, T>(x, src + t, a.in_stride == 0);
     fetch_ckpt();
     if (in_spec) {
       if (a.pre) {
@@ -393,8 +405,7 @@ void row_pair_kernel(RowArgs a) {
       for (int m = 0; m < kE; ++m) x[m] = y[m];
     } else {
       const float2* src = a.in + r * a.in_stride + row_off;
-#pragma unroll
-      for (int m = 0; m < kE; ++m) x[m] = ld_s<TURPY_NT_PAIR>(src + t + T * m);
+      load_field_row<TURPY_NT_PAIR, T>(x, src + t, a.in_stride == 0);
     }
     fetch_ckpt();
     if (in_spec) {
@@ -471,8 +482,7 @@ void row_relay_kernel(RowArgs a) {
   float2 x[kE], y[kE];
   auto load_field = [&](float2 (&v)[kE], int64_t r, int row) {
     const float2* src = a.in + r * a.in_stride + static_cast<size_t>(row) * N + t;
-#pragma unroll
-    for (int m = 0; m < kE; ++m) v[m] = ld_s<TURPY_NT_ROW>(src + T * m);
+    load_field_row<TURPY_NT_ROW, T>(v, src, a.in_stride == 0);
   };
   // x (a loaded field row) to real space; slot: the other worker transforms
   // in this stage
