@@ -7,6 +7,7 @@ HIP stream.
 
 import ctypes
 import json
+import os
 
 import torch
 
@@ -33,6 +34,7 @@ class Plan:
     def __init__(self, path, flags=0, device=None):
         self.path = path
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        tune_cache_from_env()
         with torch.cuda.device(self.device):
             self.handle = B.plan_create(path, flags)
         self.n, self.m, self.r = path.n, len(path.cn2dz), path.realizations
@@ -76,6 +78,7 @@ class Plan:
         ws = torch.empty(max(size, 256), dtype=torch.uint8, device=self.device)
         col, syn = B.plan_tune(self.handle, B.TUNE_FORCE if force else 0, _ptr(ws), size, _stream())
         del ws
+        _tune_cache_to_env()
         return {"col": col, "synth": syn}
 
     @property
@@ -221,6 +224,7 @@ class Batch:
             self.ck_offsets.append(self.ck_offsets[-1] + c)
         self.ck_total = sum(ck)
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        tune_cache_from_env()
         with torch.cuda.device(self.device):
             self.handle = B.batch_create(self.paths, self.offsets, flags)
         self._ws = {}
@@ -270,6 +274,7 @@ class Batch:
         ws = torch.empty(max(size, 256), dtype=torch.uint8, device=self.device)
         B.batch_tune(self.handle, B.TUNE_FORCE if force else 0, _ptr(ws), size, _stream())
         del ws
+        _tune_cache_to_env()
 
     def propagate(self, u_in, seed=0, t=0, checkpoints=False, out=None):
         _need(u_in, torch.complex64, (self.total,), "u_in")
@@ -318,6 +323,27 @@ def tune_cache_load(path):
 
 def tune_cache_clear():
     B.tune_cache_clear()
+
+
+TUNE_CACHE_ENV = "TURPY_TUNE_CACHE"
+_env_cache_read = []
+
+
+def tune_cache_from_env():
+    """Merge the JSON file named by $TURPY_TUNE_CACHE into the cache, once per
+    process (plans and batches call this before they are created; a missing
+    file is skipped).  Returns the number of entries read."""
+    path = os.environ.get(TUNE_CACHE_ENV)
+    if not path or path in _env_cache_read:
+        return 0
+    _env_cache_read.append(path)
+    return tune_cache_load(path) if os.path.exists(path) else 0
+
+
+def _tune_cache_to_env():
+    path = os.environ.get(TUNE_CACHE_ENV)
+    if path:
+        tune_cache_save(path)
 
 
 class Moments:

@@ -209,6 +209,32 @@ def test_evolve_and_spectra_propagation(api):
     assert e_spec < TOL and e_out < TOL
 
 
+def test_ar_resume_is_exact(api):
+    """Resuming an AR sequence (Sec. 2.3) from a copy of its state: the pair
+    spectra and the subharmonic coefficients after step k, evolved on in a
+    fresh plan, give bit for bit the fields of the uninterrupted run, because
+    the noise of every step is keyed by (seed, t) alone."""
+    path = sized_path(256, realizations=4, m=2, sh=3)
+    say("[resume] n=256 sh=3")
+    plan = api.Plan(path)
+    spec = plan.init_spectra(seed=5)
+    for t in (1, 2):
+        plan.evolve(spec, seed=5, t=t, alpha=0.95, shift_x=0.5, shift_y=0.25)
+    saved = spec._base.clone()  # the whole state buffer: spectra, then the subharmonic tail
+    u0 = c64(gaussian(path))
+    outs = []
+    for t in (3, 4, 5):
+        plan.evolve(spec, seed=5, t=t, alpha=0.95, shift_x=0.5, shift_y=0.25)
+        outs.append(plan.propagate(u0, spectra=spec).clone())
+    plan.close()
+    plan2 = api.Plan(path)
+    spec2 = saved[: spec.numel()].view(spec.shape)
+    for i, t in enumerate((3, 4, 5)):
+        plan2.evolve(spec2, seed=5, t=t, alpha=0.95, shift_x=0.5, shift_y=0.25)
+        assert torch.equal(plan2.propagate(u0, spectra=spec2), outs[i]), t
+    plan2.close()
+
+
 def test_evolve_with_subharmonics(api):
     """AR state with three subharmonic levels: at t = 0 it reproduces the
     synthesised screens; after three Eq. 4 + Eq. 5 steps (fractional shifts)

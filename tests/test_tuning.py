@@ -92,3 +92,19 @@ def test_json_round_trip(cache, tmp_path):
     bad.write_text(json.dumps({"format": "other", "version": 1, "entries": []}))
     with pytest.raises(ValueError):
         cache.tune_cache_load(str(bad))
+
+
+def test_cache_file_from_environment(cache, tmp_path, monkeypatch):
+    """$TURPY_TUNE_CACHE names a cache file that plans read before they are
+    created (once per process and path) and that tuning writes back."""
+    path = tmp_path / "env_tune.json"
+    B.tune_cache_put([entry(n=512, width=16, batch_class=4)])
+    cache.tune_cache_save(str(path))
+    cache.tune_cache_clear()
+    monkeypatch.setenv(cache.TUNE_CACHE_ENV, str(path))
+    monkeypatch.setattr(cache, "_env_cache_read", [])
+    assert cache.tune_cache_from_env() == 1
+    assert [(e["n"], e["width"]) for e in cache.tune_cache()] == [(512, 16)]
+    assert cache.tune_cache_from_env() == 0  # read once
+    monkeypatch.setenv(cache.TUNE_CACHE_ENV, str(tmp_path / "missing.json"))
+    assert cache.tune_cache_from_env() == 0
