@@ -64,12 +64,6 @@ turpy_status hip_fail(hipError_t e, const char* where) {
     if (e_ != hipSuccess) return e_; \
   } while (0)
 
-#ifndef TURPY_FUSED_COLUMNS
-#define TURPY_FUSED_COLUMNS 0
-#endif
-// Column passes over realization pairs fused with the next screen's synthesis.
-constexpr bool kFusedColumns = TURPY_FUSED_COLUMNS != 0;
-
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kLog2e = 1.4426950408889634;
 constexpr size_t kAlign = 256;
@@ -483,24 +477,15 @@ hipError_t enqueue_screen_col(const turpy_plan* pl, uint64_t seed, uint32_t t, i
   return timed("synth", st, [&] { return launch_synth(pl->n, a, st); });
 }
 
-// Column pass of distance `step` over pairs; with synth_screen >= 0 the same
-// launch synthesises that screen's column half into ws.scratch.
+// Column pass of distance `step` over all realizations; with synth_screen >= 0
+// the column half of that screen's synthesis follows it into ws.scratch.
 hipError_t enqueue_col(const turpy_plan* pl, int step, const float2* in, int64_t in_stride, float2* out,
                        bool adjoint, int synth_screen, uint64_t seed, uint32_t t, const float2* spectra,
                        const Ws& w, hipStream_t st) {
   const ColArgs c = col_args(pl, step, in, in_stride, out, pl->R, adjoint);
-  if (!kFusedColumns || pl->n >= 2048) {
-    // separate launches: per-realization column pass, then the screen's column half
-    TURPY_HIP_E(timed("col", st, [&] { return launch_col(pl->n, c, st); }));
-    if (synth_screen >= 0) return enqueue_screen_col(pl, seed, t, synth_screen, spectra, w, st);
-    return hipSuccess;
-  }
-  if (synth_screen >= 0) {
-    const SynthArgs syn = synth_args(pl, seed, t, synth_screen, spectra, w);
-    return timed("col_synth", st, [&] { return launch_col_pair(pl->n, c, syn, 1, st); });
-  }
-  const SynthArgs none{};
-  return timed("col", st, [&] { return launch_col_pair(pl->n, c, none, 0, st); });
+  TURPY_HIP_E(timed("col", st, [&] { return launch_col(pl->n, c, st); }));
+  if (synth_screen >= 0) return enqueue_screen_col(pl, seed, t, synth_screen, spectra, w, st);
+  return hipSuccess;
 }
 
 // Enqueue the column half of screen s into ws.scratch (noise or stored spectra).

@@ -5,22 +5,6 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-// Field, scratch and checkpoint rows read by the row passes, and the fields
-// read by the moments kernel, with the non-temporal cache policy (each is
-// read once); loads in flight per thread in the moments kernel.
-#ifndef TURPY_NT_ROW
-#define TURPY_NT_ROW 1
-#endif
-#ifndef TURPY_NT_PAIR
-#define TURPY_NT_PAIR 1
-#endif
-#ifndef TURPY_NT_STATS
-#define TURPY_NT_STATS 1
-#endif
-#ifndef TURPY_STATS_UNROLL
-#define TURPY_STATS_UNROLL 16
-#endif
-
 namespace turpy {
 
 // Global load of a complex value, with the non-temporal (nt) cache policy
@@ -70,9 +54,11 @@ __device__ __forceinline__ float u01(uint32_t v) {
   return (static_cast<float>(v >> 9) + 0.5f) * 0x1p-23f;
 }
 
-// sin / cos of 2*pi*x for |x| <= 256 revolutions (hardware transcendental units
-// take their argument in revolutions).  The argument is first reduced to
-// [-1/2, 1/2] exactly.
+// sin / cos of 2*pi*x (the hardware transcendental units take their argument
+// in revolutions).  The argument is first reduced to [-1/2, 1/2]: x - rint(x)
+// is exact in FP32 for every finite x, so the only error beyond the hardware
+// units' own is the rounding already in x (absolute, about |x| * 2^-24
+// revolutions).
 __device__ __forceinline__ void sincos_rev(float x, float* s, float* c) {
   const float r = x - rintf(x);
   *s = __builtin_amdgcn_sinf(r);

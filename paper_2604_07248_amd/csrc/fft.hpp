@@ -16,12 +16,6 @@
 
 #include "device_common.hpp"
 
-// Fetch a pass's twiddles before the preceding LDS exchange (1) or right
-// before the pass (0).
-#ifndef TURPY_TW_PREFETCH
-#define TURPY_TW_PREFETCH 0
-#endif
-
 namespace turpy {
 
 // exp(-+ i theta) with (c, s) = (cos theta, sin theta); forward uses exp(-i theta).
@@ -168,62 +162,6 @@ __device__ __forceinline__ void lds_sync() {
   }
 }
 
-// Twiddles of one pass for this thread: w[q][r-1] = tw[r k STRIDE], k = j mod NS.
-template <int N, int E, int R, int NS>
-struct PassTwiddles {
-  float2 w[E / R][R - 1];
-  __device__ __forceinline__ void load(const float2* __restrict__ tw, int t) {
-    constexpr int T = N / E;
-    constexpr int STRIDE = N / (NS * R);
-#pragma unroll
-    for (int q = 0; q < E / R; ++q) {
-      const int k = (t + T * q) & (NS - 1);
-#pragma unroll
-      for (int r = 1; r < R; ++r) w[q][r - 1] = tw[r * k * STRIDE];
-    }
-  }
-};
-
-// One Stockham pass of radix R at sub-length NS with its twiddles already in
-// registers (NS > 1).  tw[i] = exp(-2 pi i * i / N).
-template <int N, int E, int R, int NS, bool INV, bool LAST, bool WAVE, class Lds, class TW>
-__device__ __forceinline__ void stockham_pass_tw(float2 (&x)[E], const Lds& lds, int t, const TW* ptw) {
-  constexpr int T = N / E;
-  constexpr int B = E / R;
-  static_assert(E % R == 0, "radix must divide the elements per thread");
-#pragma unroll
-  for (int q = 0; q < B; ++q) {
-    const int j = t + T * q;
-    float2 v[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) v[r] = x[q + B * r];
-    if constexpr (NS > 1) {
-#pragma unroll
-      for (int r = 1; r < R; ++r) {
-        const float2 w = ptw->w[q][r - 1];
-        v[r] = INV ? c_mulc(v[r], w) : c_mul(v[r], w);
-      }
-    }
-    dft<R, INV>(v);
-    if constexpr (LAST) {
-#pragma unroll
-      for (int r = 0; r < R; ++r) x[q + B * r] = v[r];
-    } else {
-      const int k = j & (NS - 1);
-      const int base = (j - k) * R + k;
-#pragma unroll
-      for (int r = 0; r < R; ++r) lds[base + r * NS] = v[r];
-    }
-  }
-  if constexpr (!LAST) {
-    lds_sync<WAVE>();
-    lds_gather<T>(x, lds, t);
-    lds_sync<WAVE>();
-  }
-}
-
-struct NoTwiddles {};
-
 // One Stockham pass loading each twiddle right where it is used.
 template <int N, int E, int R, int NS, bool INV, bool LAST, bool WAVE, class Lds>
 __device__ __forceinline__ void stockham_pass(float2 (&x)[E], const Lds& lds, int t,
@@ -272,32 +210,12 @@ __device__ __forceinline__ void fft(float2 (&x)[E], const Lds& lds, int t, const
   static_assert(N >= 16 && N <= 4096 && (N & (N - 1)) == 0, "N must be a power of two in 16..4096");
   static_assert(!WAVE || N / E <= 64, "a wave-local transform needs at most 64 threads");
   constexpr int REM1 = N / 16;
-  if constexpr (!TURPY_TW_PREFETCH) {
-    stockham_pass<N, E, 16, 1, INV, REM1 == 1, WAVE>(x, lds, t, tw);
-    if constexpr (REM1 > 1) {
-      constexpr int R2 = REM1 >= 16 ? 16 : REM1;
-      constexpr int REM2 = REM1 / R2;
-      stockham_pass<N, E, R2, 16, INV, REM2 == 1, WAVE>(x, lds, t, tw);
-      if constexpr (REM2 > 1) stockham_pass<N, E, REM2, 256, INV, true, WAVE>(x, lds, t, tw);
-    }
-  } else if constexpr (REM1 == 1) {
-    stockham_pass_tw<N, E, 16, 1, INV, true, WAVE>(x, lds, t, static_cast<const NoTwiddles*>(nullptr));
-  } else {
+  stockham_pass<N, E, 16, 1, INV, REM1 == 1, WAVE>(x, lds, t, tw);
+  if constexpr (REM1 > 1) {
     constexpr int R2 = REM1 >= 16 ? 16 : REM1;
     constexpr int REM2 = REM1 / R2;
-    // the second pass's twiddles are fetched before the first exchange, so that
-    // their latency overlaps the first pass and its LDS round trip
-    PassTwiddles<N, E, R2, 16> tw2;
-    tw2.load(tw, t);
-    stockham_pass_tw<N, E, 16, 1, INV, false, WAVE>(x, lds, t, static_cast<const NoTwiddles*>(nullptr));
-    if constexpr (REM2 == 1) {
-      stockham_pass_tw<N, E, R2, 16, INV, true, WAVE>(x, lds, t, &tw2);
-    } else {
-      PassTwiddles<N, E, REM2, 256> tw3;
-      tw3.load(tw, t);
-      stockham_pass_tw<N, E, R2, 16, INV, false, WAVE>(x, lds, t, &tw2);
-      stockham_pass_tw<N, E, REM2, 256, INV, true, WAVE>(x, lds, t, &tw3);
-    }
+    stockham_pass<N, E, R2, 16, INV, REM2 == 1, WAVE>(x, lds, t, tw);
+    if constexpr (REM2 > 1) stockham_pass<N, E, REM2, 256, INV, true, WAVE>(x, lds, t, tw);
   }
 }
 

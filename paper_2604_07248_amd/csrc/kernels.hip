@@ -62,11 +62,10 @@ __device__ __forceinline__ void load_field_row(float2 (&v)[kE], const float2* p,
 // Row pass.
 // ---------------------------------------------------------------------------
 template <int N, int SCREEN, bool BWD>
-__global__ __launch_bounds__(row_block<N>()) __attribute__((amdgpu_waves_per_eu(TURPY_ROW_WAVES, 0)))
-void row_pass_kernel(RowArgs a) {
+__global__ __launch_bounds__(row_block<N>()) void row_pass_kernel(RowArgs a) {
   constexpr int T = N / kE;
   constexpr int G = row_groups<N>();
-  constexpr bool WV = TURPY_WAVE_SYNC && T <= 64;  // each row's transform lives in one wavefront
+  constexpr bool WV = T <= 64;  // each row's transform lives in one wavefront
   __shared__ float2 smem[G * RowLds::words(N)];
   const int g = threadIdx.x / T;
   const int t = threadIdx.x % T;
@@ -223,12 +222,12 @@ void row_pass_kernel(RowArgs a) {
 // sequence: a half with no transform at a stage runs idle_fft.
 // ---------------------------------------------------------------------------
 template <int N, int SCREEN, bool BWD>
-__global__ __launch_bounds__(pair_block<N>()) __attribute__((amdgpu_waves_per_eu(TURPY_PAIR_WAVES, 0)))
+__global__ __launch_bounds__(pair_block<N>()) __attribute__((amdgpu_waves_per_eu(3, 0)))
 void row_pair_kernel(RowArgs a) {
   constexpr int T = N / kE;
   constexpr int G = pair_rows<N>();
   constexpr int HALF = G * T;
-  constexpr bool WV = TURPY_WAVE_SYNC && T <= 64;  // each row's transform lives in one wavefront
+  constexpr bool WV = T <= 64;  // each row's transform lives in one wavefront
   __shared__ float2 smem[2 * G * RowLds::words(N)];
   const int role = threadIdx.x / HALF;
   const int g = (threadIdx.x % HALF) / T;
@@ -259,7 +258,7 @@ void row_pair_kernel(RowArgs a) {
     if constexpr (BWD) {
       if (want_ck) {
 #pragma unroll
-        for (int m = 0; m < kE; ++m) wck[m] = ld_s<TURPY_NT_PAIR>(a.ckpt_in + cw_row + t + T * m);
+        for (int m = 0; m < kE; ++m) wck[m] = ld_s<true>(a.ckpt_in + cw_row + t + T * m);
       }
     }
   };
@@ -268,10 +267,10 @@ void row_pair_kernel(RowArgs a) {
     if constexpr (SCREEN == ROW_SCRATCH) {
       const float2* src = a.scratch + j * plane + row_off;
 #pragma unroll
-      for (int m = 0; m < kE; ++m) x[m] = ld_s<TURPY_NT_PAIR>(src + t + T * m);
-      if (TURPY_ROW_PREFETCH) {
+      for (int m = 0; m < kE; ++m) x[m] = ld_s<true>(src + t + T * m);
+      {
         const float2* fa = a.in + r * a.in_stride + row_off;
-        load_field_row<TURPY_NT_PAIR, T>(y, fa + t, a.in_stride == 0);
+        load_field_row<true, T>(y, fa + t, a.in_stride == 0);
       }
       fft<N, kE, true, WV>(x, lds, t, tw);
     } else {
@@ -283,7 +282,7 @@ void row_pair_kernel(RowArgs a) {
     }
   } else {
     const float2* src = a.in + r * a.in_stride + row_off;
-    load_field_row<TURPY_NT_PAIR, T>(x, src + t, a.in_stride == 0);
+    load_field_row<true, T>(x, src + t, a.in_stride == 0);
     fetch_ckpt();
     if (in_spec) {
       if (a.pre) {
@@ -400,12 +399,12 @@ void row_pair_kernel(RowArgs a) {
 
   // stage 3: A loads / inverse-transforms its field; B finishes
   if (role == 0) {
-    if (SCREEN == ROW_SCRATCH && TURPY_ROW_PREFETCH) {
+    if (SCREEN == ROW_SCRATCH) {
 #pragma unroll
       for (int m = 0; m < kE; ++m) x[m] = y[m];
     } else {
       const float2* src = a.in + r * a.in_stride + row_off;
-      load_field_row<TURPY_NT_PAIR, T>(x, src + t, a.in_stride == 0);
+      load_field_row<true, T>(x, src + t, a.in_stride == 0);
     }
     fetch_ckpt();
     if (in_spec) {
@@ -453,12 +452,12 @@ void row_pair_kernel(RowArgs a) {
 // barriers on both sides (idle_fft).
 // ---------------------------------------------------------------------------
 template <int N>
-__global__ __launch_bounds__(relay_block<N>()) __attribute__((amdgpu_waves_per_eu(TURPY_PAIR_WAVES, 0)))
+__global__ __launch_bounds__(relay_block<N>()) __attribute__((amdgpu_waves_per_eu(3, 0)))
 void row_relay_kernel(RowArgs a) {
   constexpr int T = N / kE;
   constexpr int G = relay_rows<N>();
   constexpr int HALF = G * T;
-  constexpr bool WV = TURPY_WAVE_SYNC && T <= 64;  // each row's transform lives in one wavefront
+  constexpr bool WV = T <= 64;  // each row's transform lives in one wavefront
   static_assert(HALF % 64 == 0 && 2 * G <= N, "a relay worker is whole waves over half the block's rows");
   __shared__ float2 smem[2 * G * RowLds::words(N)];
   __shared__ float handoff_rows[G * N];
@@ -482,7 +481,7 @@ void row_relay_kernel(RowArgs a) {
   float2 x[kE], y[kE];
   auto load_field = [&](float2 (&v)[kE], int64_t r, int row) {
     const float2* src = a.in + r * a.in_stride + static_cast<size_t>(row) * N + t;
-    load_field_row<TURPY_NT_ROW, T>(v, src, a.in_stride == 0);
+    load_field_row<true, T>(v, src, a.in_stride == 0);
   };
   // x (a loaded field row) to real space; slot: the other worker transforms
   // in this stage
@@ -496,7 +495,7 @@ void row_relay_kernel(RowArgs a) {
   auto load_screen = [&](int row) {
     const float2* src = a.scratch + j * plane + static_cast<size_t>(row) * N + t;
 #pragma unroll
-    for (int m = 0; m < kE; ++m) x[m] = ld_s<TURPY_NT_ROW>(src + T * m);
+    for (int m = 0; m < kE; ++m) x[m] = ld_s<true>(src + T * m);
   };
   // screen row of pair j: inverse row transform of the scratch row, the
   // subharmonics and the piston of Eq. 2-3; Re into ph, Im into the hand-off
@@ -625,7 +624,7 @@ __device__ __forceinline__ float2 angular_correction(const ColArgs& a, int k0, i
 }
 
 template <int N, int ANGULAR, int K>
-__global__ __launch_bounds__(K * (N / kE)) __attribute__((amdgpu_waves_per_eu(TURPY_COL_WAVES, 0)))
+__global__ __launch_bounds__(K * (N / kE))
 void col_pass_kernel(ColArgs a) {
   constexpr int T = N / kE;
   constexpr int STRIPS = N / K;
@@ -638,13 +637,9 @@ void col_pass_kernel(ColArgs a) {
   const int k1 = strip * K + c;
   const ColLds<K> lds{smem, c};
   __shared__ float2 tw_lds[N];
-#if TURPY_CHIRP_LDS
   __shared__ float2 h_lds[N];
   for (int i = threadIdx.x; i < N; i += blockDim.x) h_lds[i] = a.table[i];
   const float2* chirp = h_lds;
-#else
-  const float2* chirp = a.table;
-#endif
   const float2* tw = stage_twiddles<N>(tw_lds, a.tw);
   const float2* src = a.in + r * a.in_stride + k1;
   float2 x[kE];
@@ -669,7 +664,7 @@ void col_pass_kernel(ColArgs a) {
 // stored spectrum, then the unnormalised inverse transform along y.
 // ---------------------------------------------------------------------------
 template <int N, int K>
-__global__ __launch_bounds__(K * (N / kE)) __attribute__((amdgpu_waves_per_eu(TURPY_COL_WAVES, 0)))
+__global__ __launch_bounds__(K * (N / kE))
 void synth_col_kernel(SynthArgs a) {
   constexpr int T = N / kE;
   constexpr int STRIPS = N / K;
@@ -709,108 +704,6 @@ void synth_col_kernel(SynthArgs a) {
   float2* dst = a.scratch + j * static_cast<int64_t>(N) * N + k1;
 #pragma unroll
   for (int m = 0; m < kE; ++m) (dst + static_cast<size_t>(t) * N)[static_cast<size_t>(T * m) * N] = x[m];
-}
-
-// ---------------------------------------------------------------------------
-// Column pass over a realization pair, fused with the column half of the next
-// screen's synthesis.  Block (strip, j): the loads of field 2j's strip are
-// issued first; while they are in flight the block draws the pair's noise (or
-// reads its stored spectrum), weights it and inverse-transforms it along y
-// into the scratch plane; then fields 2j and 2j+1 get FFT_y, x h(k0)/N and
-// IFFT_y.  The screen's column synthesis can only run after the previous row
-// pass consumed the scratch plane, which is exactly when this pass runs.
-// ---------------------------------------------------------------------------
-template <int N>
-__device__ __forceinline__ void synth_column(float2 (&z)[kE], const SynthArgs& a, int64_t j, int k1, int t) {
-  constexpr int T = N / kE;
-  if (a.spectra) {
-    constexpr float inv2pi = 0.15915494309189535f;
-    const float2* src = a.spectra + (static_cast<size_t>(j) * a.M + a.screen) * N * N + k1;
-#pragma unroll
-    for (int m = 0; m < kE; ++m) z[m] = c_scale((src + static_cast<size_t>(t) * N)[static_cast<size_t>(T * m) * N], inv2pi);
-  } else {
-    const int kx = signed_bin(k1, N);
-#pragma unroll
-    for (int m = 0; m < kE / 2; ++m) {
-      const int k0 = t + T * m;  // < N/2
-      const uint32_t e = static_cast<uint32_t>(k0) * N + k1;
-      const uint4 v = philox4x32_10(noise_counter(e, time_step(a), static_cast<uint32_t>(j), a.tag, a.screen), a.key0,
-                                    a.key1);
-      const int ky_hi = k0 - N / 2;
-      const float w_lo = psd_amp(k0 * k0 + kx * kx, a.amp, a.df2, a.inner, a.f02, a.q);
-      const float w_hi = psd_amp(ky_hi * ky_hi + kx * kx, a.amp, a.df2, a.inner, a.f02, a.q);
-      z[m] = c_scale(box_muller(v.x, v.y), w_lo);
-      z[m + kE / 2] = c_scale(box_muller(v.z, v.w), w_hi);
-    }
-  }
-}
-
-template <int N, int ANGULAR>
-__device__ __forceinline__ void col_transfer(float2 (&x)[kE], const ColArgs& a, int k1, int t) {
-  constexpr int T = N / kE;
-#pragma unroll
-  for (int m = 0; m < kE; ++m) {
-    const int k0 = t + T * m;
-    float2 h = a.table[k0];
-    if constexpr (ANGULAR != TF_FRESNEL_ONLY) h = c_mul(h, angular_correction<ANGULAR>(a, k0, k1, N));
-    x[m] = a.conj_table ? c_mulc(x[m], h) : c_mul(x[m], h);
-  }
-}
-
-template <int N, int ANGULAR, bool SYNTH>
-__global__ __launch_bounds__(col_block<N>()) __attribute__((amdgpu_waves_per_eu(TURPY_COL_WAVES, 0)))
-void col_pair_kernel(ColArgs a, SynthArgs syn) {
-  constexpr int T = N / kE;
-  constexpr int K = col_width<N>();
-  constexpr int STRIPS = N / K;
-  __shared__ float2 smem[ColLds<K>::words(N)];
-  const uint32_t bid = xcd_remap(blockIdx.x, gridDim.x);
-  const int strip = bid % STRIPS;
-  const int64_t j = bid / STRIPS;
-  const int c = threadIdx.x % K;
-  const int t = threadIdx.x / K;
-  const int k1 = strip * K + c;
-  const ColLds<K> lds{smem, c};
-  __shared__ float2 tw_lds[N];
-  const float2* tw = stage_twiddles<N>(tw_lds, a.tw);
-  const size_t plane = static_cast<size_t>(N) * N;
-  const int64_t ra = 2 * j, rb = 2 * j + 1;
-
-  float2 x[kE];
-  const float2* sa = a.in + ra * a.in_stride + k1;
-#if TURPY_COL_PREFETCH
-#pragma unroll
-  for (int m = 0; m < kE; ++m) x[m] = (sa + static_cast<size_t>(t) * N)[static_cast<size_t>(T * m) * N];
-#endif
-  if constexpr (SYNTH) {
-    float2 z[kE];
-    synth_column<N>(z, syn, j, k1, t);
-    fft<N, kE, true>(z, lds, t, tw);
-    float2* dz = syn.scratch + j * static_cast<int64_t>(plane) + k1;
-#pragma unroll
-    for (int m = 0; m < kE; ++m) (dz + static_cast<size_t>(t) * N)[static_cast<size_t>(T * m) * N] = z[m];
-  }
-#if !TURPY_COL_PREFETCH
-#pragma unroll
-  for (int m = 0; m < kE; ++m) x[m] = (sa + static_cast<size_t>(t) * N)[static_cast<size_t>(T * m) * N];
-#endif
-  fft<N, kE, false>(x, lds, t, tw);
-  col_transfer<N, ANGULAR>(x, a, k1, t);
-  fft<N, kE, true>(x, lds, t, tw);
-  float2* da = a.out + ra * static_cast<int64_t>(plane) + k1;
-#pragma unroll
-  for (int m = 0; m < kE; ++m) (da + static_cast<size_t>(t) * N)[static_cast<size_t>(T * m) * N] = x[m];
-  if (rb < a.R) {  // uniform over the block
-    const float2* sb = a.in + rb * a.in_stride + k1;
-#pragma unroll
-    for (int m = 0; m < kE; ++m) x[m] = (sb + static_cast<size_t>(t) * N)[static_cast<size_t>(T * m) * N];
-    fft<N, kE, false>(x, lds, t, tw);
-    col_transfer<N, ANGULAR>(x, a, k1, t);
-    fft<N, kE, true>(x, lds, t, tw);
-    float2* db = a.out + rb * static_cast<int64_t>(plane) + k1;
-#pragma unroll
-    for (int m = 0; m < kE; ++m) (db + static_cast<size_t>(t) * N)[static_cast<size_t>(T * m) * N] = x[m];
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -943,16 +836,16 @@ __global__ __launch_bounds__(256) void stats_kernel(StatsArgs a) {
     s2 = tt;
   };
   // U loads in flight per thread; the sums stay in batch order
-  constexpr int U = TURPY_STATS_UNROLL;
+  constexpr int U = 16;
   int64_t b = 0;
   for (; b + U <= a.batch; b += U) {
     float2 u[U];
 #pragma unroll
-    for (int q = 0; q < U; ++q) u[q] = ld_s<TURPY_NT_STATS>(a.u + (b + q) * np + p);
+    for (int q = 0; q < U; ++q) u[q] = ld_s<true>(a.u + (b + q) * np + p);
 #pragma unroll
     for (int q = 0; q < U; ++q) add(u[q]);
   }
-  for (; b < a.batch; ++b) add(ld_s<TURPY_NT_STATS>(a.u + b * np + p));
+  for (; b < a.batch; ++b) add(ld_s<true>(a.u + b * np + p));
   a.moments[p] = s1;
   a.moments[np + p] = c1;
   a.moments[2 * np + p] = s2;
@@ -1056,7 +949,7 @@ __global__ __launch_bounds__(256) void copy_kernel(const float2* in, int64_t in_
 // and in the adjoint the pair schedule measured as fast or faster.
 template <int N>
 bool relay_launch(const RowArgs& a, int64_t pairs, hipStream_t s) {
-  if constexpr (!relay_fits<N>() || N > 1024 || !TURPY_ROW_RELAY) {
+  if constexpr (!relay_fits<N>() || N > 1024) {
     return false;
   } else {
     if (a.screen_mode != ROW_SCRATCH || a.backward || a.conj_tables || a.ckpt_out || a.pre) return false;
@@ -1130,25 +1023,6 @@ hipError_t col_launch(const ColArgs& a, hipStream_t s) {
   }
 }
 
-template <int N>
-hipError_t col_pair_launch(const ColArgs& a, const SynthArgs& syn, int do_synth, hipStream_t s) {
-  constexpr int K = col_width<N>();
-  const int64_t pairs = (a.R + 1) / 2;
-  const dim3 grid(static_cast<uint32_t>(static_cast<uint64_t>(N / K) * pairs));
-  const dim3 block(col_block<N>());
-  if (a.angular && a.as_table) {
-    if (do_synth) hipLaunchKernelGGL((col_pair_kernel<N, TF_AS_TABLE, true>), grid, block, 0, s, a, syn);
-    else hipLaunchKernelGGL((col_pair_kernel<N, TF_AS_TABLE, false>), grid, block, 0, s, a, syn);
-  } else if (a.angular) {
-    if (do_synth) hipLaunchKernelGGL((col_pair_kernel<N, TF_AS_FP32, true>), grid, block, 0, s, a, syn);
-    else hipLaunchKernelGGL((col_pair_kernel<N, TF_AS_FP32, false>), grid, block, 0, s, a, syn);
-  } else {
-    if (do_synth) hipLaunchKernelGGL((col_pair_kernel<N, TF_FRESNEL_ONLY, true>), grid, block, 0, s, a, syn);
-    else hipLaunchKernelGGL((col_pair_kernel<N, TF_FRESNEL_ONLY, false>), grid, block, 0, s, a, syn);
-  }
-  return hipGetLastError();
-}
-
 template <int N, int K>
 hipError_t synth_launch_k(const SynthArgs& a, hipStream_t s) {
   if constexpr (!strip_fits<N, K>()) {
@@ -1190,9 +1064,6 @@ hipError_t launch_row(int n, const RowArgs& a, int64_t pairs, hipStream_t s) {
 }
 hipError_t launch_col(int n, const ColArgs& a, hipStream_t s) { TURPY_DISPATCH_N(n, col_launch, a, s) }
 hipError_t launch_synth(int n, const SynthArgs& a, hipStream_t s) { TURPY_DISPATCH_N(n, synth_launch, a, s) }
-hipError_t launch_col_pair(int n, const ColArgs& c, const SynthArgs& syn, int do_synth, hipStream_t s) {
-  TURPY_DISPATCH_N(n, col_pair_launch, c, syn, do_synth, s)
-}
 
 hipError_t launch_sh(const ShArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(sh_kernel, dim3(static_cast<uint32_t>(a.P), a.M), dim3(64), 0, s, a);

@@ -147,9 +147,6 @@ struct RecvArgs {
 hipError_t launch_row(int n, const RowArgs& a, int64_t pairs, hipStream_t s);
 hipError_t launch_col(int n, const ColArgs& a, hipStream_t s);
 hipError_t launch_synth(int n, const SynthArgs& a, hipStream_t s);
-// Column pass over the two fields of each realization pair, optionally fused
-// with the column half of the next screen's synthesis (do_synth).
-hipError_t launch_col_pair(int n, const ColArgs& c, const SynthArgs& syn, int do_synth, hipStream_t s);
 hipError_t launch_sh(const ShArgs& a, hipStream_t s);
 hipError_t launch_evolve(const EvolveArgs& a, hipStream_t s);
 hipError_t launch_stats(const StatsArgs& a, hipStream_t s);

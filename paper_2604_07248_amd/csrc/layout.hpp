@@ -15,27 +15,6 @@ constexpr int row_groups() {  // rows per block of the row kernels
 }
 template <int N>
 constexpr int row_block() { return row_groups<N>() * (N / kE); }
-#ifndef TURPY_ROW_WAVES
-#define TURPY_ROW_WAVES 0
-#endif
-#ifndef TURPY_WAVE_SYNC
-#define TURPY_WAVE_SYNC 1
-#endif
-#ifndef TURPY_PAIR_WAVES
-#define TURPY_PAIR_WAVES 3
-#endif
-#ifndef TURPY_CHIRP_LDS
-#define TURPY_CHIRP_LDS 1
-#endif
-#ifndef TURPY_ROW_PREFETCH
-#define TURPY_ROW_PREFETCH 1
-#endif
-#ifndef TURPY_COL_PREFETCH
-#define TURPY_COL_PREFETCH 1
-#endif
-#ifndef TURPY_COL_WAVES
-#define TURPY_COL_WAVES 0
-#endif
 // Columns per block of the column pass and of the screen synthesis, per grid
 // size, when no tuned choice is set: the fastest of 4, 8 and 16 measured on
 // MI355X at constant R N^2 (column pass: 16 up to N = 512, 8 above;
@@ -79,9 +58,6 @@ template <int N>
 constexpr int relay_block() { return 2 * relay_rows<N>() * (N / kE); }
 template <int N>
 constexpr bool relay_fits() { return (relay_rows<N>() * (N / kE)) % 64 == 0; }
-#ifndef TURPY_ROW_RELAY
-#define TURPY_ROW_RELAY 1
-#endif
 
 // Spread a 1-D block index so that consecutive logical tiles land on the same
 // XCD (blocks are dealt round-robin over the 8 XCDs, each with its own L2).
@@ -90,18 +66,15 @@ __device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t nb) {
   return (b % 8u) * (nb / 8u) + b / 8u;
 }
 
-#ifndef TURPY_COL_ORDER
-#define TURPY_COL_ORDER 1
-#endif
 // Strip and plane of block b of a column pass over R planes of `strips`
-// strips.  Order 1: plane-major, the planes from last to first, each XCD
-// taking one contiguous eighth of every plane's strips (neighbouring strips,
-// which share cache lines, stay on one XCD's L2).  The row passes run the
-// planes from first to last, so a column pass starts on the planes the row
-// pass before it wrote last, and the row pass after it on the planes it wrote
-// last.  Order 0: xcd_remap over (plane, strip).
+// strips: plane-major, the planes from last to first, each XCD taking one
+// contiguous eighth of every plane's strips (neighbouring strips, which share
+// cache lines, stay on one XCD's L2).  The row passes run the planes from
+// first to last, so a column pass starts on the planes the row pass before it
+// wrote last, and the row pass after it on the planes it wrote last.  With a
+// strip count that is not a multiple of 8: xcd_remap over (plane, strip).
 __device__ __forceinline__ void col_tile(uint32_t b, uint32_t nb, int strips, int64_t R, int* strip, int64_t* r) {
-  if (TURPY_COL_ORDER && strips % 8 == 0) {
+  if (strips % 8 == 0) {
     const uint32_t x = b % 8u, i = b / 8u;
     const int per = strips / 8;
     *strip = static_cast<int>(x) * per + static_cast<int>(i % static_cast<uint32_t>(per));

@@ -54,7 +54,7 @@ def family(kernel_name):
         return "row_bwd" if m.group(3) == "true" else "row_fwd"
     if "row_relay_kernel" in n:
         return "row_fwd"
-    for key, fam in (("col_pair_kernel", "col_synth"), ("col_pass_kernel", "col"), ("synth_col_kernel", "synth"),
+    for key, fam in (("col_pass_kernel", "col"), ("synth_col_kernel", "synth"),
                      ("sh_kernel", "sh"), ("evolve_kernel", "evolve"), ("stats_kernel", "stats"),
                      ("finalize_kernel", "finalize"), ("copy_kernel", "copy"), ("recv_row_in", "recv_row"),
                      ("recv_col_grad", "recv_col_grad"), ("recv_col", "recv_col"),
