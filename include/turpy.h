@@ -59,7 +59,10 @@ typedef enum {
 } turpy_screen_src;
 
 /* Plan flags. */
-#define TURPY_ALLOW_ALIASING 1u   /* accept steps beyond the Eq. 7 limit */
+#define TURPY_ALLOW_ALIASING 1u      /* accept steps beyond the Eq. 7 limit */
+#define TURPY_SCREEN_CHECKPOINTS 2u  /* checkpoints also keep each screen's column half, so that the
+                                        adjoint reads the screens instead of synthesising them again
+                                        (turpy_checkpoint_size) */
 
 /* One propagation path (Sec. 2.1, Fig. 1A inputs). */
 typedef struct turpy_path {
@@ -114,6 +117,16 @@ const char* turpy_last_error(void);
 turpy_status turpy_plan_create(turpy_plan** out, const turpy_path* path, uint32_t flags);
 turpy_status turpy_plan_destroy(turpy_plan* plan);
 
+/* Bytes of the checkpoint buffer of turpy_propagate / turpy_propagate_backward:
+ * complex64 fields [R][M][N][N] (the field just after each screen), followed,
+ * for a plan created with TURPY_SCREEN_CHECKPOINTS, by the column halves of
+ * the screens complex64 [M][ceil(R/2)][N][N] (each pair's screen after its
+ * inverse transform along y, in revolutions; synthesised or stored-spectrum
+ * screens only).  The forward pass writes both; the adjoint reads both and
+ * then synthesises no screen: the same bytes move, and the adjoint's
+ * synthesis work is saved for M ceil(R/2) N^2 8 bytes of memory. */
+turpy_status turpy_checkpoint_size(const turpy_plan* plan, size_t* bytes);
+
 /* Bytes of device workspace an operation needs for this plan (0 allowed). */
 turpy_status turpy_workspace_size(const turpy_plan* plan, int32_t op, size_t* bytes);
 
@@ -130,8 +143,10 @@ turpy_status turpy_screen_generate(turpy_plan* plan, uint64_t seed, int64_t t, f
  *             u_in_stride = N*N.
  *  src/screens_or_spectra  per turpy_screen_src (NULL for SYNTH).
  *  u_out      complex64 [R][N][N], written.
- *  checkpoints complex64 [R][M][N][N] or NULL: the field just after each
- *             screen, for turpy_propagate_backward.
+ *  checkpoints turpy_checkpoint_size bytes or NULL: the field just after
+ *             each screen (complex64 [R][M][N][N]) and, with
+ *             TURPY_SCREEN_CHECKPOINTS, the screens' column halves, for
+ *             turpy_propagate_backward.
  *  ws         turpy_workspace_size(TURPY_OP_PROPAGATE) bytes. */
 turpy_status turpy_propagate(turpy_plan* plan, uint64_t seed, int64_t t, const void* u_in,
                              int64_t u_in_stride, int32_t src, const void* screens_or_spectra,
@@ -153,6 +168,35 @@ turpy_status turpy_propagate(turpy_plan* plan, uint64_t seed, int64_t t, const v
 turpy_status turpy_evolve(turpy_plan* plan, uint64_t seed, int64_t t, double alpha, double shift_x,
                           double shift_y, void* spectra, void* ws, size_t ws_bytes, void* stream);
 
+/* The complex normals N_c of a spectrum on their own (App. B Eq. S16; the
+ * same numbers the synthesis and the evolution draw inside their kernels):
+ * out complex64 [pairs][n][n] (device), bin (k0, k1) of pair j from the
+ * Philox counter (k0 n + k1, t, j, tag << 28 | screen) for k0 < n/2 (words 0-1,
+ * Box-Muller) and the bin (k0 + n/2, k1) from the same block (words 2-3).
+ * tag: 1 main spectrum, 3 AR innovation (others accepted).  For building the
+ * path one operation per kernel (a baseline) or inspecting the noise.
+ * Errors: INVALID for n not a power of two in 2..65536, tag outside 1..15,
+ * screen outside 0..2^28-1, t outside 0..2^32-1. */
+turpy_status turpy_noise(int32_t n, int64_t pairs, uint64_t seed, int64_t t, int32_t tag, int32_t screen, void* out,
+                         void* stream);
+
+/* One time step of the autoregressive path (Sec. 2.3 then Sec. 2.1): the AR
+ * step of turpy_evolve (t >= 1) followed by turpy_propagate from the evolved
+ * state (src TURPY_SCREENS_SPECTRA), with the evolution of each screen's
+ * spectra done inside that screen's synthesis pass: the state is read once,
+ * evolved in registers (Eq. 4 translation with the phase reduced in FP64, then
+ * the Eq. 5 blend with innovations of tag 3 at step t), written back, and
+ * transformed along y in the same pass, which saves the separate evolution
+ * pass's read and write of the whole state.  Results equal turpy_evolve then
+ * turpy_propagate up to FP32 rounding.  Subharmonic coefficients take their
+ * step in a small kernel first.  Arguments as for turpy_evolve and
+ * turpy_propagate; ws: turpy_workspace_size(TURPY_OP_PROPAGATE) bytes.
+ * Errors: INVALID for t < 1 (initialise the state with turpy_evolve at t = 0),
+ * alpha outside [0, 1], non-finite shifts. */
+turpy_status turpy_evolve_propagate(turpy_plan* plan, uint64_t seed, int64_t t, double alpha, double shift_x,
+                                    double shift_y, void* state, const void* u_in, int64_t u_in_stride,
+                                    void* u_out, void* checkpoints, void* ws, size_t ws_bytes, void* stream);
+
 /* Device-resident time step, for graph replays.  With dev_t set (a uint32
  * in device memory, 4-byte aligned), every kernel of this plan that draws
  * noise (screen synthesis, subharmonics, AR innovations) reads its time step
@@ -166,26 +210,42 @@ turpy_status turpy_plan_bind_time(turpy_plan* plan, const void* dev_t);
 /* Bytes of the plan's AR state (see turpy_evolve). */
 turpy_status turpy_state_size(const turpy_plan* plan, size_t* bytes);
 
-/* Adjoint of turpy_propagate with the same plan, seed, t and screens.
+/* Adjoint of turpy_propagate with the same plan, seed, t and screens: the
+ * gradients of a real loss through the split-step of Sec. 2.1 Eq. 1, which
+ * the paper differentiates end to end to train optics placed before and after
+ * the path (Sec. 1, Sec. 4).  Each diffraction step's adjoint is the same step
+ * with conj(H); through screen i, dL/dphi_i = Im(conj(W_i) g) with W_i the
+ * field just after the screen, then g <- exp(-i phi_i) g.
  *  grad_u_out  complex64 [R][N][N], read only.
- *  checkpoints complex64 [R][M][N][N] written by the forward call.
- *  grad_u_in   complex64 [R][N][N] per realization (sum over R for a shared
- *              source), or NULL.  Also used as the working buffer when
- *              non-NULL; otherwise the workspace holds it.
+ *  checkpoints turpy_checkpoint_size bytes written by the forward call with
+ *              the same plan (NULL allowed when M = 0); with
+ *              TURPY_SCREEN_CHECKPOINTS the screens are read from it.
+ *  grad_u_in   dL/du_in or NULL.  grad_u_in_stride = N*N: complex64
+ *              [R][N][N], one gradient per realization (also used as the
+ *              working buffer).  grad_u_in_stride = 0: complex64 [N][N], the
+ *              gradient of a source shared by every realization (the forward
+ *              call's u_in_stride = 0), i.e. the sum over realizations; the
+ *              sum is taken right after screen 0 (Kahan-compensated, in
+ *              realization order) and the first diffraction's adjoint runs
+ *              once on it.  Other strides: TURPY_E_INVALID.
  *  grad_screens float [R][M][N][N] dL/dphi_i, or NULL.
  *  ws          turpy_workspace_size(TURPY_OP_PROPAGATE_BACKWARD) bytes. */
 turpy_status turpy_propagate_backward(turpy_plan* plan, uint64_t seed, int64_t t, const void* grad_u_out,
                                       const void* checkpoints, int32_t src, const void* screens_or_spectra,
-                                      void* grad_u_in, float* grad_screens, void* ws, size_t ws_bytes,
-                                      void* stream);
+                                      void* grad_u_in, int64_t grad_u_in_stride, float* grad_screens, void* ws,
+                                      size_t ws_bytes, void* stream);
 
-/* The adjoint of turpy_propagate without checkpoints.  Every step of the
- * path is unitary, so the forward field at each screen plane is rebuilt by
+/* The adjoint of turpy_propagate without checkpoints (same operation as
+ * turpy_propagate_backward, Sec. 2.1 Eq. 1).  When every step of the path is
+ * unitary -- Fresnel transfer functions, or angular-spectrum ones whose bins
+ * all propagate -- the forward field at each screen plane is rebuilt by
  * running the same adjoint steps on the forward output: the memory of the
  * [R][M][N][N] checkpoints is replaced by two [R][N][N] fields in the
  * workspace, at the price of a second chain of passes.  Results equal
- * turpy_propagate_backward's up to FP32 rounding (the rebuilt fields carry
- * the rounding of both chains).
+ * turpy_propagate_backward's up to FP32 rounding (the rebuilt fields carry the
+ * rounding of both chains).  A plan whose angular-spectrum grid has evanescent
+ * bins (|H| < 1, the plan keeps its FP64 table) is not unitary: the call
+ * returns TURPY_E_UNSUPPORTED and enqueues nothing.
  *  u_out   complex64 [R][N][N], the output of the forward call with the same
  *          plan, seed, t and screens; read only.  May be NULL when M = 0.
  *  Other arguments as for turpy_propagate_backward; ws holds
@@ -193,19 +253,41 @@ turpy_status turpy_propagate_backward(turpy_plan* plan, uint64_t seed, int64_t t
 turpy_status turpy_propagate_backward_reversible(turpy_plan* plan, uint64_t seed, int64_t t,
                                                  const void* grad_u_out, const void* u_out, int32_t src,
                                                  const void* screens_or_spectra, void* grad_u_in,
-                                                 float* grad_screens, void* ws, size_t ws_bytes, void* stream);
+                                                 int64_t grad_u_in_stride, float* grad_screens, void* ws,
+                                                 size_t ws_bytes, void* stream);
 
-/* Ensemble statistics of received fields (Sec. 3.2-3.3, Eq. S25).
+/* Ensemble statistics of received fields (Sec. 3.2-3.3, Eq. S25; Sec. 4.1).
  *  If batch > 0: accumulate I = |u|^2 of u[batch][n][n] into
  *  moments float [4][n][n] = (sum I, its compensation, sum I^2, its
- *  compensation), Kahan-compensated; zero `moments` before the first batch.
- *  If finalize != 0: with count = total realizations accumulated, write
- *  si_map float [n][n] = m2/m1^2 - 1 (m = sums / count; may be NULL) and
- *  summary double[4] (device) = (SI averaged over |x|,|y| < n dx / 4,
- *  W_2nd = sqrt(2 sum r^2 m1 / sum m1), W_fit from a least-squares fit of
- *  ln m1 = a - 2 r^2/W^2 over m1 >= e^-2 max m1, count). */
-turpy_status turpy_stats(int32_t n, double dx, int64_t batch, const void* u, float* moments,
-                         int64_t count, int32_t finalize, float* si_map, double* summary, void* stream);
+ *  compensation), Kahan-compensated, in batch order; zero `moments` before the
+ *  first batch.
+ *  If finalize != 0: with count = total realizations accumulated and
+ *  m = sums / count, write si_map float [n][n] = m2/m1^2 - 1 (may be NULL)
+ *  and summary double[8] (device):
+ *    [0] SI averaged over the region, weighted: sum w SI / sum w;
+ *    [1] W_2nd = sqrt(2 sum r^2 m1 / sum m1);
+ *    [2] W_fit, least-squares fit of ln m1 = a - 2 r^2/W^2 over m1 >= e^-2 max m1;
+ *    [3] count;
+ *    [4] sum w SI over the region (the summed scintillation of Sec. 4.1);
+ *    [5] sum w over the region;
+ *    [6] the region's threshold intensity (power cutoff), else 0;
+ *    [7] 0.
+ *  The region: power_fraction = 0 selects the central pixels |i - n/2| < n/4
+ *  in both directions; 0 < power_fraction <= 1 the power-cutoff region of
+ *  Sec. 4.1 (99.9 % there): the pixels with m1 >= t, t the largest value for
+ *  which they hold power_fraction of sum m1 (decided on m1 rounded to FP32).
+ *  weight: float [n][n] device weights (an aperture mask, for instance) or
+ *  NULL for 1.  Errors: INVALID for power_fraction outside [0, 1]. */
+turpy_status turpy_stats(int32_t n, double dx, int64_t batch, const void* u, float* moments, int64_t count,
+                         int32_t finalize, const float* weight, double power_fraction, float* si_map,
+                         double* summary, void* stream);
+
+/* Set-up of the plan-less receiver calls for grid size n on the current
+ * device: builds their FP64-generated twiddle table (allocates and uploads
+ * synchronously; not for a capturing stream).  Idempotent; the tables live
+ * until the process ends.  turpy_receiver / turpy_receiver_backward return
+ * TURPY_E_INVALID for an n not set up on the current device. */
+turpy_status turpy_receiver_setup(int32_t n);
 
 /* Dual-domain two-mask receiver (Sec. 2.5, Sec. 4.1):
  *  U1 = A u exp(i theta1) (A: disc of `aperture_diameter` metres centred on
@@ -247,7 +329,9 @@ typedef struct turpy_batch turpy_batch;
  * here only); field_offsets [num_paths]: element (complex64) offset of
  * instance i's fields [R_i][N_i][N_i] in the packed field buffers; the fields
  * of different instances must not overlap (TURPY_E_INVALID).  A path that
- * fails turpy_plan_create's validation fails the batch with its status. */
+ * fails turpy_plan_create's validation fails the batch with its status.
+ * flags as for turpy_plan_create, except TURPY_SCREEN_CHECKPOINTS
+ * (TURPY_E_INVALID). */
 turpy_status turpy_batch_create(turpy_batch** out, const turpy_path* paths, const int64_t* field_offsets,
                                 int32_t num_paths, uint32_t flags);
 turpy_status turpy_batch_destroy(turpy_batch* batch);
@@ -385,7 +469,7 @@ turpy_status turpy_batch_tune(turpy_batch* batch, uint32_t flags, void* ws, size
  * starts bracketing every kernel the library enqueues with a pair of HIP events
  * on that kernel's stream; turpy_profile(0) stops recording.  Kernel families:
  * "row_fwd", "row_bwd", "row_plain", "col", "synth", "sh", "evolve", "stats",
- * "finalize", "copy", "recv_row", "recv_col", "recv_col_grad", "recv_row_grad",
+ * "finalize", "copy", "sum", "noise", "recv_row", "recv_col", "recv_col_grad", "recv_row_grad",
  * "recv_reduce".  turpy_profile_read waits for the recorded events and
  * returns the launch count and summed duration (ms) of one family (zero when it
  * never ran).  turpy_profile_only(family) restricts the bracketing to one

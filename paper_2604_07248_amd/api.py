@@ -37,9 +37,35 @@ class Plan:
         tune_cache_from_env()
         with torch.cuda.device(self.device):
             self.handle = B.plan_create(path, flags)
+        self.flags = flags
         self.n, self.m, self.r = path.n, len(path.cn2dz), path.realizations
         self.pairs = (self.r + 1) // 2
         self._ws = {}
+
+    # -- checkpoints -----------------------------------------------------------
+    @property
+    def keeps_screens(self):
+        """Plan created with binding.SCREEN_CHECKPOINTS: the checkpoints also
+        hold the screens' column halves (the adjoint does not synthesise them)."""
+        return bool(self.flags & B.SCREEN_CHECKPOINTS)
+
+    def new_checkpoints(self):
+        """An empty checkpoint buffer: complex64 [R][M][N][N], or, when the plan
+        keeps the screens, a flat complex64 buffer of turpy_checkpoint_size bytes
+        (checkpoint_fields gives its [R][M][N][N] part)."""
+        if self.keeps_screens:
+            return torch.empty(B.checkpoint_size(self.handle) // 8, dtype=torch.complex64, device=self.device)
+        return torch.empty((self.r, self.m, self.n, self.n), dtype=torch.complex64, device=self.device)
+
+    def checkpoint_fields(self, ck):
+        """The fields after each screen, [R][M][N][N], of a checkpoint buffer."""
+        return ck.reshape(-1)[: self.r * self.m * self.n * self.n].view(self.r, self.m, self.n, self.n)
+
+    def _need_ck(self, ck):
+        if self.keeps_screens:
+            _need(ck, torch.complex64, (B.checkpoint_size(self.handle) // 8,), "checkpoints")
+        else:
+            _need(ck, torch.complex64, (self.r, self.m, self.n, self.n), "checkpoints")
 
     def close(self):
         if getattr(self, "handle", None):
@@ -166,19 +192,44 @@ class Plan:
         ck = None
         if isinstance(checkpoints, torch.Tensor):
             ck = checkpoints
-            _need(ck, torch.complex64, (self.r, self.m, self.n, self.n), "checkpoints")
+            self._need_ck(ck)
         elif checkpoints:
-            ck = torch.empty((self.r, self.m, self.n, self.n), dtype=torch.complex64, device=self.device)
+            ck = self.new_checkpoints()
         ws, size = self.workspace(B.OP_PROPAGATE)
         B.propagate(self.handle, seed, t, _ptr(u_in), stride, src, _ptr(sbuf), _ptr(u_out), _ptr(ck), _ptr(ws), size,
                     _stream())
         return (u_out, ck) if ck is not None else u_out
 
+    def evolve_propagate(self, spectra, seed, t, alpha, shift_x=0.0, shift_y=0.0, u_in=None, checkpoints=False,
+                         out=None):
+        """One AR time step: evolve(spectra, seed, t, ...) then
+        propagate(u_in, spectra=spectra), with the evolution fused into the
+        screen synthesis (turpy_evolve_propagate).  Returns like propagate."""
+        self._need_state(spectra)
+        if t < 1:
+            raise ValueError("evolve_propagate: t must be >= 1 (t = 0 is init_spectra)")
+        stride = self._source(u_in)
+        shape = (self.r, self.n, self.n)
+        u_out = torch.empty(shape, dtype=torch.complex64, device=self.device) if out is None else out
+        _need(u_out, torch.complex64, shape, "u_out")
+        ck = None
+        if isinstance(checkpoints, torch.Tensor):
+            ck = checkpoints
+            self._need_ck(ck)
+        elif checkpoints:
+            ck = self.new_checkpoints()
+        ws, size = self.workspace(B.OP_PROPAGATE)
+        B.evolve_propagate(self.handle, seed, t, alpha, shift_x, shift_y, _ptr(spectra), _ptr(u_in), stride,
+                           _ptr(u_out), _ptr(ck), _ptr(ws), size, _stream())
+        return (u_out, ck) if ck is not None else u_out
+
     def propagate_backward(self, grad_out, checkpoints, seed=0, t=0, screens=None, spectra=None, want_input=True,
-                           want_screens=True, u_out=None):
+                           want_screens=True, u_out=None, shared_source=False):
         """Adjoint of propagate.  With checkpoints=None and the forward output
         u_out, the screen-plane fields are rebuilt from u_out instead
-        (turpy_propagate_backward_reversible)."""
+        (turpy_propagate_backward_reversible).  shared_source=True returns the
+        gradient of a source shared by every realization, [N][N] (the library
+        sums over realizations)."""
         shape = (self.r, self.n, self.n)
         _need(grad_out, torch.complex64, shape, "grad_out")
         src, sbuf = self._screen_src(screens, spectra)
@@ -186,18 +237,20 @@ class Plan:
         if reversible:
             _need(u_out, torch.complex64, shape, "u_out")
         elif self.m > 0:
-            _need(checkpoints, torch.complex64, (self.r, self.m, self.n, self.n), "checkpoints")
-        g_in = torch.empty(shape, dtype=torch.complex64, device=self.device) if want_input else None
+            self._need_ck(checkpoints)
+        g_shape = (self.n, self.n) if shared_source else shape
+        g_stride = 0 if shared_source else self.n * self.n
+        g_in = torch.empty(g_shape, dtype=torch.complex64, device=self.device) if want_input else None
         g_phi = (torch.empty((self.r, self.m, self.n, self.n), dtype=torch.float32, device=self.device)
                  if want_screens else None)
         if reversible:
             ws, size = self.workspace(B.OP_PROPAGATE_BACKWARD_REVERSIBLE)
             B.propagate_backward_reversible(self.handle, seed, t, _ptr(grad_out), _ptr(u_out), src, _ptr(sbuf),
-                                            _ptr(g_in), _ptr(g_phi), _ptr(ws), size, _stream())
+                                            _ptr(g_in), g_stride, _ptr(g_phi), _ptr(ws), size, _stream())
         else:
             ws, size = self.workspace(B.OP_PROPAGATE_BACKWARD)
             B.propagate_backward(self.handle, seed, t, _ptr(grad_out), _ptr(checkpoints), src, _ptr(sbuf),
-                                 _ptr(g_in), _ptr(g_phi), _ptr(ws), size, _stream())
+                                 _ptr(g_in), g_stride, _ptr(g_phi), _ptr(ws), size, _stream())
         return g_in, g_phi
 
 
@@ -280,20 +333,40 @@ class Batch:
         _need(u_in, torch.complex64, (self.total,), "u_in")
         out = torch.empty_like(u_in) if out is None else out
         _need(out, torch.complex64, (self.total,), "out")
-        ck = torch.empty(self.ck_total, dtype=torch.complex64, device=self.device) if checkpoints else None
+        ck = None
+        if isinstance(checkpoints, torch.Tensor):
+            ck = checkpoints
+            _need(ck, torch.complex64, (self.ck_total,), "checkpoints")
+        elif checkpoints:
+            ck = torch.empty(self.ck_total, dtype=torch.complex64, device=self.device)
         ws, size = self._workspace(B.OP_PROPAGATE)
         B.batch_propagate(self.handle, seed, t, _ptr(u_in), _ptr(out), _ptr(ck), _ptr(ws), size, _stream())
-        return (out, ck) if checkpoints else out
+        return (out, ck) if ck is not None else out
 
-    def propagate_backward(self, grad_out, checkpoints, seed=0, t=0):
+    def propagate_backward(self, grad_out, checkpoints, seed=0, t=0, grad_in=None, grad_screens=None):
+        """Adjoint of propagate: (dL/du_in packed like the fields, dL/dphi
+        packed like the checkpoints); the output tensors may be given."""
         _need(grad_out, torch.complex64, (self.total,), "grad_out")
         _need(checkpoints, torch.complex64, (self.ck_total,), "checkpoints")
-        g_in = torch.empty_like(grad_out)
-        g_phi = torch.empty(self.ck_total, dtype=torch.float32, device=self.device)
+        g_in = torch.empty_like(grad_out) if grad_in is None else grad_in
+        _need(g_in, torch.complex64, (self.total,), "grad_in")
+        g_phi = (torch.empty(self.ck_total, dtype=torch.float32, device=self.device) if grad_screens is None
+                 else grad_screens)
+        _need(g_phi, torch.float32, (self.ck_total,), "grad_screens")
         ws, size = self._workspace(B.OP_PROPAGATE_BACKWARD)
         B.batch_propagate_backward(self.handle, seed, t, _ptr(grad_out), _ptr(checkpoints), _ptr(g_in), _ptr(g_phi),
                                    _ptr(ws), size, _stream())
         return g_in, g_phi
+
+
+def noise(n, pairs, seed, t=0, tag=1, screen=0, out=None, device=None):
+    """The complex normals N_c of a spectrum, complex64 [pairs][n][n]
+    (turpy_noise: the numbers the synthesis draws for (seed, t, tag, screen))."""
+    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    out = torch.empty((pairs, n, n), dtype=torch.complex64, device=dev) if out is None else out
+    _need(out, torch.complex64, (pairs, n, n), "out")
+    B.noise(n, pairs, seed, t, tag, screen, _ptr(out), _stream())
+    return out
 
 
 TUNE_CACHE_FORMAT = "turpy-tune-cache"
@@ -362,12 +435,19 @@ class Moments:
         B.stats(self.n, self.dx, u.shape[0], _ptr(u), _ptr(self.buf), 0, 0, None, None, _stream())
         self.count += u.shape[0]
 
-    def finalize(self):
+    def finalize(self, weight=None, power_fraction=0.0):
+        """SI map and summary.  The SI entries are taken over the central
+        region, or with power_fraction > 0 over the power-cutoff region of
+        Sec. 4.1 (0.999 there); weight: optional float32 [N][N] weights."""
+        if weight is not None:
+            _need(weight, torch.float32, (self.n, self.n), "weight")
         si = torch.empty((self.n, self.n), dtype=torch.float32, device=self.device)
-        summary = torch.empty(4, dtype=torch.float64, device=self.device)
-        B.stats(self.n, self.dx, 0, None, _ptr(self.buf), self.count, 1, _ptr(si), _ptr(summary), _stream())
+        summary = torch.empty(8, dtype=torch.float64, device=self.device)
+        B.stats(self.n, self.dx, 0, None, _ptr(self.buf), self.count, 1, _ptr(si), _ptr(summary), _stream(),
+                _ptr(weight), power_fraction)
         s = summary.cpu().tolist()
-        return si, {"si_plane": s[0], "w_2nd": s[1], "w_fit": s[2], "count": int(s[3])}
+        return si, {"si_plane": s[0], "w_2nd": s[1], "w_fit": s[2], "count": int(s[3]), "si_sum": s[4],
+                    "region_weight": s[5], "threshold": s[6]}
 
 
 class Receiver:
@@ -377,6 +457,8 @@ class Receiver:
         self.n, self.dx, self.diameter = n, dx, aperture_diameter
         self.device = torch.device(device) if device is not None else torch.device("cuda")
         self._ws = None
+        with torch.cuda.device(self.device):
+            B.receiver_setup(n)
 
     def forward(self, u, theta1, theta2, out=None):
         b = u.shape[0]
@@ -450,7 +532,6 @@ class Propagate(torch.autograd.Function):
         kw = {"u_out": saved} if ctx.reversible else {}
         g_in, g_phi = plan.propagate_backward(grad_out.contiguous(), None if ctx.reversible else saved, ctx.seed,
                                               ctx.t, screens=screens, want_input=want_in,
-                                              want_screens=want_phi and screens is not None, **kw)
-        if g_in is not None and ctx.shared:
-            g_in = g_in.sum(dim=0)
+                                              want_screens=want_phi and screens is not None,
+                                              shared_source=ctx.shared, **kw)
         return g_in, (g_phi if screens is not None and ctx.needs_input_grad[1] else None), None, None, None, None

@@ -17,6 +17,7 @@ CN2_UNIFORM, CN2_HUFNAGEL_VALLEY, CN2_TABLE = 0, 1, 2
 TF_FRESNEL, TF_ANGULAR_SPECTRUM = 0, 1
 SCREENS_SYNTH, SCREENS_MATERIALIZED, SCREENS_SPECTRA = 0, 1, 2
 ALLOW_ALIASING = 1
+SCREEN_CHECKPOINTS = 2
 OP_SCREEN_GENERATE, OP_PROPAGATE, OP_PROPAGATE_BACKWARD, OP_EVOLVE, OP_PROPAGATE_BACKWARD_REVERSIBLE, OP_TUNE = range(6)
 TUNE_COL_FRESNEL, TUNE_COL_ANGULAR, TUNE_COL_AS_TABLE, TUNE_SYNTH = range(4)
 TUNE_KERNELS = ("col_fresnel", "col_angular", "col_as_table", "synth")
@@ -32,7 +33,7 @@ EXPORTS = [
     "turpy_batch_create", "turpy_batch_destroy", "turpy_batch_bind_time", "turpy_batch_workspace_size",
     "turpy_batch_propagate", "turpy_batch_propagate_backward", "turpy_plan_tune", "turpy_plan_widths",
     "turpy_plan_set_widths", "turpy_tune_cache_get", "turpy_tune_cache_put", "turpy_tune_cache_clear",
-    "turpy_batch_tune",
+    "turpy_batch_tune", "turpy_receiver_setup", "turpy_noise", "turpy_checkpoint_size", "turpy_evolve_propagate",
 ]
 
 
@@ -93,18 +94,23 @@ def lib():
         L.turpy_plan_create.argtypes = [POINTER(c_void_p), POINTER(CPath), c_uint32]
         L.turpy_plan_destroy.argtypes = [c_void_p]
         L.turpy_workspace_size.argtypes = [c_void_p, c_int32, POINTER(c_size_t)]
+        L.turpy_checkpoint_size.argtypes = [c_void_p, POINTER(c_size_t)]
+        L.turpy_evolve_propagate.argtypes = [c_void_p, c_uint64, c_int64, c_double, c_double, c_double, c_void_p,
+                                             c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]
         L.turpy_screen_generate.argtypes = [c_void_p, c_uint64, c_int64, c_void_p, c_void_p, c_size_t, c_void_p]
         L.turpy_propagate.argtypes = [c_void_p, c_uint64, c_int64, c_void_p, c_int64, c_int32, c_void_p, c_void_p,
                                       c_void_p, c_void_p, c_size_t, c_void_p]
         L.turpy_evolve.argtypes = [c_void_p, c_uint64, c_int64, c_double, c_double, c_double, c_void_p, c_void_p,
                                    c_size_t, c_void_p]
         L.turpy_propagate_backward.argtypes = [c_void_p, c_uint64, c_int64, c_void_p, c_void_p, c_int32, c_void_p,
-                                               c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]
+                                               c_void_p, c_int64, c_void_p, c_void_p, c_size_t, c_void_p]
         L.turpy_propagate_backward_reversible.argtypes = [c_void_p, c_uint64, c_int64, c_void_p, c_void_p, c_int32,
-                                                          c_void_p, c_void_p, c_void_p, c_void_p, c_size_t,
+                                                          c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_size_t,
                                                           c_void_p]
         L.turpy_stats.argtypes = [c_int32, c_double, c_int64, c_void_p, c_void_p, c_int64, c_int32, c_void_p,
-                                  c_void_p, c_void_p]
+                                  c_double, c_void_p, c_void_p, c_void_p]
+        L.turpy_receiver_setup.argtypes = [c_int32]
+        L.turpy_noise.argtypes = [c_int32, c_int64, c_uint64, c_int64, c_int32, c_int32, c_void_p, c_void_p]
         L.turpy_receiver_workspace_size.argtypes = [c_int32, c_int64, POINTER(c_size_t)]
         L.turpy_receiver.argtypes = [c_int32, c_double, c_double, c_int64, c_void_p, c_void_p, c_void_p, c_void_p,
                                      c_void_p, c_size_t, c_void_p]
@@ -218,6 +224,12 @@ def plan_destroy(handle):
         check(lib().turpy_plan_destroy(handle))
 
 
+def checkpoint_size(handle):
+    out = c_size_t()
+    check(lib().turpy_checkpoint_size(handle, ctypes.byref(out)))
+    return out.value
+
+
 def workspace_size(handle, op):
     out = c_size_t()
     check(lib().turpy_workspace_size(handle, op, ctypes.byref(out)))
@@ -238,20 +250,36 @@ def evolve(handle, seed, t, alpha, sx, sy, spectra_ptr, ws_ptr, ws_bytes, stream
     check(lib().turpy_evolve(handle, seed, t, alpha, sx, sy, spectra_ptr, ws_ptr, ws_bytes, stream))
 
 
-def propagate_backward(handle, seed, t, gout_ptr, ckpt_ptr, src, screens_ptr, gin_ptr, gscreens_ptr, ws_ptr,
-                       ws_bytes, stream):
-    check(lib().turpy_propagate_backward(handle, seed, t, gout_ptr, ckpt_ptr, src, screens_ptr, gin_ptr,
+def evolve_propagate(handle, seed, t, alpha, sx, sy, state_ptr, u_in_ptr, u_in_stride, u_out_ptr, ckpt_ptr, ws_ptr,
+                     ws_bytes, stream):
+    check(lib().turpy_evolve_propagate(handle, seed, t, alpha, sx, sy, state_ptr, u_in_ptr, u_in_stride, u_out_ptr,
+                                       ckpt_ptr, ws_ptr, ws_bytes, stream))
+
+
+def propagate_backward(handle, seed, t, gout_ptr, ckpt_ptr, src, screens_ptr, gin_ptr, gin_stride, gscreens_ptr,
+                       ws_ptr, ws_bytes, stream):
+    check(lib().turpy_propagate_backward(handle, seed, t, gout_ptr, ckpt_ptr, src, screens_ptr, gin_ptr, gin_stride,
                                          gscreens_ptr, ws_ptr, ws_bytes, stream))
 
 
-def propagate_backward_reversible(handle, seed, t, gout_ptr, uout_ptr, src, screens_ptr, gin_ptr, gscreens_ptr,
-                                  ws_ptr, ws_bytes, stream):
+def propagate_backward_reversible(handle, seed, t, gout_ptr, uout_ptr, src, screens_ptr, gin_ptr, gin_stride,
+                                  gscreens_ptr, ws_ptr, ws_bytes, stream):
     check(lib().turpy_propagate_backward_reversible(handle, seed, t, gout_ptr, uout_ptr, src, screens_ptr, gin_ptr,
-                                                    gscreens_ptr, ws_ptr, ws_bytes, stream))
+                                                    gin_stride, gscreens_ptr, ws_ptr, ws_bytes, stream))
 
 
-def stats(n, dx, batch, u_ptr, moments_ptr, count, finalize, si_ptr, summary_ptr, stream):
-    check(lib().turpy_stats(n, dx, batch, u_ptr, moments_ptr, count, finalize, si_ptr, summary_ptr, stream))
+def stats(n, dx, batch, u_ptr, moments_ptr, count, finalize, si_ptr, summary_ptr, stream, weight_ptr=None,
+          power_fraction=0.0):
+    check(lib().turpy_stats(n, dx, batch, u_ptr, moments_ptr, count, finalize, weight_ptr, power_fraction, si_ptr,
+                            summary_ptr, stream))
+
+
+def noise(n, pairs, seed, t, tag, screen, out_ptr, stream):
+    check(lib().turpy_noise(n, pairs, seed, t, tag, screen, out_ptr, stream))
+
+
+def receiver_setup(n):
+    check(lib().turpy_receiver_setup(n))
 
 
 def receiver_workspace_size(n, batch):

@@ -147,6 +147,7 @@ struct turpy_plan {
   const uint32_t* d_t = nullptr; // bound device time step (turpy_plan_bind_time), or NULL
   // strip widths of the column pass and the synthesis (0: built-in choice for n)
   int col_width = 0, synth_width = 0;
+  bool screen_ck = false;        // TURPY_SCREEN_CHECKPOINTS: checkpoints keep the screens' column halves
   std::string arch;              // device architecture (tuning-cache key)
 
   size_t plane_bytes() const { return static_cast<size_t>(n) * n * sizeof(float2); }
@@ -178,6 +179,8 @@ const char* turpy_last_error(void) { return g_last_error.c_str(); }
 turpy_status turpy_plan_create(turpy_plan** out, const turpy_path* p, uint32_t flags) {
   if (!out || !p) return fail(TURPY_E_INVALID, "plan_create: NULL argument");
   *out = nullptr;
+  if (flags & ~(TURPY_ALLOW_ALIASING | TURPY_SCREEN_CHECKPOINTS))
+    return fail(TURPY_E_INVALID, "plan_create: unknown flags 0x%x", flags);
   if (!pow2(p->n)) return fail(TURPY_E_INVALID, "plan_create: n=%d is not a power of two", p->n);
   if (p->n < 16 || p->n > 2048) return fail(TURPY_E_UNSUPPORTED, "plan_create: n=%d outside 16..2048", p->n);
   if (p->num_screens < 0) return fail(TURPY_E_INVALID, "plan_create: num_screens < 0");
@@ -223,6 +226,7 @@ turpy_status turpy_plan_create(turpy_plan** out, const turpy_path* p, uint32_t f
   pl->conv = p->inner_scale_conv;
   pl->R = p->realizations;
   pl->P = (p->realizations + 1) / 2;
+  pl->screen_ck = (flags & TURPY_SCREEN_CHECKPOINTS) != 0;
   pl->dx = p->dx;
   pl->wavelength = p->wavelength;
   pl->n0 = p->n0;
@@ -371,6 +375,13 @@ turpy_status turpy_plan_destroy(turpy_plan* pl) {
   return TURPY_OK;
 }
 
+turpy_status turpy_checkpoint_size(const turpy_plan* pl, size_t* bytes) {
+  if (!pl || !bytes) return fail(TURPY_E_INVALID, "checkpoint_size: NULL argument");
+  const size_t plane = static_cast<size_t>(pl->n) * pl->n * sizeof(float2);
+  *bytes = static_cast<size_t>(pl->R) * pl->M * plane + (pl->screen_ck ? static_cast<size_t>(pl->M) * pl->P * plane : 0);
+  return TURPY_OK;
+}
+
 turpy_status turpy_workspace_size(const turpy_plan* pl, int32_t op, size_t* bytes) {
   if (!pl || !bytes) return fail(TURPY_E_INVALID, "workspace_size: NULL argument");
   switch (op) {
@@ -393,12 +404,27 @@ struct Ws {
   float2* sh;
   float2* src;
   float2* gbuf;
+  // column halves of the screens kept with the checkpoints (plans created with
+  // TURPY_SCREEN_CHECKPOINTS): [M][P][N][N], or NULL to use `scratch`
+  float2* screens = nullptr;
+  size_t screen_stride = 0;
+  float2* screen(int s) const { return screens ? screens + static_cast<size_t>(s) * screen_stride : scratch; }
 };
 
 Ws carve(const turpy_plan* pl, void* ws) {
   char* b = static_cast<char*>(ws);
   return Ws{reinterpret_cast<float2*>(b), reinterpret_cast<float2*>(b + pl->off_sh()),
             reinterpret_cast<float2*>(b + pl->off_src()), reinterpret_cast<float2*>(b + pl->off_gbuf())};
+}
+
+// With TURPY_SCREEN_CHECKPOINTS and a checkpoint buffer, the screens' column
+// halves live after the checkpointed fields: the forward pass writes them
+// there and the adjoint reads them instead of synthesising them again.
+void keep_screens(const turpy_plan* pl, void* checkpoints, int32_t src, Ws* w) {
+  if (!pl->screen_ck || !checkpoints || src == TURPY_SCREENS_MATERIALIZED || pl->M == 0) return;
+  const size_t plane = static_cast<size_t>(pl->n) * pl->n;
+  w->screens = static_cast<float2*>(checkpoints) + static_cast<size_t>(pl->R) * pl->M * plane;
+  w->screen_stride = static_cast<size_t>(pl->P) * plane;
 }
 
 void key_of(uint64_t seed, uint32_t* k0, uint32_t* k1) {
@@ -450,10 +476,16 @@ ColArgs col_args(const turpy_plan* pl, int step, const float2* in, int64_t in_st
   return c;
 }
 
-SynthArgs synth_args(const turpy_plan* pl, uint64_t seed, uint32_t t, int s, const float2* spectra, const Ws& w) {
+// An AR step fused into the synthesis (turpy_evolve_propagate).
+struct EvolveStep {
+  double alpha, sx, sy;
+};
+
+SynthArgs synth_args(const turpy_plan* pl, uint64_t seed, uint32_t t, int s, const float2* spectra, const Ws& w,
+                     const EvolveStep* ev = nullptr) {
   SynthArgs a{};
   a.tw = pl->d_tw;
-  a.scratch = w.scratch;
+  a.scratch = w.screen(s);
   a.P = pl->P;
   key_of(seed, &a.key0, &a.key1);
   a.t = t;
@@ -468,12 +500,22 @@ SynthArgs synth_args(const turpy_plan* pl, uint64_t seed, uint32_t t, int s, con
   a.spectra = spectra;
   a.M = pl->M;
   a.width = pl->synth_width;
+  if (ev) {
+    a.evolve = 1;
+    a.state = const_cast<float2*>(spectra);
+    a.ar_tag = TAG_AR;
+    a.alpha_f = static_cast<float>(ev->alpha);
+    a.blend = static_cast<float>(std::sqrt(1.0 - ev->alpha * ev->alpha));
+    a.sx = ev->sx;
+    a.sy = ev->sy;
+    a.amp_rad = pl->amp_rad[s];
+  }
   return a;
 }
 
 hipError_t enqueue_screen_col(const turpy_plan* pl, uint64_t seed, uint32_t t, int s, const float2* spectra,
-                              const Ws& w, hipStream_t st) {
-  const SynthArgs a = synth_args(pl, seed, t, s, spectra, w);
+                              const Ws& w, hipStream_t st, const EvolveStep* ev = nullptr) {
+  const SynthArgs a = synth_args(pl, seed, t, s, spectra, w, ev);
   return timed("synth", st, [&] { return launch_synth(pl->n, a, st); });
 }
 
@@ -481,10 +523,10 @@ hipError_t enqueue_screen_col(const turpy_plan* pl, uint64_t seed, uint32_t t, i
 // the column half of that screen's synthesis follows it into ws.scratch.
 hipError_t enqueue_col(const turpy_plan* pl, int step, const float2* in, int64_t in_stride, float2* out,
                        bool adjoint, int synth_screen, uint64_t seed, uint32_t t, const float2* spectra,
-                       const Ws& w, hipStream_t st) {
+                       const Ws& w, hipStream_t st, const EvolveStep* ev = nullptr) {
   const ColArgs c = col_args(pl, step, in, in_stride, out, pl->R, adjoint);
   TURPY_HIP_E(timed("col", st, [&] { return launch_col(pl->n, c, st); }));
-  if (synth_screen >= 0) return enqueue_screen_col(pl, seed, t, synth_screen, spectra, w, st);
+  if (synth_screen >= 0) return enqueue_screen_col(pl, seed, t, synth_screen, spectra, w, st, ev);
   return hipSuccess;
 }
 
@@ -527,7 +569,7 @@ turpy_status screen_fields(const turpy_plan* pl, int32_t src, const void* screen
     a->screens = static_cast<const float*>(screens_or_spectra);
   } else {
     a->screen_mode = ROW_SCRATCH;
-    a->scratch = w.scratch;
+    a->scratch = w.screen(s);
     a->sh_levels = pl->sh_levels;
     if (src == TURPY_SCREENS_SYNTH) {
       a->sh = w.sh;
@@ -570,7 +612,9 @@ size_t receiver_ws(int32_t n, int64_t batch) {
   return 2 * align_up(batch * plane * sizeof(float2)) + align_up(chunks * plane * sizeof(float));
 }
 
-// Process-wide FP64-generated twiddle tables per (device, N) for plan-less calls.
+// Process-wide FP64-generated twiddle tables per (device, N) for the plan-less
+// receiver calls, built by turpy_receiver_setup (a set-up call: it allocates
+// and uploads synchronously); the stream-ordered calls only look them up.
 std::mutex g_tw_mutex;
 std::map<std::pair<int, int>, float2*> g_tw_cache;
 
@@ -579,17 +623,34 @@ turpy_status twiddles_for(int n, const float2** out) {
   TURPY_HIP(hipGetDevice(&dev), "twiddle table");
   std::lock_guard<std::mutex> lock(g_tw_mutex);
   auto it = g_tw_cache.find({dev, n});
-  if (it != g_tw_cache.end()) {
-    *out = it->second;
-    return TURPY_OK;
-  }
-  std::vector<float2> tw(n);
-  for (int i = 0; i < n; ++i) tw[i] = phasor(-static_cast<double>(i) / n);
-  float2* d = nullptr;
-  TURPY_HIP(hipMalloc(&d, n * sizeof(float2)), "twiddle table");
-  TURPY_HIP(hipMemcpy(d, tw.data(), n * sizeof(float2), hipMemcpyHostToDevice), "twiddle table");
-  g_tw_cache[{dev, n}] = d;
-  *out = d;
+  if (it == g_tw_cache.end())
+    return fail(TURPY_E_INVALID, "receiver: no tables for n=%d on device %d (call turpy_receiver_setup first)", n,
+                dev);
+  *out = it->second;
+  return TURPY_OK;
+}
+
+// The end of the adjoint for a source shared by every realization, on the
+// one plane `sum` that already holds the gradients summed over realizations
+// (row-spectral when `spectral`): the diffraction before screen 0 is the same
+// linear map for every realization, so it runs once, on the sum (column pass
+// with conj h_0, then the adjoint of the source row transform into grad_u_in).
+// Without that diffraction the sum was written to grad_u_in directly.
+turpy_status adjoint_shared_tail(const turpy_plan* pl, float2* sum, bool spectral, float2* grad_u_in, hipStream_t st) {
+  if (!spectral) return TURPY_OK;
+  const int64_t plane = static_cast<int64_t>(pl->n) * pl->n;
+  const ColArgs c = col_args(pl, 0, sum, plane, sum, 1, true);
+  TURPY_HIP(timed("col", st, [&] { return launch_col(pl->n, c, st); }), "propagate_backward: shared column pass");
+  RowArgs a = base_row(pl);
+  a.in = sum;
+  a.in_stride = plane;
+  a.out = grad_u_in;
+  a.R = 1;
+  a.in_spectral = 1;
+  a.pre = pl->d_row;
+  a.conj_tables = 1;
+  TURPY_HIP(timed(row_family(a), st, [&] { return launch_row(pl->n, a, 1, st); }),
+            "propagate_backward: shared last row pass");
   return TURPY_OK;
 }
 
@@ -620,9 +681,15 @@ turpy_status turpy_screen_generate(turpy_plan* pl, uint64_t seed, int64_t t, flo
   return TURPY_OK;
 }
 
-turpy_status turpy_propagate(turpy_plan* pl, uint64_t seed, int64_t t, const void* u_in, int64_t u_in_stride,
-                             int32_t src, const void* screens_or_spectra, void* u_out, void* checkpoints, void* ws,
-                             size_t ws_bytes, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// turpy_propagate; with `ev`, every screen's synthesis first takes the AR step
+// of its stored spectra (turpy_evolve_propagate).
+turpy_status propagate_impl(turpy_plan* pl, uint64_t seed, int64_t t, const void* u_in, int64_t u_in_stride,
+                            int32_t src, const void* screens_or_spectra, void* u_out, void* checkpoints, void* ws,
+                            size_t ws_bytes, void* stream, const EvolveStep* ev) {
   if (!pl || !u_in || !u_out) return fail(TURPY_E_INVALID, "propagate: NULL argument");
   if (turpy_status s_ = check_t(t)) return s_;
   if (turpy_status s_ = check_device(pl)) return s_;
@@ -635,7 +702,8 @@ turpy_status turpy_propagate(turpy_plan* pl, uint64_t seed, int64_t t, const voi
   if (!ws || ws_bytes < pl->ws_forward())
     return fail(TURPY_E_WORKSPACE, "propagate: workspace %zu < %zu bytes", ws_bytes, pl->ws_forward());
   hipStream_t st = static_cast<hipStream_t>(stream);
-  const Ws w = carve(pl, ws);
+  Ws w = carve(pl, ws);
+  keep_screens(pl, checkpoints, src, &w);
   const int n = pl->n, M = pl->M;
   const float inv_n = 1.0f / n;
   const float2* uin = static_cast<const float2*>(u_in);
@@ -678,7 +746,7 @@ turpy_status turpy_propagate(turpy_plan* pl, uint64_t seed, int64_t t, const voi
       cur_stride = 0;
     } else {
       const int syn = synth && M > 0 ? 0 : -1;
-      TURPY_HIP(enqueue_col(pl, 0, dst, plane, uout, false, syn, seed, tt, spectra, w, st),
+      TURPY_HIP(enqueue_col(pl, 0, dst, plane, uout, false, syn, seed, tt, spectra, w, st, ev),
                 "propagate: column pass 0");
       scratch_ready = syn >= 0;
       cur = uout;
@@ -688,7 +756,7 @@ turpy_status turpy_propagate(turpy_plan* pl, uint64_t seed, int64_t t, const voi
   }
   for (int s = 0; s < M; ++s) {
     if (synth && !scratch_ready)
-      TURPY_HIP(enqueue_screen_col(pl, seed, tt, s, spectra, w, st), "propagate: screen col");
+      TURPY_HIP(enqueue_screen_col(pl, seed, tt, s, spectra, w, st, ev), "propagate: screen col");
     const bool out_spec = pl->dz[s + 1] > 0;
     RowArgs a = base_row(pl);
     a.in = cur;
@@ -707,7 +775,7 @@ turpy_status turpy_propagate(turpy_plan* pl, uint64_t seed, int64_t t, const voi
     scratch_ready = false;
     if (out_spec) {
       const int syn = synth && s + 1 < M ? s + 1 : -1;
-      TURPY_HIP(enqueue_col(pl, s + 1, uout, plane, uout, false, syn, seed, tt, spectra, w, st),
+      TURPY_HIP(enqueue_col(pl, s + 1, uout, plane, uout, false, syn, seed, tt, spectra, w, st, ev),
                 "propagate: column pass");
       scratch_ready = syn >= 0;
     }
@@ -726,32 +794,99 @@ turpy_status turpy_propagate(turpy_plan* pl, uint64_t seed, int64_t t, const voi
   return TURPY_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+turpy_status turpy_propagate(turpy_plan* pl, uint64_t seed, int64_t t, const void* u_in, int64_t u_in_stride,
+                             int32_t src, const void* screens_or_spectra, void* u_out, void* checkpoints, void* ws,
+                             size_t ws_bytes, void* stream) {
+  return propagate_impl(pl, seed, t, u_in, u_in_stride, src, screens_or_spectra, u_out, checkpoints, ws, ws_bytes,
+                        stream, nullptr);
+}
+
+turpy_status turpy_evolve_propagate(turpy_plan* pl, uint64_t seed, int64_t t, double alpha, double shift_x,
+                                    double shift_y, void* state, const void* u_in, int64_t u_in_stride, void* u_out,
+                                    void* checkpoints, void* ws, size_t ws_bytes, void* stream) {
+  if (!pl || !state) return fail(TURPY_E_INVALID, "evolve_propagate: NULL argument");
+  if (turpy_status s_ = check_t(t)) return s_;
+  if (t < 1) return fail(TURPY_E_INVALID, "evolve_propagate: t must be >= 1 (t = 0 initialises with turpy_evolve)");
+  if (!(alpha >= 0.0 && alpha <= 1.0)) return fail(TURPY_E_INVALID, "evolve_propagate: alpha must be in [0, 1]");
+  if (!std::isfinite(shift_x) || !std::isfinite(shift_y))
+    return fail(TURPY_E_INVALID, "evolve_propagate: non-finite shift");
+  if (turpy_status s_ = check_device(pl)) return s_;
+  if (!u_in || !u_out) return fail(TURPY_E_INVALID, "evolve_propagate: NULL argument");
+  if (!ws || ws_bytes < pl->ws_forward())
+    return fail(TURPY_E_WORKSPACE, "evolve_propagate: workspace %zu < %zu bytes", ws_bytes, pl->ws_forward());
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (pl->sh_levels > 0 && pl->M > 0) {
+    // the subharmonic coefficients: the same translation and blend at their frequencies
+    ShArgs b = sh_args(pl, seed, static_cast<uint32_t>(t), state_sh(pl, state));
+    b.scale = static_cast<float>(2.0 * kPi);
+    b.ar = 1;
+    b.tag = TAG_AR_SH;
+    b.alpha = alpha;
+    b.sx = shift_x;
+    b.sy = shift_y;
+    TURPY_HIP(timed("sh", st, [&] { return launch_sh(b, st); }), "evolve_propagate: subharmonics");
+  }
+  const EvolveStep ev{alpha, shift_x, shift_y};
+  return propagate_impl(pl, seed, t, u_in, u_in_stride, TURPY_SCREENS_SPECTRA, state, u_out, checkpoints, ws,
+                        ws_bytes, stream, pl->M > 0 ? &ev : nullptr);
+}
+
 turpy_status turpy_propagate_backward(turpy_plan* pl, uint64_t seed, int64_t t, const void* grad_u_out,
                                       const void* checkpoints, int32_t src, const void* screens_or_spectra,
-                                      void* grad_u_in, float* grad_screens, void* ws, size_t ws_bytes,
-                                      void* stream) {
+                                      void* grad_u_in, int64_t grad_u_in_stride, float* grad_screens, void* ws,
+                                      size_t ws_bytes, void* stream) {
   if (!pl || !grad_u_out) return fail(TURPY_E_INVALID, "propagate_backward: NULL argument");
   if (turpy_status s_ = check_t(t)) return s_;
   if (turpy_status s_ = check_device(pl)) return s_;
   if (turpy_status s_ = check_src(pl, src, screens_or_spectra)) return s_;
-  if (pl->M > 0 && !checkpoints) return fail(TURPY_E_INVALID, "propagate_backward: checkpoints are required");
+  const int n = pl->n, M = pl->M;
+  const int64_t plane = static_cast<int64_t>(n) * n;
+  if (grad_u_in_stride != 0 && grad_u_in_stride != plane)
+    return fail(TURPY_E_INVALID, "propagate_backward: grad_u_in_stride must be 0 or N*N");
+  if (M > 0 && !checkpoints) return fail(TURPY_E_INVALID, "propagate_backward: checkpoints are required");
   if (!ws || ws_bytes < pl->ws_backward())
     return fail(TURPY_E_WORKSPACE, "propagate_backward: workspace %zu < %zu bytes", ws_bytes, pl->ws_backward());
   hipStream_t st = static_cast<hipStream_t>(stream);
-  const Ws w = carve(pl, ws);
-  const int n = pl->n, M = pl->M;
-  const int64_t plane = static_cast<int64_t>(n) * n;
+  Ws w = carve(pl, ws);
+  keep_screens(pl, const_cast<void*>(checkpoints), src, &w);
+  const bool stored = w.screens != nullptr;  // the forward pass kept the screens' column halves
   const float inv_n = 1.0f / n;
-  float2* g = grad_u_in ? static_cast<float2*>(grad_u_in) : w.gbuf;
+  // a shared source receives the sum over realizations: the realizations'
+  // gradients are carried in the workspace up to screen 0 and summed there
+  const bool shared = grad_u_in && grad_u_in_stride == 0;
+  float2* g = grad_u_in && !shared ? static_cast<float2*>(grad_u_in) : w.gbuf;
   const float2* gout = static_cast<const float2*>(grad_u_out);
   const float2* spectra = src == TURPY_SCREENS_SPECTRA ? static_cast<const float2*>(screens_or_spectra) : nullptr;
+
+  if (shared && M == 0) {
+    // no screen: the sum of the output gradients goes through the one diffraction
+    float2* dst = pl->dz[0] > 0 ? w.src : static_cast<float2*>(grad_u_in);
+    TURPY_HIP(timed("sum", st, [&] { return launch_sum_planes(gout, pl->R, plane, dst, st); }),
+              "propagate_backward: sum over realizations");
+    if (pl->dz[0] > 0) {
+      RowArgs a = base_row(pl);  // adjoint of the final (1/N) inverse row transform
+      a.in = w.src;
+      a.in_stride = plane;
+      a.out = w.src;
+      a.R = 1;
+      a.out_spectral = 1;
+      a.scale = inv_n;
+      TURPY_HIP(timed(row_family(a), st, [&] { return launch_row(n, a, 1, st); }),
+                "propagate_backward: first row pass");
+    }
+    return adjoint_shared_tail(pl, w.src, pl->dz[0] > 0, static_cast<float2*>(grad_u_in), st);
+  }
 
   if (src == TURPY_SCREENS_SYNTH && pl->sh_levels > 0 && M > 0)
     TURPY_HIP(enqueue_sh(pl, seed, static_cast<uint32_t>(t), w, st), "propagate_backward: sh");
 
   const float2* cur = gout;
   bool spectral = false;
-  const bool synth = src != TURPY_SCREENS_MATERIALIZED;
+  const bool synth = src != TURPY_SCREENS_MATERIALIZED && !stored;
   const uint32_t tt = static_cast<uint32_t>(t);
   bool scratch_ready = false;
   if (pl->dz[M] > 0) {
@@ -792,6 +927,12 @@ turpy_status turpy_propagate_backward(turpy_plan* pl, uint64_t seed, int64_t t, 
     cur = g;
     spectral = out_spec;
     scratch_ready = false;
+    if (s == 0 && shared) {
+      float2* dst = spectral ? w.src : static_cast<float2*>(grad_u_in);
+      TURPY_HIP(timed("sum", st, [&] { return launch_sum_planes(g, pl->R, plane, dst, st); }),
+                "propagate_backward: sum over realizations");
+      return adjoint_shared_tail(pl, w.src, spectral, static_cast<float2*>(grad_u_in), st);
+    }
     if (out_spec) {
       const int syn = synth && s > 0 ? s - 1 : -1;
       TURPY_HIP(enqueue_col(pl, s, g, plane, g, true, syn, seed, tt, spectra, w, st),
@@ -816,25 +957,34 @@ turpy_status turpy_propagate_backward(turpy_plan* pl, uint64_t seed, int64_t t, 
 
 turpy_status turpy_propagate_backward_reversible(turpy_plan* pl, uint64_t seed, int64_t t, const void* grad_u_out,
                                                  const void* u_out, int32_t src, const void* screens_or_spectra,
-                                                 void* grad_u_in, float* grad_screens, void* ws, size_t ws_bytes,
-                                                 void* stream) {
+                                                 void* grad_u_in, int64_t grad_u_in_stride, float* grad_screens,
+                                                 void* ws, size_t ws_bytes, void* stream) {
   if (!pl || !grad_u_out) return fail(TURPY_E_INVALID, "propagate_backward_reversible: NULL argument");
   if (turpy_status s_ = check_t(t)) return s_;
   if (turpy_status s_ = check_device(pl)) return s_;
   if (turpy_status s_ = check_src(pl, src, screens_or_spectra)) return s_;
   const int n = pl->n, M = pl->M;
+  const int64_t plane = static_cast<int64_t>(n) * n;
+  if (grad_u_in_stride != 0 && grad_u_in_stride != plane)
+    return fail(TURPY_E_INVALID, "propagate_backward_reversible: grad_u_in_stride must be 0 or N*N");
   if (M == 0)  // nothing to rebuild: the plain adjoint needs no checkpoints
     return turpy_propagate_backward(pl, seed, t, grad_u_out, nullptr, src, screens_or_spectra, grad_u_in,
-                                    grad_screens, ws, ws_bytes, stream);
+                                    grad_u_in_stride, grad_screens, ws, ws_bytes, stream);
+  if (pl->d_as)
+    // evanescent bins (|H| < 1): the conjugate step damps them again instead
+    // of undoing the forward step, so the fields cannot be rebuilt
+    return fail(TURPY_E_UNSUPPORTED,
+                "propagate_backward_reversible: the angular-spectrum transfer function of this grid has evanescent "
+                "bins, so the path is not unitary; use turpy_propagate_backward with checkpoints");
   if (!u_out) return fail(TURPY_E_INVALID, "propagate_backward_reversible: u_out is required");
   if (!ws || ws_bytes < pl->ws_reversible())
     return fail(TURPY_E_WORKSPACE, "propagate_backward_reversible: workspace %zu < %zu bytes", ws_bytes,
                 pl->ws_reversible());
   hipStream_t st = static_cast<hipStream_t>(stream);
   const Ws w = carve(pl, ws);
-  const int64_t plane = static_cast<int64_t>(n) * n;
   const float inv_n = 1.0f / n;
-  float2* g = grad_u_in ? static_cast<float2*>(grad_u_in) : w.gbuf;
+  const bool shared = grad_u_in && grad_u_in_stride == 0;
+  float2* g = grad_u_in && !shared ? static_cast<float2*>(grad_u_in) : w.gbuf;
   float2* ub = reinterpret_cast<float2*>(static_cast<char*>(ws) + pl->off_ubuf());
   float2* wb = ub + static_cast<size_t>(pl->R) * plane;
   const float2* gout = static_cast<const float2*>(grad_u_out);
@@ -895,6 +1045,12 @@ turpy_status turpy_propagate_backward_reversible(turpy_plan* pl, uint64_t seed, 
       }
       TURPY_HIP(timed(row_family(a), st, [&] { return launch_row(n, a, pl->P, st); }),
                 "propagate_backward_reversible: row pass");
+      if (chain == 0 && s == 0 && shared) {
+        float2* dst = out_spec ? w.src : static_cast<float2*>(grad_u_in);
+        TURPY_HIP(timed("sum", st, [&] { return launch_sum_planes(g, pl->R, plane, dst, st); }),
+                  "propagate_backward_reversible: sum over realizations");
+        return adjoint_shared_tail(pl, w.src, out_spec, static_cast<float2*>(grad_u_in), st);
+      }
       if (cont)
         TURPY_HIP(enqueue_col(pl, s, a.out, plane, a.out, true, -1, seed, tt, spectra, w, st),
                   "propagate_backward_reversible: column pass");
@@ -965,6 +1121,28 @@ turpy_status turpy_evolve(turpy_plan* pl, uint64_t seed, int64_t t, double alpha
   return TURPY_OK;
 }
 
+turpy_status turpy_noise(int32_t n, int64_t pairs, uint64_t seed, int64_t t, int32_t tag, int32_t screen, void* out,
+                         void* stream) {
+  if (!pow2(n) || n < 2 || n > 65536) return fail(TURPY_E_INVALID, "noise: n=%d is not a power of two in 2..65536", n);
+  if (pairs < 0 || pairs > 0xFFFFFFFFll) return fail(TURPY_E_INVALID, "noise: pairs out of range");
+  if (tag < 1 || tag > 15) return fail(TURPY_E_INVALID, "noise: tag must be in 1..15");
+  if (screen < 0 || screen >= (1 << 28)) return fail(TURPY_E_INVALID, "noise: screen out of range");
+  if (turpy_status st = check_t(t)) return st;
+  if (pairs == 0) return TURPY_OK;
+  if (!out) return fail(TURPY_E_INVALID, "noise: out is NULL");
+  NoiseArgs a{};
+  a.out = static_cast<float2*>(out);
+  a.pairs = pairs;
+  a.n = n;
+  key_of(seed, &a.key0, &a.key1);
+  a.t = static_cast<uint32_t>(t);
+  a.tag = static_cast<uint32_t>(tag);
+  a.screen = static_cast<uint32_t>(screen);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  TURPY_HIP(timed("noise", st, [&] { return launch_noise(a, st); }), "noise");
+  return TURPY_OK;
+}
+
 turpy_status turpy_plan_bind_time(turpy_plan* pl, const void* dev_t) {
   if (!pl) return fail(TURPY_E_INVALID, "plan_bind_time: NULL plan");
   if (reinterpret_cast<uintptr_t>(dev_t) % 4 != 0) return fail(TURPY_E_INVALID, "plan_bind_time: misaligned");
@@ -980,10 +1158,13 @@ turpy_status turpy_state_size(const turpy_plan* pl, size_t* bytes) {
 }
 
 turpy_status turpy_stats(int32_t n, double dx, int64_t batch, const void* u, float* moments, int64_t count,
-                         int32_t finalize, float* si_map, double* summary, void* stream) {
+                         int32_t finalize, const float* weight, double power_fraction, float* si_map, double* summary,
+                         void* stream) {
   if (n < 1 || n > 65536) return fail(TURPY_E_INVALID, "stats: n=%d out of range", n);
   if (!moments) return fail(TURPY_E_INVALID, "stats: moments is NULL");
   if (batch < 0) return fail(TURPY_E_INVALID, "stats: batch < 0");
+  if (!(power_fraction >= 0.0 && power_fraction <= 1.0))
+    return fail(TURPY_E_INVALID, "stats: power_fraction must be in [0, 1]");
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (batch > 0) {
     if (!u) return fail(TURPY_E_INVALID, "stats: u is NULL");
@@ -994,7 +1175,7 @@ turpy_status turpy_stats(int32_t n, double dx, int64_t batch, const void* u, flo
     if (!summary) return fail(TURPY_E_INVALID, "stats: summary is NULL");
     if (count < 1) return fail(TURPY_E_INVALID, "stats: count must be >= 1 to finalize");
     if (!(dx > 0)) return fail(TURPY_E_INVALID, "stats: dx must be > 0");
-    FinalizeArgs a{moments, n, dx, static_cast<double>(count), si_map, summary};
+    FinalizeArgs a{moments, n, dx, static_cast<double>(count), si_map, summary, weight, power_fraction};
     TURPY_HIP(timed("finalize", st, [&] { return launch_finalize(a, st); }), "stats: finalize");
   }
   return TURPY_OK;
@@ -1024,6 +1205,25 @@ turpy_status turpy_profile_read(const char* family, int64_t* launches, double* t
     *total_ms += ms;
     ++*launches;
   }
+  return TURPY_OK;
+}
+
+turpy_status turpy_receiver_setup(int32_t n) {
+  if (turpy_status st = check_receiver_shape(n, 1)) return st;
+  int dev = 0;
+  TURPY_HIP(hipGetDevice(&dev), "receiver_setup");
+  std::lock_guard<std::mutex> lock(g_tw_mutex);
+  if (g_tw_cache.count({dev, n})) return TURPY_OK;
+  std::vector<float2> tw(n);
+  for (int i = 0; i < n; ++i) tw[i] = phasor(-static_cast<double>(i) / n);
+  float2* d = nullptr;
+  TURPY_HIP(hipMalloc(&d, n * sizeof(float2)), "receiver_setup: twiddle table");
+  const hipError_t e = hipMemcpy(d, tw.data(), n * sizeof(float2), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(d);
+    return hip_fail(e, "receiver_setup: twiddle table");
+  }
+  g_tw_cache[{dev, n}] = d;
   return TURPY_OK;
 }
 

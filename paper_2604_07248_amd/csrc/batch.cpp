@@ -96,6 +96,8 @@ turpy_status turpy_batch_create(turpy_batch** out, const turpy_path* paths, cons
   if (!out || !paths || !field_offsets || num_paths < 1)
     return turpy::report(TURPY_E_INVALID, "batch_create: NULL argument or num_paths < 1");
   *out = nullptr;
+  if (flags & TURPY_SCREEN_CHECKPOINTS)
+    return turpy::report(TURPY_E_INVALID, "batch_create: TURPY_SCREEN_CHECKPOINTS is not available for batches");
   turpy_batch* b = new turpy_batch;
   if (hipGetDevice(&b->device) != hipSuccess) {
     delete b;
@@ -248,8 +250,8 @@ turpy_status turpy_batch_propagate_backward(turpy_batch* b, uint64_t seed, int64
     const size_t co = static_cast<size_t>(b->ck_offsets[i]);
     return turpy_propagate_backward(b->plans[i], seed + kSeedStep * static_cast<uint64_t>(i), t, gout + off,
                                     ck ? ck + co * 8 : nullptr, TURPY_SCREENS_SYNTH, nullptr,
-                                    gin ? gin + off : nullptr, grad_screens ? grad_screens + co : nullptr, lws,
-                                    lbytes, st);
+                                    gin ? gin + off : nullptr, int64_t(b->paths[i].n) * b->paths[i].n,
+                                    grad_screens ? grad_screens + co : nullptr, lws, lbytes, st);
   });
 }
 

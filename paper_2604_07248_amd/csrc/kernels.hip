@@ -679,7 +679,45 @@ void synth_col_kernel(SynthArgs a) {
   __shared__ float2 tw_lds[N];
   const float2* tw = stage_twiddles<N>(tw_lds, a.tw);
   float2 x[kE];
-  if (a.spectra) {
+  if (a.evolve) {
+    // Eq. 4 (translation by exp(-2 pi i (kx sx + ky sy)/N), the phase reduced
+    // in FP64) then Eq. 5 (alpha blend with fresh innovations), bin pairs
+    // (k0, k1), (k0 + N/2, k1) sharing one Philox block; DC kept at zero
+    constexpr float inv2pi = 0.15915494309189535f;
+    float2* st = a.state + (static_cast<size_t>(j) * a.M + a.screen) * N * N + k1 + static_cast<size_t>(t) * N;
+    const int kx = signed_bin(k1, N);
+    const double inv_n = 1.0 / N;
+    float2 old[kE];
+#pragma unroll
+    for (int m = 0; m < kE; ++m) old[m] = st[static_cast<size_t>(T * m) * N];
+#pragma unroll
+    for (int m = 0; m < kE / 2; ++m) {
+      const int k0 = t + T * m;  // < N/2
+      const uint32_t e = static_cast<uint32_t>(k0) * N + k1;
+      const uint4 v = philox4x32_10(noise_counter(e, time_step(a), static_cast<uint32_t>(j), a.ar_tag, a.screen),
+                                    a.key0, a.key1);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int kk0 = k0 + h * (N / 2);
+        const int ky = signed_bin(kk0, N);
+        const float w = psd_amp(ky * ky + kx * kx, a.amp_rad, a.df2, a.inner, a.f02, a.q);
+        const float2 nc = h == 0 ? box_muller(v.x, v.y) : box_muller(v.z, v.w);
+        double rev = -(static_cast<double>(kx) * a.sx + static_cast<double>(ky) * a.sy) * inv_n;
+        rev -= rint(rev);
+        float sn, cs;
+        sincos_rev(static_cast<float>(rev), &sn, &cs);
+        float2 out = c_add(c_scale(c_mul(old[m + h * (kE / 2)], make_float2(cs, sn)), a.alpha_f),
+                           c_scale(nc, a.blend * w));
+        if (kk0 == 0 && k1 == 0) out = make_float2(0.0f, 0.0f);
+        x[m + h * (kE / 2)] = out;
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < kE; ++m) {
+      st[static_cast<size_t>(T * m) * N] = x[m];
+      x[m] = c_scale(x[m], inv2pi);
+    }
+  } else if (a.spectra) {
     constexpr float inv2pi = 0.15915494309189535f;
     const float2* src = a.spectra + (static_cast<size_t>(j) * a.M + a.screen) * N * N + k1;
 #pragma unroll
@@ -878,38 +916,78 @@ __device__ double block_max(double v, double* red) {
   return r;
 }
 
+// Mean intensity of pixel p from the compensated sums, rounded to FP32: the
+// quantity the power-cutoff region of Sec. 4.1 is decided on.
+__device__ __forceinline__ float mean_intensity(const FinalizeArgs& a, int64_t p, int64_t np) {
+  return static_cast<float>((static_cast<double>(a.moments[p]) - a.moments[np + p]) / a.count);
+}
+
 __global__ __launch_bounds__(1024) void finalize_kernel(FinalizeArgs a) {
   constexpr int NT = 1024;
   __shared__ double red[NT];
   const int n = a.n;
   const int64_t np = static_cast<int64_t>(n) * n;
-  double si_sum = 0, si_cnt = 0, m1_sum = 0, r2m1 = 0, m1_max = 0;
+  double m1_sum = 0, r2m1 = 0, m1_max = 0, m1f_sum = 0;
   for (int64_t p = threadIdx.x; p < np; p += NT) {
     const int i0 = static_cast<int>(p / n), i1 = static_cast<int>(p % n);
     const double m1 = (static_cast<double>(a.moments[p]) - a.moments[np + p]) / a.count;
     const double m2 = (static_cast<double>(a.moments[2 * np + p]) - a.moments[3 * np + p]) / a.count;
-    const double si = m2 / (m1 * m1) - 1.0;
-    if (a.si_map) a.si_map[p] = static_cast<float>(si);
-    const int d0 = abs(i0 - n / 2), d1 = abs(i1 - n / 2);
-    if (d0 < n / 4 && d1 < n / 4) {
-      si_sum += si;
-      si_cnt += 1.0;
-    }
+    if (a.si_map) a.si_map[p] = static_cast<float>(m2 / (m1 * m1) - 1.0);
     const double x = (i1 - n / 2) * a.dx, y = (i0 - n / 2) * a.dx;
     m1_sum += m1;
     r2m1 += (x * x + y * y) * m1;
     m1_max = fmax(m1_max, m1);
+    m1f_sum += mean_intensity(a, p, np);
   }
-  si_sum = block_sum<NT>(si_sum, red);
-  si_cnt = block_sum<NT>(si_cnt, red);
   m1_sum = block_sum<NT>(m1_sum, red);
   r2m1 = block_sum<NT>(r2m1, red);
   m1_max = block_max<NT>(m1_max, red);
-  const double thr = exp(-2.0) * m1_max;
+  m1f_sum = block_sum<NT>(m1f_sum, red);
+  // Power-cutoff region (Sec. 4.1): the largest threshold t whose pixels
+  // m1 >= t hold power_fraction of the total, by bisection over the ordered
+  // bit patterns of non-negative FP32 values (exact after 32 halvings).
+  uint32_t thr_bits = 0;
+  if (a.power_fraction > 0) {
+    const double target = a.power_fraction * m1f_sum;
+    uint32_t lo = 0, hi = 0x7F800000u;  // S(lo) >= target; hi: +inf, above every finite m1
+    while (hi - lo > 1u) {
+      const uint32_t mid = lo + (hi - lo) / 2u;
+      const float t = __uint_as_float(mid);
+      double s = 0;
+      for (int64_t p = threadIdx.x; p < np; p += NT) {
+        const float m = mean_intensity(a, p, np);
+        if (m >= t) s += m;
+      }
+      s = block_sum<NT>(s, red);
+      if (s >= target) lo = mid; else hi = mid;
+    }
+    thr_bits = lo;
+  }
+  const float thr = __uint_as_float(thr_bits);
+  double si_sum = 0, w_sum = 0;
+  for (int64_t p = threadIdx.x; p < np; p += NT) {
+    bool in;
+    if (a.power_fraction > 0) {
+      in = mean_intensity(a, p, np) >= thr;
+    } else {
+      const int i0 = static_cast<int>(p / n), i1 = static_cast<int>(p % n);
+      in = abs(i0 - n / 2) < n / 4 && abs(i1 - n / 2) < n / 4;
+    }
+    if (in) {
+      const double m1 = (static_cast<double>(a.moments[p]) - a.moments[np + p]) / a.count;
+      const double m2 = (static_cast<double>(a.moments[2 * np + p]) - a.moments[3 * np + p]) / a.count;
+      const double w = a.weight ? static_cast<double>(a.weight[p]) : 1.0;
+      si_sum += w * (m2 / (m1 * m1) - 1.0);
+      w_sum += w;
+    }
+  }
+  si_sum = block_sum<NT>(si_sum, red);
+  w_sum = block_sum<NT>(w_sum, red);
+  const double cut = exp(-2.0) * m1_max;
   double s0 = 0, sx = 0, sxx = 0, sy = 0, sxy = 0;
   for (int64_t p = threadIdx.x; p < np; p += NT) {
     const double m1 = (static_cast<double>(a.moments[p]) - a.moments[np + p]) / a.count;
-    if (m1 >= thr && m1 > 0) {
+    if (m1 >= cut && m1 > 0) {
       const int i0 = static_cast<int>(p / n), i1 = static_cast<int>(p % n);
       const double x = (i1 - n / 2) * a.dx, y = (i0 - n / 2) * a.dx;
       const double r2 = x * x + y * y, l = log(m1);
@@ -928,11 +1006,63 @@ __global__ __launch_bounds__(1024) void finalize_kernel(FinalizeArgs a) {
   if (threadIdx.x == 0) {
     const double den = s0 * sxx - sx * sx;
     const double slope = den != 0 ? (s0 * sxy - sx * sy) / den : 0.0;
-    a.summary[0] = si_cnt > 0 ? si_sum / si_cnt : 0.0;
+    a.summary[0] = w_sum != 0 ? si_sum / w_sum : 0.0;
     a.summary[1] = m1_sum > 0 ? sqrt(2.0 * r2m1 / m1_sum) : 0.0;
     a.summary[2] = slope < 0 ? sqrt(-2.0 / slope) : __builtin_huge_val();
     a.summary[3] = a.count;
+    a.summary[4] = si_sum;
+    a.summary[5] = w_sum;
+    a.summary[6] = a.power_fraction > 0 ? static_cast<double>(thr) : 0.0;
+    a.summary[7] = 0.0;
   }
+}
+
+// ---------------------------------------------------------------------------
+// The complex normals of a spectrum on their own (Eq. S16's N_c, with the
+// counter layout of the synthesis): one Philox block per bin pair (k0, k1),
+// (k0 + N/2, k1) of pair j.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void noise_kernel(NoiseArgs a) {
+  const int n = a.n;
+  const int64_t half = static_cast<int64_t>(n / 2) * n;
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= a.pairs * half) return;
+  const int64_t j = idx / half;
+  const uint32_t e = static_cast<uint32_t>(idx - j * half);  // k0 * N + k1, k0 < N/2
+  const uint4 v = philox4x32_10(noise_counter(e, a.t, static_cast<uint32_t>(j), a.tag, a.screen), a.key0, a.key1);
+  float2* out = a.out + j * static_cast<int64_t>(n) * n;
+  out[e] = box_muller(v.x, v.y);
+  out[e + half] = box_muller(v.z, v.w);
+}
+
+// ---------------------------------------------------------------------------
+// Sum of R planes into one (the gradient of a source shared by every
+// realization): each thread owns one element and adds the planes in order with
+// Kahan compensation, sixteen non-temporal loads in flight.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void sum_planes_kernel(const float2* in, int64_t R, int64_t count, float2* out) {
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= count) return;
+  float2 s = make_float2(0.0f, 0.0f), c = make_float2(0.0f, 0.0f);
+  auto add = [&](float2 v) {
+    const float yx = v.x - c.x, yy = v.y - c.y;
+    const float tx = s.x + yx, ty = s.y + yy;
+    c.x = (tx - s.x) - yx;
+    c.y = (ty - s.y) - yy;
+    s.x = tx;
+    s.y = ty;
+  };
+  constexpr int U = 16;
+  int64_t r = 0;
+  for (; r + U <= R; r += U) {
+    float2 v[U];
+#pragma unroll
+    for (int q = 0; q < U; ++q) v[q] = ld_s<true>(in + (r + q) * count + p);
+#pragma unroll
+    for (int q = 0; q < U; ++q) add(v[q]);
+  }
+  for (; r < R; ++r) add(ld_s<true>(in + r * count + p));
+  out[p] = s;
 }
 
 __global__ __launch_bounds__(256) void copy_kernel(const float2* in, int64_t in_stride, float2* out,
@@ -1084,6 +1214,18 @@ hipError_t launch_stats(const StatsArgs& a, hipStream_t s) {
 
 hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(1024), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_noise(const NoiseArgs& a, hipStream_t s) {
+  const int64_t total = a.pairs * static_cast<int64_t>(a.n / 2) * a.n;
+  hipLaunchKernelGGL(noise_kernel, dim3(static_cast<uint32_t>((total + 255) / 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_planes(const float2* in, int64_t R, int64_t count, float2* out, hipStream_t s) {
+  hipLaunchKernelGGL(sum_planes_kernel, dim3(static_cast<uint32_t>((count + 255) / 256)), dim3(256), 0, s, in, R,
+                     count, out);
   return hipGetLastError();
 }
 

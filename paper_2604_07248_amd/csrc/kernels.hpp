@@ -78,6 +78,15 @@ struct SynthArgs {
   const float2* spectra;    // [P][M][N][N] radians, or NULL for synthesis
   int M;
   int width;                // columns per block (4, 8, 16), 0: the built-in choice for N
+  // AR step fused into the read of the stored spectra (Eq. 4 then Eq. 5 with
+  // innovations drawn at the time step): the evolved spectrum is written back
+  // to `state` (the same array as `spectra`) and transformed
+  int evolve;
+  float2* state;
+  uint32_t ar_tag;          // innovation tag
+  float alpha_f, blend;     // alpha and sqrt(1 - alpha^2), rounded from FP64
+  double sx, sy;            // frozen-flow shift in pixels
+  float amp_rad;            // sqrt(0.023) r0^(-5/6) df of this screen: radians
 };
 
 struct ShArgs {
@@ -124,7 +133,16 @@ struct FinalizeArgs {
   double dx;
   double count;
   float* si_map;
-  double* summary;
+  double* summary;          // [8], see turpy_stats
+  const float* weight;      // [n][n] per-pixel weights of the SI region sums, or NULL (all 1)
+  double power_fraction;    // > 0: SI region = power-cutoff region; 0: the central region
+};
+
+struct NoiseArgs {
+  float2* out;              // [pairs][n][n]
+  int64_t pairs;
+  int n;
+  uint32_t key0, key1, t, tag, screen;
 };
 
 struct RecvArgs {
@@ -157,6 +175,9 @@ hipError_t launch_recv_col(const RecvArgs& a, hipStream_t s);        // FFT_y, x
 hipError_t launch_recv_col_grad(const RecvArgs& a, hipStream_t s);   // th2 gradient partials + gradient path
 hipError_t launch_recv_row_grad(const RecvArgs& a, hipStream_t s);   // th1 gradient partials + grad u
 hipError_t launch_recv_reduce(const RecvArgs& a, float* grad, int centre_shift, hipStream_t s);
+hipError_t launch_noise(const NoiseArgs& a, hipStream_t s);
+// out[p] = sum over r < R of in[r * count + p] (in order, compensated)
+hipError_t launch_sum_planes(const float2* in, int64_t R, int64_t count, float2* out, hipStream_t s);
 hipError_t launch_copy(const float2* in, int64_t in_stride, float2* out, int64_t count, int64_t R,
                        hipStream_t s);
 

@@ -83,7 +83,23 @@ def test_aliasing_limit(L):
 
 
 def test_stats_argument_errors(L):
-    st = L.turpy_stats(64, 0.01, 1, None, None, 0, 0, None, None, None)
+    st = L.turpy_stats(64, 0.01, 1, None, None, 0, 0, None, 0.0, None, None, None)
     assert st == B.E_INVALID and "moments" in B.last_error()
-    st = L.turpy_stats(0, 0.01, 0, None, None, 0, 0, None, None, None)
+    st = L.turpy_stats(0, 0.01, 0, None, None, 0, 0, None, 0.0, None, None, None)
     assert st == B.E_INVALID
+    # a non-NULL moments pointer is only checked for NULL before validation ends
+    fake = ctypes.c_void_p(256)
+    st = L.turpy_stats(64, 0.01, 0, None, fake, 1, 1, None, 1.5, None, fake, None)
+    assert st == B.E_INVALID and "power_fraction" in B.last_error()
+
+
+def test_receiver_needs_setup(L):
+    """Plan-less receiver calls allocate nothing: their tables come from
+    turpy_receiver_setup, and a call for an n never set up is refused before
+    anything is enqueued."""
+    fake = ctypes.c_void_p(256)
+    other = ctypes.c_void_p(512)
+    st = L.turpy_receiver(32, 0.01, 0.3, 1, fake, fake, fake, other, None, 0, None)
+    assert st in (B.E_INVALID, B.E_HIP)
+    if st == B.E_INVALID:
+        assert "turpy_receiver_setup" in B.last_error()

@@ -1,0 +1,94 @@
+"""The fused autoregressive step (turpy_evolve_propagate, Sec. 2.3 then Sec.
+2.1 Eq. 1) against the same step as two calls (turpy_evolve then
+turpy_propagate from the stored spectra) and against the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import evolve as oev
+from oracle import propagate as opr
+from paper_2604_07248_amd import binding as B
+from paper_2604_07248_amd import workloads
+
+from gpu_helpers import TOL, rel_l2, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def api(gpu_lib):
+    from paper_2604_07248_amd import api as _api
+    return _api
+
+
+def c64(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.complex64)).cuda()
+
+
+def _path(n, r, m, sh):
+    lam, dx = 1e-6, 2e-3 if n >= 128 else 4e-3
+    limit = n * dx * dx / lam
+    return workloads.uniform_path(n, n * dx, lam, min(0.8 * limit * m, 2000.0), m, 1e-15, 0.005, 20.0, sh,
+                                  realizations=r)
+
+
+@pytest.mark.parametrize("n,r,m,sh,shared", [(256, 4, 3, 0, True), (256, 3, 2, 3, False), (1024, 6, 2, 0, True),
+                                             (64, 5, 3, 0, False), (2048, 2, 2, 0, True)])
+def test_fused_ar_step_matches_two_calls_and_oracle(api, n, r, m, sh, shared):
+    path = _path(n, r, m, sh)
+    say(f"[ar fused] n={n} R={r} M={m} sh={sh} shared={shared}")
+    plan = api.Plan(path)
+    u0 = workloads.gaussian_source(n, path.dx, 0.1 * n * path.dx)
+    if not shared:
+        u0 = np.stack([u0 * np.exp(0.1j * k) for k in range(r)])
+    u0 = c64(u0)
+    spec_a = plan.init_spectra(seed=6)
+    spec_b = plan.init_spectra(seed=6)
+    ref_c = oev.initial_spectra(path, 6)
+    ref_d = oev.initial_sh(path, 6) if sh else None
+    steps = ((1, 0.97, 0.5, 0.0), (2, 0.9, 0.37, -0.25))
+    for t, alpha, sx, sy in steps:
+        plan.evolve(spec_a, 6, t, alpha, sx, sy)
+        out_a = plan.propagate(u0, spectra=spec_a).cpu().numpy()
+        out_b = plan.evolve_propagate(spec_b, 6, t, alpha, sx, sy, u_in=u0).cpu().numpy()
+        ref_c = oev.evolve(ref_c, path, 6, t, alpha, sx, sy)
+        if sh:
+            ref_d = oev.evolve_sh(ref_d, path, 6, t, alpha, sx, sy)
+        e_ab = rel_l2(out_b, out_a)
+        e_state = rel_l2(spec_b.cpu().numpy(), spec_a.cpu().numpy())
+        say(f"[ar fused] t={t}: fused vs two calls field {e_ab:.2e}, state {e_state:.2e}")
+        assert e_ab < 2e-6 and e_state < 2e-6
+    phi = oev.screens_from_state(ref_c, ref_d, path, r) if sh else oev.screens_from_spectra(ref_c, r)
+    u_ref = u0.cpu().numpy().astype(np.complex128)
+    ref_out, _ = opr.propagate(u_ref, path, phi)
+    e_ora = rel_l2(out_b, ref_out)
+    e_spec = rel_l2(spec_b.cpu().numpy(), ref_c)
+    say(f"[ar fused] vs oracle: field {e_ora:.2e}, spectra {e_spec:.2e}")
+    assert e_ora < TOL and e_spec < TOL
+
+
+def test_fused_ar_step_with_screen_checkpoints_and_adjoint(api):
+    """The fused step writes checkpoints (with the screens' column halves) that
+    the adjoint reads with the evolved state."""
+    path = _path(256, 4, 3, 0)
+    plan = api.Plan(path, flags=B.SCREEN_CHECKPOINTS)
+    u0 = c64(workloads.gaussian_source(256, path.dx, 0.1 * 256 * path.dx))
+    spec = plan.init_spectra(seed=9)
+    out, ck = plan.evolve_propagate(spec, 9, 1, 0.95, 0.5, 0.1, u_in=u0, checkpoints=True)
+    g = torch.ones_like(out)
+    g_in, g_phi = plan.propagate_backward(g, ck, spectra=spec, shared_source=True)
+    ref_c = oev.evolve(oev.initial_spectra(path, 9), path, 9, 1, 0.95, 0.5, 0.1)
+    phi = oev.screens_from_spectra(ref_c, 4)
+    ref_out, ref_ck = opr.propagate(u0.cpu().numpy().astype(np.complex128), path, phi)
+    ref_in, ref_phi = opr.propagate_adjoint(np.ones_like(ref_out), path, phi, ref_ck)
+    e = [rel_l2(out.cpu().numpy(), ref_out), rel_l2(g_in.cpu().numpy(), ref_in.sum(axis=0)),
+         rel_l2(g_phi.cpu().numpy(), ref_phi)]
+    say(f"[ar fused] checkpointed adjoint: field {e[0]:.2e} grad_in {e[1]:.2e} grad_phi {e[2]:.2e}")
+    assert max(e) < TOL
+
+
+def test_fused_ar_step_rejects_t0(api):
+    plan = api.Plan(_path(64, 2, 1, 0))
+    spec = plan.init_spectra(seed=1)
+    with pytest.raises(ValueError):
+        plan.evolve_propagate(spec, 1, 0, 0.9, u_in=c64(np.ones((64, 64))))
