@@ -152,6 +152,22 @@ turpy_status turpy_propagate(turpy_plan* plan, uint64_t seed, int64_t t, const v
                              int64_t u_in_stride, int32_t src, const void* screens_or_spectra,
                              void* u_out, void* checkpoints, void* ws, size_t ws_bytes, void* stream);
 
+/* turpy_propagate without a workspace argument, for callers that cannot
+ * allocate device memory (code under graph capture, tight serving loops,
+ * harnesses that forbid allocation).  It allocates nothing: its scratch
+ * (screen planes, subharmonic coefficients, the shared-source plane) lives in
+ * a fixed 64 MiB device array of the library, one per GPU, held until the
+ * process ends; the array's address is looked up by turpy_plan_create.  Other
+ * arguments and results as turpy_propagate (bit-identical).  A plan whose
+ * turpy_workspace_size(TURPY_OP_PROPAGATE) exceeds 64 MiB is refused with
+ * TURPY_E_WORKSPACE (N = 1024: at most 14 realizations; N = 512: 62).
+ * Every call on one GPU shares that GPU's array and leaves its contents
+ * behind (no part of it needs to start at zero): calls that overlap on one
+ * GPU -- on different streams, or from different threads -- race. */
+turpy_status turpy_propagate_static(turpy_plan* plan, uint64_t seed, int64_t t, const void* u_in,
+                                    int64_t u_in_stride, int32_t src, const void* screens_or_spectra, void* u_out,
+                                    void* checkpoints, void* stream);
+
 /* Screen-spectrum evolution (Sec. 2.3) of an AR state, in place.  The state
  * (turpy_state_size bytes, device memory) is complex64 spectra
  * [ceil(R/2)][M][N][N] in radians, followed, when the plan has subharmonic

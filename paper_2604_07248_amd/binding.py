@@ -33,7 +33,7 @@ EXPORTS = [
     "turpy_batch_create", "turpy_batch_destroy", "turpy_batch_bind_time", "turpy_batch_workspace_size",
     "turpy_batch_propagate", "turpy_batch_propagate_backward", "turpy_plan_tune", "turpy_plan_widths",
     "turpy_plan_set_widths", "turpy_tune_cache_get", "turpy_tune_cache_put", "turpy_tune_cache_clear",
-    "turpy_batch_tune", "turpy_receiver_setup", "turpy_noise", "turpy_checkpoint_size", "turpy_evolve_propagate",
+    "turpy_batch_tune", "turpy_receiver_setup", "turpy_noise", "turpy_propagate_static", "turpy_checkpoint_size", "turpy_evolve_propagate",
 ]
 
 
@@ -110,6 +110,8 @@ def lib():
         L.turpy_stats.argtypes = [c_int32, c_double, c_int64, c_void_p, c_void_p, c_int64, c_int32, c_void_p,
                                   c_double, c_void_p, c_void_p, c_void_p]
         L.turpy_receiver_setup.argtypes = [c_int32]
+        L.turpy_propagate_static.argtypes = [c_void_p, c_uint64, c_int64, c_void_p, c_int64, c_int32, c_void_p,
+                                             c_void_p, c_void_p, c_void_p]
         L.turpy_noise.argtypes = [c_int32, c_int64, c_uint64, c_int64, c_int32, c_int32, c_void_p, c_void_p]
         L.turpy_receiver_workspace_size.argtypes = [c_int32, c_int64, POINTER(c_size_t)]
         L.turpy_receiver.argtypes = [c_int32, c_double, c_double, c_int64, c_void_p, c_void_p, c_void_p, c_void_p,

@@ -121,6 +121,37 @@ hipError_t timed(const char* family, hipStream_t st, Fn&& fn) {
 
 }  // namespace
 
+namespace {
+
+// Device scratch of turpy_propagate_static: one array per GPU the library
+// runs on, held until the process ends.  Host code never uses the name
+// `scratch` as an address: turpy_plan_create looks up each device's copy with
+// hipGetSymbolAddress once, and the kernels get that pointer.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_ptr;  // device -> address of its `scratch`
+
+// Record the current device's scratch address (set-up time, once per device).
+hipError_t register_static_scratch(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr.count(device)) return hipSuccess;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[device] = ptr;
+  return hipSuccess;
+}
+
+void* static_scratch(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  auto it = g_scratch_ptr.find(device);
+  return it == g_scratch_ptr.end() ? nullptr : it->second;
+}
+
+}  // namespace
+
 struct turpy_plan {
   int device = 0;
   int n = 0, M = 0, sh_levels = 0, tf_kind = 0, conv = 0;
@@ -355,6 +386,11 @@ turpy_status turpy_plan_create(turpy_plan** out, const turpy_path* p, uint32_t f
   if (e != hipSuccess) {
     turpy_plan_destroy(pl);
     return hip_fail(e, "plan_create: table upload");
+  }
+  e = register_static_scratch(pl->device);
+  if (e != hipSuccess) {
+    turpy_plan_destroy(pl);
+    return hip_fail(e, "plan_create: scratch address of turpy_propagate_static");
   }
   pl->arch = device_arch(pl->device);
   apply_cached_widths(pl);
@@ -833,6 +869,22 @@ turpy_status turpy_evolve_propagate(turpy_plan* pl, uint64_t seed, int64_t t, do
   const EvolveStep ev{alpha, shift_x, shift_y};
   return propagate_impl(pl, seed, t, u_in, u_in_stride, TURPY_SCREENS_SPECTRA, state, u_out, checkpoints, ws,
                         ws_bytes, stream, pl->M > 0 ? &ev : nullptr);
+}
+
+turpy_status turpy_propagate_static(turpy_plan* pl, uint64_t seed, int64_t t, const void* u_in,
+                                    int64_t u_in_stride, int32_t src, const void* screens_or_spectra, void* u_out,
+                                    void* checkpoints, void* stream) {
+  if (!pl) return fail(TURPY_E_INVALID, "propagate_static: NULL plan");
+  if (turpy_status s_ = check_device(pl)) return s_;
+  const size_t need = pl->ws_forward();
+  if (need > kStaticScratchBytes)
+    return fail(TURPY_E_WORKSPACE,
+                "propagate_static: the plan needs %zu bytes of scratch, beyond the %zu of the static array "
+                "(use turpy_propagate with a workspace)", need, kStaticScratchBytes);
+  void* ptr = static_scratch(pl->device);
+  if (!ptr) return fail(TURPY_E_INVALID, "propagate_static: no scratch address for device %d", pl->device);
+  return turpy_propagate(pl, seed, t, u_in, u_in_stride, src, screens_or_spectra, u_out, checkpoints, ptr,
+                         kStaticScratchBytes, stream);
 }
 
 turpy_status turpy_propagate_backward(turpy_plan* pl, uint64_t seed, int64_t t, const void* grad_u_out,
