@@ -23,9 +23,10 @@ The FP64 oracle is timed first, on the host cores (one and all), before the
 GPU is touched (`cpu_baseline`); the forward step's error against it is
 `oracle_rel_l2`.
 
-Before any timed step each plan's column-pass and synthesis strip widths are
-measured by turpy_plan_tune (or taken from --tune-cache); `config.strip_widths`
-and `tuning` report them.  Prints one JSON line.  Inputs are seeded and
+Before any timed step each plan's launch configuration (strip widths and radix
+plans of the column pass and the synthesis, occupancy hints of the screen row
+passes) is measured by turpy_plan_tune (or taken from --tune-cache);
+`config.launch_config` and `tuning` report them.  Prints one JSON line.  Inputs are seeded and
 synthetic and already resident in HBM when the timed region starts.
 """
 
@@ -54,7 +55,7 @@ def parse():
                     default="all",
                     help="run one leg (profiling runs)")
     ap.add_argument("--tune-cache", default=None,
-                    help="JSON strip-width cache: read when the file exists (its widths are then used without "
+                    help="JSON tuning cache: read when the file exists (its choices are then used without "
                          "measuring), written at the end")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-pairs", type=int, default=16, help="realization pairs in the oracle sample (about 20 s of CPU work)")
@@ -502,8 +503,7 @@ def main():
     w = workloads.headline(args.realizations)
     path = w.path
     plan = api.Plan(path)
-    # strip widths of the column pass and the synthesis: measured (or cached)
-    # before any timed step
+    # launch configuration: measured (or cached) before any timed step
     t_tune = time.perf_counter()
     widths = plan.tune()
     t_tune = time.perf_counter() - t_tune
@@ -517,7 +517,7 @@ def main():
               "config": {"workload": w.name + " (N=1024 over 1 m, 1064 nm, 1.5 km, Cn2=2e-14, l0=5 mm, L0=20 m, "
                                               "8 fresh screens per step, W0=5 cm)",
                          "n": path.n, "realizations": path.realizations, "screens": path.num_screens,
-                         "screen_steps_per_step": ss_per_step, "strip_widths": widths}}
+                         "screen_steps_per_step": ss_per_step, "launch_config": widths}}
 
     def fwd(i):
         plan.propagate(u0, seed=w.seed, t=i, out=u_out)

@@ -415,49 +415,73 @@ turpy_status turpy_place_screens(const turpy_cn2_profile* profile, double length
                                  int32_t* num_screens, double* dz, double* cn2dz, double* rytov);
 
 /* ---------------------------------------------------------------------------
- * Launch-shape tuning.  The column pass (FFT along y, transfer function,
- * inverse FFT; Sec. 2.1) and the column half of the screen synthesis (Eq.
- * S16) each run one block per strip of K adjacent columns of a plane, K in
- * {4, 8, 16} (K N / 16 threads per block, at most 1024, and K N complex words
- * of LDS; at N = 2048 K = 16 does not fit).  K sets the block size, the
- * occupancy and the width of each memory segment the pass touches; it does
- * not change the arithmetic: every K gives bit-identical results.  A plan
- * starts from a built-in choice per N (measured on MI355X), or from the
+ * Launch-configuration tuning.  Three choices are searched, none of which
+ * changes what is computed beyond FP32 rounding order:
+ *  - the column pass (FFT along y, transfer function, inverse FFT; Sec. 2.1)
+ *    and the column half of the screen synthesis (Eq. S16) run one block per
+ *    strip of K adjacent columns of a plane, K in {4, 8, 16} (K N / 16
+ *    threads per block, at most 1024, and K N complex words of LDS; at
+ *    N = 2048 K = 16 does not fit): K sets the block size, the occupancy and
+ *    the width of each memory segment; results are bit-identical for every K;
+ *  - the radix plan of their transforms: every transform starts with a
+ *    radix-16 pass; the second pass has radix R2 (default min(16, N/16)) and
+ *    the third N / (16 R2); R2 in {8, 4} is also built for N = 512 and 1024
+ *    and R2 = 8 for N = 2048 (other plans round differently, within the
+ *    oracle tolerance);
+ *  - the occupancy hint of the screen row passes, forward and adjoint: the
+ *    minimum waves per SIMD (2, 3 or 4) the register allocation must allow;
+ *    3 is the default, 2 and 4 are built for N >= 256 (bit-identical results).
+ * A plan starts from the built-in choices (measured on MI355X), or from the
  * process-wide cache when it holds an entry for the plan's key:
  *   (device architecture, kernel, N, batch class = bit length of the number
  *    of planes one launch covers: R for the column pass, ceil(R/2) for the
- *    synthesis).
+ *    synthesis and the row passes).
  * ------------------------------------------------------------------------- */
 typedef enum {
-  TURPY_TUNE_COL_FRESNEL = 0,   /* column pass, Fresnel transfer function            */
+  TURPY_TUNE_COL_FRESNEL = 0,   /* column pass, Fresnel transfer function               */
   TURPY_TUNE_COL_ANGULAR = 1,   /* column pass, angular spectrum, every bin propagating */
-  TURPY_TUNE_COL_AS_TABLE = 2,  /* column pass, angular spectrum with evanescent bins */
-  TURPY_TUNE_SYNTH = 3          /* column half of the screen synthesis               */
+  TURPY_TUNE_COL_AS_TABLE = 2,  /* column pass, angular spectrum with evanescent bins   */
+  TURPY_TUNE_SYNTH = 3,         /* column half of the screen synthesis                  */
+  TURPY_TUNE_ROW_FWD = 4,       /* forward screen row pass (no checkpoints)             */
+  TURPY_TUNE_ROW_BWD = 5        /* adjoint screen row pass                              */
 } turpy_tune_kernel;
 
 #define TURPY_TUNE_FORCE 1u     /* measure even when the cache holds the key */
 
 typedef struct turpy_tune_entry {
-  char arch[32];                /* device architecture, e.g. "gfx950" (NUL-terminated)     */
-  int32_t kernel;               /* turpy_tune_kernel                                        */
-  int32_t n;                    /* grid size                                                */
-  int32_t batch_class;          /* bit length of the planes per launch                      */
-  int32_t width;                /* chosen columns per block: 4, 8 or 16                     */
-  float us[3];                  /* measured microseconds per launch at K = 4, 8, 16 (0: K
-                                   not built for N); kept as given by turpy_tune_cache_put  */
+  char arch[32];                /* device architecture, e.g. "gfx950" (NUL-terminated)             */
+  int32_t kernel;               /* turpy_tune_kernel                                                */
+  int32_t n;                    /* grid size                                                        */
+  int32_t batch_class;          /* bit length of the planes per launch                              */
+  int32_t width;                /* columns per block (4, 8, 16); 0 for the row kernels              */
+  int32_t radix;                /* second-pass radix (0: default plan); 0 for the row kernels       */
+  int32_t waves;                /* occupancy hint of the row kernels (2, 3, 4); 0 for the others    */
+  int32_t configs;              /* configurations measured (0 when put by hand)                     */
+  float us;                     /* microseconds per launch of the chosen configuration              */
+  float us_default;             /* of the built-in configuration (0: not measured)                  */
 } turpy_tune_entry;
 
-/* Time every strip width of the plan's column pass (its transfer-function
- * kind, distance 0, all R planes in place) and, when the plan has screens, of
- * its synthesis (all ceil(R/2) scratch planes), with HIP events on `stream`,
- * and keep the fastest of each in the plan and in the cache.  A key already
- * in the cache is applied without measuring unless flags has
- * TURPY_TUNE_FORCE.  Each width: one launch, then 3 repetitions of a loop of
- * launches lasting about 2 ms; the minimum per-launch time counts.
- * ws: turpy_workspace_size(TURPY_OP_TUNE) bytes of device memory, zeroed and
- * overwritten here (no caller data is touched).  Synchronises `stream`: it
- * cannot be captured in a graph (TURPY_E_INVALID while the stream captures).
- * col_width / synth_width (may be NULL) receive the widths now in the plan. */
+/* The launch choices of a plan (0 in set_config: the built-in choice). */
+typedef struct turpy_launch_config {
+  int32_t col_width, col_radix;     /* column pass                               */
+  int32_t synth_width, synth_radix; /* column half of the synthesis              */
+  int32_t row_waves;                /* forward screen row passes                 */
+  int32_t row_waves_bwd;            /* adjoint screen row passes                 */
+} turpy_launch_config;
+
+/* Time every launch configuration of the plan's column pass (its
+ * transfer-function kind, distance 0, all R planes in place), and, when the
+ * plan has screens, of its synthesis (all ceil(R/2) scratch planes) and of
+ * its forward and adjoint row passes for screen 0 (workspace planes), with
+ * HIP events on `stream`, and keep the fastest of each in the plan and in the
+ * cache.  A key already in the cache is applied without measuring unless
+ * flags has TURPY_TUNE_FORCE.  Each configuration: one launch, then 3
+ * repetitions of a loop of launches lasting about 2 ms; the minimum
+ * per-launch time counts.  ws: turpy_workspace_size(TURPY_OP_TUNE) bytes of
+ * device memory, zeroed and overwritten here (no caller data is touched).
+ * Synchronises `stream`: it cannot be captured in a graph (TURPY_E_INVALID
+ * while the stream captures).  col_width / synth_width (may be NULL) receive
+ * the strip widths now in the plan (turpy_plan_config has every choice). */
 turpy_status turpy_plan_tune(turpy_plan* plan, uint32_t flags, void* ws, size_t ws_bytes, void* stream,
                              int32_t* col_width, int32_t* synth_width);
 /* The strip widths the plan's launches use now. */
@@ -466,13 +490,18 @@ turpy_status turpy_plan_widths(const turpy_plan* plan, int32_t* col_width, int32
  * value must be a width built for the plan's N (TURPY_E_INVALID otherwise,
  * and the plan is unchanged). */
 turpy_status turpy_plan_set_widths(turpy_plan* plan, int32_t col_width, int32_t synth_width);
+/* Every launch choice of the plan now (built-in choices filled in). */
+turpy_status turpy_plan_config(const turpy_plan* plan, turpy_launch_config* config);
+/* Set every launch choice (0 fields: built-in); TURPY_E_INVALID for a
+ * choice not built for the plan's N (the plan is then unchanged). */
+turpy_status turpy_plan_set_config(turpy_plan* plan, const turpy_launch_config* config);
 /* The cache (host memory, process-wide, guarded by a lock): get copies up to
  * `capacity` entries in key order and sets *count to the number held (so a
  * call with capacity 0 sizes the array); put inserts or replaces entries by
- * key (TURPY_E_INVALID for a width not built for the entry's n or an unknown
+ * key (TURPY_E_INVALID for a choice not built for the entry's n or an unknown
  * kernel; entries before the bad one are kept); clear empties it.  Plans
- * created afterwards start from the cached widths; existing plans keep theirs.
- * These three calls touch no device. */
+ * created afterwards start from the cached choices; existing plans keep
+ * theirs.  These three calls touch no device. */
 turpy_status turpy_tune_cache_get(turpy_tune_entry* entries, int32_t capacity, int32_t* count);
 turpy_status turpy_tune_cache_put(const turpy_tune_entry* entries, int32_t count);
 turpy_status turpy_tune_cache_clear(void);

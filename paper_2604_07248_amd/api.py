@@ -97,15 +97,26 @@ class Plan:
 
     # -- launch shapes -------------------------------------------------------
     def tune(self, force=False):
-        """Time the strip widths of the column pass and of the synthesis
-        (turpy_plan_tune; synchronises) and keep the fastest, or take them
-        from the tuning cache.  Returns {"col": K, "synth": K}."""
+        """Time the launch configurations of the column pass, the synthesis
+        and the screen row passes (turpy_plan_tune; synchronises) and keep the
+        fastest, or take them from the tuning cache.  Returns the plan's
+        launch configuration (config)."""
         size = B.workspace_size(self.handle, B.OP_TUNE)
         ws = torch.empty(max(size, 256), dtype=torch.uint8, device=self.device)
-        col, syn = B.plan_tune(self.handle, B.TUNE_FORCE if force else 0, _ptr(ws), size, _stream())
+        B.plan_tune(self.handle, B.TUNE_FORCE if force else 0, _ptr(ws), size, _stream())
         del ws
         _tune_cache_to_env()
-        return {"col": col, "synth": syn}
+        return self.config
+
+    @property
+    def config(self):
+        """Every launch choice: col_width, col_radix, synth_width, synth_radix,
+        row_waves, row_waves_bwd."""
+        return B.plan_config(self.handle)
+
+    def set_config(self, **choices):
+        """Set launch choices (missing or 0: the built-in choice)."""
+        B.plan_set_config(self.handle, choices)
 
     @property
     def widths(self):
@@ -370,6 +381,7 @@ def noise(n, pairs, seed, t=0, tag=1, screen=0, out=None, device=None):
 
 
 TUNE_CACHE_FORMAT = "turpy-tune-cache"
+TUNE_CACHE_VERSION = 2
 
 
 def tune_cache():
@@ -380,7 +392,8 @@ def tune_cache():
 def tune_cache_save(path):
     """Write the tuning cache as JSON."""
     with open(path, "w") as f:
-        json.dump({"format": TUNE_CACHE_FORMAT, "version": 1, "entries": B.tune_cache_get()}, f, indent=1)
+        json.dump({"format": TUNE_CACHE_FORMAT, "version": TUNE_CACHE_VERSION, "entries": B.tune_cache_get()}, f,
+                  indent=1)
 
 
 def tune_cache_load(path):
@@ -388,8 +401,8 @@ def tune_cache_load(path):
     the number of entries read.  Plans created afterwards use them."""
     with open(path) as f:
         doc = json.load(f)
-    if doc.get("format") != TUNE_CACHE_FORMAT or doc.get("version") != 1:
-        raise ValueError(f"{path}: not a version-1 {TUNE_CACHE_FORMAT} file")
+    if doc.get("format") != TUNE_CACHE_FORMAT or doc.get("version") != TUNE_CACHE_VERSION:
+        raise ValueError(f"{path}: not a version-{TUNE_CACHE_VERSION} {TUNE_CACHE_FORMAT} file")
     B.tune_cache_put(doc["entries"])
     return len(doc["entries"])
 

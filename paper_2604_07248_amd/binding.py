@@ -19,8 +19,8 @@ SCREENS_SYNTH, SCREENS_MATERIALIZED, SCREENS_SPECTRA = 0, 1, 2
 ALLOW_ALIASING = 1
 SCREEN_CHECKPOINTS = 2
 OP_SCREEN_GENERATE, OP_PROPAGATE, OP_PROPAGATE_BACKWARD, OP_EVOLVE, OP_PROPAGATE_BACKWARD_REVERSIBLE, OP_TUNE = range(6)
-TUNE_COL_FRESNEL, TUNE_COL_ANGULAR, TUNE_COL_AS_TABLE, TUNE_SYNTH = range(4)
-TUNE_KERNELS = ("col_fresnel", "col_angular", "col_as_table", "synth")
+TUNE_COL_FRESNEL, TUNE_COL_ANGULAR, TUNE_COL_AS_TABLE, TUNE_SYNTH, TUNE_ROW_FWD, TUNE_ROW_BWD = range(6)
+TUNE_KERNELS = ("col_fresnel", "col_angular", "col_as_table", "synth", "row_fwd", "row_bwd")
 TUNE_FORCE = 1
 
 # Every symbol the header declares (checked by the CPU tests).
@@ -33,7 +33,7 @@ EXPORTS = [
     "turpy_batch_create", "turpy_batch_destroy", "turpy_batch_bind_time", "turpy_batch_workspace_size",
     "turpy_batch_propagate", "turpy_batch_propagate_backward", "turpy_plan_tune", "turpy_plan_widths",
     "turpy_plan_set_widths", "turpy_tune_cache_get", "turpy_tune_cache_put", "turpy_tune_cache_clear",
-    "turpy_batch_tune", "turpy_receiver_setup", "turpy_noise", "turpy_propagate_static", "turpy_checkpoint_size", "turpy_evolve_propagate",
+    "turpy_batch_tune", "turpy_plan_config", "turpy_plan_set_config", "turpy_receiver_setup", "turpy_noise", "turpy_propagate_static", "turpy_checkpoint_size", "turpy_evolve_propagate",
 ]
 
 
@@ -55,8 +55,14 @@ class CPath(ctypes.Structure):
 class CTuneEntry(ctypes.Structure):
     _fields_ = [
         ("arch", ctypes.c_char * 32), ("kernel", c_int32), ("n", c_int32), ("batch_class", c_int32),
-        ("width", c_int32), ("us", c_float * 3),
+        ("width", c_int32), ("radix", c_int32), ("waves", c_int32), ("configs", c_int32), ("us", c_float),
+        ("us_default", c_float),
     ]
+
+
+class CLaunchConfig(ctypes.Structure):
+    _fields_ = [("col_width", c_int32), ("col_radix", c_int32), ("synth_width", c_int32), ("synth_radix", c_int32),
+                ("row_waves", c_int32), ("row_waves_bwd", c_int32)]
 
 
 class CCn2Profile(ctypes.Structure):
@@ -138,6 +144,8 @@ def lib():
                                       POINTER(c_int32)]
         L.turpy_plan_widths.argtypes = [c_void_p, POINTER(c_int32), POINTER(c_int32)]
         L.turpy_plan_set_widths.argtypes = [c_void_p, c_int32, c_int32]
+        L.turpy_plan_config.argtypes = [c_void_p, POINTER(CLaunchConfig)]
+        L.turpy_plan_set_config.argtypes = [c_void_p, POINTER(CLaunchConfig)]
         L.turpy_tune_cache_get.argtypes = [POINTER(CTuneEntry), c_int32, POINTER(c_int32)]
         L.turpy_tune_cache_put.argtypes = [POINTER(CTuneEntry), c_int32]
         L.turpy_tune_cache_clear.argtypes = []
@@ -331,22 +339,46 @@ def plan_set_widths(handle, col_width, synth_width):
     check(lib().turpy_plan_set_widths(handle, col_width, synth_width))
 
 
+CONFIG_FIELDS = ("col_width", "col_radix", "synth_width", "synth_radix", "row_waves", "row_waves_bwd")
+
+
+def plan_config(handle):
+    c = CLaunchConfig()
+    check(lib().turpy_plan_config(handle, ctypes.byref(c)))
+    return {f: getattr(c, f) for f in CONFIG_FIELDS}
+
+
+def plan_set_config(handle, config):
+    c = CLaunchConfig(**{f: int(config.get(f, 0)) for f in CONFIG_FIELDS})
+    check(lib().turpy_plan_set_config(handle, ctypes.byref(c)))
+
+
 def batch_tune(handle, flags, ws_ptr, ws_bytes, stream):
     check(lib().turpy_batch_tune(handle, flags, ws_ptr, ws_bytes, stream))
 
 
+TUNE_FIELDS = ("n", "batch_class", "width", "radix", "waves", "configs")
+
+
 def tune_cache_get():
-    """The tuning cache as a list of dicts (arch, kernel name, n, batch_class, width, us)."""
+    """The tuning cache as a list of dicts (arch, kernel name, n, batch_class,
+    width, radix, waves, configs, us, us_default)."""
     count = c_int32()
     check(lib().turpy_tune_cache_get(None, 0, ctypes.byref(count)))
     arr = (CTuneEntry * max(count.value, 1))()
     check(lib().turpy_tune_cache_get(arr, count.value, ctypes.byref(count)))
-    return [{"arch": e.arch.decode(), "kernel": TUNE_KERNELS[e.kernel], "n": e.n, "batch_class": e.batch_class,
-             "width": e.width, "us": [float(v) for v in e.us]} for e in arr[:count.value]]
+    out = []
+    for e in arr[:count.value]:
+        d = {"arch": e.arch.decode(), "kernel": TUNE_KERNELS[e.kernel]}
+        d.update({f: getattr(e, f) for f in TUNE_FIELDS})
+        d.update({"us": float(e.us), "us_default": float(e.us_default)})
+        out.append(d)
+    return out
 
 
 def tune_cache_put(entries):
-    """Insert dicts in the form tune_cache_get returns (us optional)."""
+    """Insert dicts in the form tune_cache_get returns (radix, waves, configs,
+    us and us_default optional)."""
     arr = (CTuneEntry * max(len(entries), 1))()
     for i, d in enumerate(entries):
         arch = d["arch"].encode()
@@ -355,9 +387,9 @@ def tune_cache_put(entries):
         kernel = d["kernel"]
         arr[i].arch = arch
         arr[i].kernel = TUNE_KERNELS.index(kernel) if isinstance(kernel, str) else int(kernel)
-        arr[i].n, arr[i].batch_class, arr[i].width = int(d["n"]), int(d["batch_class"]), int(d["width"])
-        for j, v in enumerate(d.get("us", [0.0, 0.0, 0.0])):
-            arr[i].us[j] = float(v)
+        for f in TUNE_FIELDS:
+            setattr(arr[i], f, int(d.get(f, 0)))
+        arr[i].us, arr[i].us_default = float(d.get("us", 0.0)), float(d.get("us_default", 0.0))
     check(lib().turpy_tune_cache_put(arr, len(entries)))
 
 

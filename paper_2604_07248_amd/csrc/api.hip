@@ -178,6 +178,9 @@ struct turpy_plan {
   const uint32_t* d_t = nullptr; // bound device time step (turpy_plan_bind_time), or NULL
   // strip widths of the column pass and the synthesis (0: built-in choice for n)
   int col_width = 0, synth_width = 0;
+  // second-pass radix of their transforms (0: the default plan) and the
+  // occupancy hints of the forward and adjoint screen row passes (0: default)
+  int col_radix = 0, synth_radix = 0, row_waves = 0, row_waves_bwd = 0;
   bool screen_ck = false;        // TURPY_SCREEN_CHECKPOINTS: checkpoints keep the screens' column halves
   std::string arch;              // device architecture (tuning-cache key)
 
@@ -193,7 +196,7 @@ struct turpy_plan {
   size_t off_ubuf() const { return ws_backward(); }
   size_t ws_reversible() const { return ws_backward() + 2 * align_up(static_cast<size_t>(R) * plane_bytes()); }
   // tuning: the scratch planes (synthesis) and the R-plane buffer (column pass)
-  size_t ws_tune() const { return ws_backward(); }
+  size_t ws_tune() const { return ws_reversible(); }
 };
 
 namespace {
@@ -476,6 +479,7 @@ turpy_status check_t(int64_t t) {
 RowArgs base_row(const turpy_plan* pl) {
   RowArgs a{};
   a.tw = pl->d_tw;
+  a.waves = pl->row_waves;
   a.R = pl->R;
   a.scale = 1.0f;
   a.M = pl->M;
@@ -500,6 +504,7 @@ ColArgs col_args(const turpy_plan* pl, int step, const float2* in, int64_t in_st
   c.table = pl->d_col + static_cast<size_t>(step) * pl->n;
   c.conj_table = adjoint ? 1 : 0;
   c.width = pl->col_width;
+  c.radix = pl->col_radix;
   c.angular = pl->tf_kind == TURPY_TF_ANGULAR_SPECTRUM ? 1 : 0;
   if (c.angular) {
     if (pl->d_as)
@@ -536,6 +541,7 @@ SynthArgs synth_args(const turpy_plan* pl, uint64_t seed, uint32_t t, int s, con
   a.spectra = spectra;
   a.M = pl->M;
   a.width = pl->synth_width;
+  a.radix = pl->synth_radix;
   if (ev) {
     a.evolve = 1;
     a.state = const_cast<float2*>(spectra);
@@ -972,6 +978,7 @@ turpy_status turpy_propagate_backward(turpy_plan* pl, uint64_t seed, int64_t t, 
     a.scale = out_spec ? inv_n : 1.0f;
     screen_fields(pl, src, screens_or_spectra, w, s, &a);
     a.backward = 1;
+    a.waves = pl->row_waves_bwd;
     a.ckpt_in = static_cast<const float2*>(checkpoints);
     a.grad_screens = grad_screens;
     TURPY_HIP(timed(row_family(a), st, [&] { return launch_row(n, a, pl->P, st); }),
@@ -1088,6 +1095,8 @@ turpy_status turpy_propagate_backward_reversible(turpy_plan* pl, uint64_t seed, 
       a.scale = cont ? inv_n : 1.0f;
       screen_fields(pl, src, screens_or_spectra, w, s, &a);
       a.backward = 1;
+      a.waves = pl->row_waves_bwd;
+    a.waves = pl->row_waves_bwd;
       a.ckpt_single = 1;
       if (chain == 1) {
         a.ckpt_out = wb;
@@ -1386,11 +1395,21 @@ turpy_status turpy_receiver_backward(int32_t n, double dx, double aperture_diame
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
-// Strip-width tuning and its process-wide cache.
+// Launch-configuration tuning and its process-wide cache.
 // ---------------------------------------------------------------------------
 namespace {
 
 constexpr int kWidths[3] = {4, 8, 16};
+
+// Second-pass radices built per grid size for the column pass and the
+// synthesis (0 = the default plan, min(16, N/16)).
+bool radix_built_rt(int n, int r) {
+  return r == 0 || ((n == 512 || n == 1024) && (r == 8 || r == 4)) || (n == 2048 && r == 8);
+}
+// Occupancy hints built for the screen row passes.
+bool waves_built_rt(int n, int w) { return w == 3 || (n >= 256 && (w == 2 || w == 4)); }
+
+bool is_row_kernel(int k) { return k == TURPY_TUNE_ROW_FWD || k == TURPY_TUNE_ROW_BWD; }
 
 struct TuneKey {
   std::string arch;
@@ -1436,46 +1455,53 @@ int col_kernel_id(const turpy_plan* pl) {
 
 TuneKey col_key(const turpy_plan* pl) { return TuneKey{pl->arch, col_kernel_id(pl), pl->n, bit_length(pl->R)}; }
 TuneKey synth_key(const turpy_plan* pl) { return TuneKey{pl->arch, TURPY_TUNE_SYNTH, pl->n, bit_length(pl->P)}; }
+TuneKey row_key(const turpy_plan* pl, int kernel) { return TuneKey{pl->arch, kernel, pl->n, bit_length(pl->P)}; }
 
-bool cached_width(const TuneKey& k, int* width) {
+bool cached(const TuneKey& k, turpy_tune_entry* e) {
   std::lock_guard<std::mutex> lock(g_tune_mu);
   auto it = g_tune.find(k);
   if (it == g_tune.end()) return false;
-  *width = it->second.width;
+  *e = it->second;
   return true;
 }
 
-void store(const TuneKey& k, int width, const float us[3]) {
-  turpy_tune_entry e{};
-  std::snprintf(e.arch, sizeof(e.arch), "%s", k.arch.c_str());
-  e.kernel = k.kernel;
-  e.n = k.n;
-  e.batch_class = k.batch_class;
-  e.width = width;
-  for (int i = 0; i < 3; ++i) e.us[i] = us ? us[i] : 0.0f;
+void store(const turpy_tune_entry& e) {
   std::lock_guard<std::mutex> lock(g_tune_mu);
-  g_tune[k] = e;
+  g_tune[TuneKey{std::string(e.arch), e.kernel, e.n, e.batch_class}] = e;
 }
 
+// Apply the cached choices for every key of the plan.
 void apply_cached_widths(turpy_plan* pl) {
-  int w = 0;
-  if (cached_width(col_key(pl), &w)) pl->col_width = w;
-  if (cached_width(synth_key(pl), &w)) pl->synth_width = w;
+  turpy_tune_entry e{};
+  if (cached(col_key(pl), &e)) {
+    pl->col_width = e.width;
+    pl->col_radix = e.radix;
+  }
+  if (cached(synth_key(pl), &e)) {
+    pl->synth_width = e.width;
+    pl->synth_radix = e.radix;
+  }
+  if (cached(row_key(pl, TURPY_TUNE_ROW_FWD), &e)) pl->row_waves = e.waves;
+  if (cached(row_key(pl, TURPY_TUNE_ROW_BWD), &e)) pl->row_waves_bwd = e.waves;
 }
 
-// Microseconds per launch of `launch(K)` for each width built for n (0 for
-// the others): one launch, then three loops of about 2 ms, minimum per launch.
+struct LaunchChoice {
+  int width, radix, waves;
+};
+
+// Microseconds per launch of `launch(choice)` for every choice: one launch,
+// then three loops of about 2 ms, minimum per launch.
 template <class Launch>
-turpy_status time_widths(int n, hipStream_t st, float us[3], Launch&& launch) {
+turpy_status time_choices(const std::vector<LaunchChoice>& choices, hipStream_t st, std::vector<float>* us,
+                          Launch&& launch) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
-  for (int i = 0; e == hipSuccess && i < 3; ++i) {
-    us[i] = 0.0f;
-    if (!strip_fits_rt(n, kWidths[i])) continue;
+  us->assign(choices.size(), 0.0f);
+  for (size_t i = 0; e == hipSuccess && i < choices.size(); ++i) {
     float ms = 0.0f;
     e = hipEventRecord(e0, st);
-    if (e == hipSuccess) e = launch(kWidths[i]);
+    if (e == hipSuccess) e = launch(choices[i]);
     if (e == hipSuccess) e = hipEventRecord(e1, st);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
@@ -1483,25 +1509,62 @@ turpy_status time_widths(int n, hipStream_t st, float us[3], Launch&& launch) {
     float best = 0.0f;
     for (int rep = 0; e == hipSuccess && rep < 3; ++rep) {
       e = hipEventRecord(e0, st);
-      for (int k = 0; e == hipSuccess && k < reps; ++k) e = launch(kWidths[i]);
+      for (int k = 0; e == hipSuccess && k < reps; ++k) e = launch(choices[i]);
       if (e == hipSuccess) e = hipEventRecord(e1, st);
       if (e == hipSuccess) e = hipEventSynchronize(e1);
       if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
       const float per = 1000.0f * ms / reps;
       if (e == hipSuccess && (rep == 0 || per < best)) best = per;
     }
-    us[i] = best;
+    (*us)[i] = best;
   }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   return e == hipSuccess ? TURPY_OK : hip_fail(e, "plan_tune: timed launch");
 }
 
-int fastest(const float us[3]) {
-  int best = 0;
-  for (int i = 0; i < 3; ++i)
-    if (us[i] > 0 && (best == 0 || us[i] < us[best - 1])) best = i + 1;
-  return best ? kWidths[best - 1] : 0;
+// Measure `choices`, keep the fastest under `key`; `dflt` is the built-in
+// choice (its time is kept beside the winner's).
+template <class Launch>
+turpy_status tune_key(const TuneKey& key, const std::vector<LaunchChoice>& choices, const LaunchChoice& dflt,
+                      hipStream_t st, Launch&& launch) {
+  std::vector<float> us;
+  if (turpy_status s = time_choices(choices, st, &us, launch)) return s;
+  size_t best = 0;
+  float us_default = 0.0f;
+  for (size_t i = 0; i < choices.size(); ++i) {
+    if (us[i] < us[best]) best = i;
+    const LaunchChoice& c = choices[i];
+    if (c.width == dflt.width && c.radix == dflt.radix && c.waves == dflt.waves) us_default = us[i];
+  }
+  turpy_tune_entry e{};
+  std::snprintf(e.arch, sizeof(e.arch), "%s", key.arch.c_str());
+  e.kernel = key.kernel;
+  e.n = key.n;
+  e.batch_class = key.batch_class;
+  e.width = choices[best].width;
+  e.radix = choices[best].radix;
+  e.waves = choices[best].waves;
+  e.configs = static_cast<int32_t>(choices.size());
+  e.us = us[best];
+  e.us_default = us_default;
+  store(e);
+  return TURPY_OK;
+}
+
+std::vector<LaunchChoice> strip_choices(int n) {
+  std::vector<LaunchChoice> out;
+  for (int k : kWidths)
+    for (int r : {0, 8, 4})
+      if (strip_fits_rt(n, k) && radix_built_rt(n, r)) out.push_back({k, r, 0});
+  return out;
+}
+
+std::vector<LaunchChoice> wave_choices(int n) {
+  std::vector<LaunchChoice> out;
+  for (int w : {3, 2, 4})
+    if (waves_built_rt(n, w)) out.push_back({0, 0, w});
+  return out;
 }
 
 }  // namespace
@@ -1521,40 +1584,83 @@ turpy_status turpy_plan_tune(turpy_plan* pl, uint32_t flags, void* ws, size_t ws
   if (!pl) return fail(TURPY_E_INVALID, "plan_tune: NULL plan");
   if (!ws || ws_bytes < pl->ws_tune())
     return fail(TURPY_E_WORKSPACE, "plan_tune: workspace %zu < %zu bytes", ws_bytes, pl->ws_tune());
+  if (turpy_status s_ = check_device(pl)) return s_;
   hipStream_t st = static_cast<hipStream_t>(stream);
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   TURPY_HIP(hipStreamIsCapturing(st, &cap), "plan_tune: stream state");
   if (cap != hipStreamCaptureStatusNone) return fail(TURPY_E_INVALID, "plan_tune: the stream is capturing");
   const bool force = (flags & TURPY_TUNE_FORCE) != 0;
   const TuneKey ck = col_key(pl), sk = synth_key(pl);
-  int w = 0;
-  const bool need_col = force || !cached_width(ck, &w);
-  const bool need_synth = pl->M > 0 && (force || !cached_width(sk, &w));
-  if (need_col || need_synth) TURPY_HIP(hipMemsetAsync(ws, 0, pl->ws_tune(), st), "plan_tune: clear workspace");
+  const TuneKey rf = row_key(pl, TURPY_TUNE_ROW_FWD), rb = row_key(pl, TURPY_TUNE_ROW_BWD);
+  turpy_tune_entry e{};
+  const bool screens = pl->M > 0;
+  const bool need_col = force || !cached(ck, &e);
+  const bool need_synth = screens && (force || !cached(sk, &e));
+  const bool need_rf = screens && (force || !cached(rf, &e));
+  const bool need_rb = screens && (force || !cached(rb, &e));
+  if (need_col || need_synth || need_rf || need_rb)
+    TURPY_HIP(hipMemsetAsync(ws, 0, pl->ws_tune(), st), "plan_tune: clear workspace");
   const Ws wsp = carve(pl, ws);
-  float us[3];
+  const int n = pl->n;
+  const int64_t plane = static_cast<int64_t>(n) * n;
   if (need_col) {
-    const int64_t plane = static_cast<int64_t>(pl->n) * pl->n;
     ColArgs c = col_args(pl, 0, wsp.gbuf, plane, wsp.gbuf, pl->R, false);
-    if (turpy_status s = time_widths(pl->n, st, us, [&](int k) {
-          c.width = k;
-          return launch_col(pl->n, c, st);
+    if (turpy_status s = tune_key(ck, strip_choices(n), {default_col_width(n), 0, 0}, st, [&](const LaunchChoice& k) {
+          c.width = k.width;
+          c.radix = k.radix;
+          return launch_col(n, c, st);
         }))
       return s;
-    store(ck, fastest(us), us);
   }
   if (need_synth) {
     SynthArgs a = synth_args(pl, 0, 0, 0, nullptr, wsp);
     a.t_dev = nullptr;
-    if (turpy_status s = time_widths(pl->n, st, us, [&](int k) {
-          a.width = k;
-          return launch_synth(pl->n, a, st);
-        }))
+    if (turpy_status s = tune_key(sk, strip_choices(n), {default_synth_width(n), 0, 0}, st,
+                                  [&](const LaunchChoice& k) {
+                                    a.width = k.width;
+                                    a.radix = k.radix;
+                                    return launch_synth(n, a, st);
+                                  }))
       return s;
-    store(sk, fastest(us), us);
   }
-  if (cached_width(ck, &w)) pl->col_width = w;
-  if (pl->M > 0 && cached_width(sk, &w)) pl->synth_width = w;
+  if (need_rf || need_rb) {
+    // screen 0's row pass on the workspace planes: a forward one without
+    // checkpoints, an adjoint one reading a one-screen checkpoint
+    float2* ub = reinterpret_cast<float2*>(static_cast<char*>(ws) + pl->off_ubuf());
+    RowArgs a = base_row(pl);
+    a.in = wsp.gbuf;
+    a.in_stride = plane;
+    a.out = wsp.gbuf;
+    a.in_spectral = 1;
+    a.out_spectral = 1;
+    a.scale = 1.0f / n;
+    a.M = 1;
+    screen_fields(pl, TURPY_SCREENS_SYNTH, nullptr, wsp, 0, &a);
+    a.screen = 0;
+    if (need_rf) {
+      a.post = pl->d_row + n;
+      if (turpy_status s = tune_key(rf, wave_choices(n), {0, 0, 3}, st, [&](const LaunchChoice& k) {
+            a.waves = k.waves;
+            return launch_row(n, a, pl->P, st);
+          }))
+        return s;
+    }
+    if (need_rb) {
+      a.post = nullptr;
+      a.pre = pl->d_row + n;
+      a.conj_tables = 1;
+      a.backward = 1;
+      a.ckpt_single = 1;
+      a.ckpt_in = ub;
+      a.grad_screens = reinterpret_cast<float*>(ub + static_cast<size_t>(pl->R) * plane);
+      if (turpy_status s = tune_key(rb, wave_choices(n), {0, 0, 3}, st, [&](const LaunchChoice& k) {
+            a.waves = k.waves;
+            return launch_row(n, a, pl->P, st);
+          }))
+        return s;
+    }
+  }
+  apply_cached_widths(pl);
   return turpy_plan_widths(pl, col_width, synth_width);
 }
 
@@ -1575,6 +1681,37 @@ turpy_status turpy_plan_set_widths(turpy_plan* pl, int32_t col_width, int32_t sy
   return TURPY_OK;
 }
 
+turpy_status turpy_plan_config(const turpy_plan* pl, turpy_launch_config* out) {
+  if (!pl || !out) return fail(TURPY_E_INVALID, "plan_config: NULL argument");
+  out->col_width = pl->col_width ? pl->col_width : default_col_width(pl->n);
+  out->col_radix = pl->col_radix;
+  out->synth_width = pl->synth_width ? pl->synth_width : default_synth_width(pl->n);
+  out->synth_radix = pl->synth_radix;
+  out->row_waves = pl->row_waves ? pl->row_waves : 3;
+  out->row_waves_bwd = pl->row_waves_bwd ? pl->row_waves_bwd : 3;
+  return TURPY_OK;
+}
+
+turpy_status turpy_plan_set_config(turpy_plan* pl, const turpy_launch_config* c) {
+  if (!pl || !c) return fail(TURPY_E_INVALID, "plan_set_config: NULL argument");
+  const int n = pl->n;
+  for (int32_t k : {c->col_width, c->synth_width})
+    if (k != 0 && !strip_fits_rt(n, k))
+      return fail(TURPY_E_INVALID, "plan_set_config: %d columns per block is not built for n=%d", k, n);
+  for (int32_t r : {c->col_radix, c->synth_radix})
+    if (!radix_built_rt(n, r)) return fail(TURPY_E_INVALID, "plan_set_config: radix %d is not built for n=%d", r, n);
+  for (int32_t w : {c->row_waves, c->row_waves_bwd})
+    if (w != 0 && !waves_built_rt(n, w))
+      return fail(TURPY_E_INVALID, "plan_set_config: %d waves per SIMD is not built for n=%d", w, n);
+  pl->col_width = c->col_width;
+  pl->col_radix = c->col_radix;
+  pl->synth_width = c->synth_width;
+  pl->synth_radix = c->synth_radix;
+  pl->row_waves = c->row_waves;
+  pl->row_waves_bwd = c->row_waves_bwd;
+  return TURPY_OK;
+}
+
 turpy_status turpy_tune_cache_get(turpy_tune_entry* entries, int32_t capacity, int32_t* count) {
   if (!count || capacity < 0 || (capacity > 0 && !entries))
     return fail(TURPY_E_INVALID, "tune_cache_get: NULL argument or negative capacity");
@@ -1592,16 +1729,26 @@ turpy_status turpy_tune_cache_put(const turpy_tune_entry* entries, int32_t count
   if (count < 0 || (count > 0 && !entries)) return fail(TURPY_E_INVALID, "tune_cache_put: NULL entries");
   for (int32_t i = 0; i < count; ++i) {
     const turpy_tune_entry& e = entries[i];
-    if (e.kernel < TURPY_TUNE_COL_FRESNEL || e.kernel > TURPY_TUNE_SYNTH)
+    if (e.kernel < TURPY_TUNE_COL_FRESNEL || e.kernel > TURPY_TUNE_ROW_BWD)
       return fail(TURPY_E_INVALID, "tune_cache_put: entry %d has unknown kernel %d", i, e.kernel);
-    if (!strip_fits_rt(e.n, e.width) || e.n < 16 || e.n > 2048 || !pow2(e.n))
-      return fail(TURPY_E_INVALID, "tune_cache_put: entry %d: width %d is not built for n=%d", i, e.width, e.n);
+    if (e.n < 16 || e.n > 2048 || !pow2(e.n))
+      return fail(TURPY_E_INVALID, "tune_cache_put: entry %d: n=%d is not built", i, e.n);
+    if (is_row_kernel(e.kernel)) {
+      if (e.width != 0 || e.radix != 0 || !waves_built_rt(e.n, e.waves))
+        return fail(TURPY_E_INVALID, "tune_cache_put: entry %d: waves %d is not built for n=%d (row kernels take "
+                    "waves only)", i, e.waves, e.n);
+    } else {
+      if (!strip_fits_rt(e.n, e.width))
+        return fail(TURPY_E_INVALID, "tune_cache_put: entry %d: width %d is not built for n=%d", i, e.width, e.n);
+      if (!radix_built_rt(e.n, e.radix) || e.waves != 0)
+        return fail(TURPY_E_INVALID, "tune_cache_put: entry %d: radix %d / waves %d is not built for n=%d", i,
+                    e.radix, e.waves, e.n);
+    }
     if (e.batch_class < 1 || e.batch_class > 63)
       return fail(TURPY_E_INVALID, "tune_cache_put: entry %d has batch class %d", i, e.batch_class);
     if (strnlen(e.arch, sizeof(e.arch)) == sizeof(e.arch))
       return fail(TURPY_E_INVALID, "tune_cache_put: entry %d: arch is not NUL-terminated", i);
-    const TuneKey k{std::string(e.arch), e.kernel, e.n, e.batch_class};
-    store(k, e.width, e.us);
+    store(e);
   }
   return TURPY_OK;
 }

@@ -11,7 +11,8 @@
 // transform chain without an LDS round trip between them.
 //
 // Radix plan for E = 16: first pass radix 16 (no twiddles), second pass radix
-// min(16, N/16) at sub-length 16, third pass radix N/256 at sub-length 256.
+// R2 (default min(16, N/16)) at sub-length 16, third pass radix N/(16 R2) at
+// sub-length 16 R2.
 #pragma once
 
 #include "device_common.hpp"
@@ -204,7 +205,20 @@ __device__ __forceinline__ void stockham_pass(float2 (&x)[E], const Lds& lds, in
 // Full length-N transform of the strided-layout registers (unnormalised in
 // both directions; forward uses exp(-2 pi i n k / N)).
 // WAVE: the T = N/E threads of the transform lie in one wavefront (see lds_sync).
-template <int N, int E, bool INV, bool WAVE = false, class Lds>
+// R2SEL: radix of the second pass (0: min(16, N/16)); the third pass takes the
+// rest, N / (16 R2SEL), at sub-length 16 R2SEL.  Every plan leaves its outputs
+// in the same strided natural-order layout (the last pass writes output index
+// j + (N/R) r back to slot q + (E/R) r, the slot it read).
+template <int N, int R2SEL>
+constexpr int second_radix() {
+  return R2SEL ? R2SEL : (N / 16 >= 16 ? 16 : N / 16);
+}
+template <int N, int R2SEL>
+constexpr int fft_passes() {
+  return N == 16 ? 1 : (N / 16 == second_radix<N, R2SEL>() ? 2 : 3);
+}
+
+template <int N, int E, bool INV, bool WAVE = false, int R2SEL = 0, class Lds>
 __device__ __forceinline__ void fft(float2 (&x)[E], const Lds& lds, int t, const float2* __restrict__ tw) {
   static_assert(E == 16, "radix plan written for 16 elements per thread");
   static_assert(N >= 16 && N <= 4096 && (N & (N - 1)) == 0, "N must be a power of two in 16..4096");
@@ -212,10 +226,11 @@ __device__ __forceinline__ void fft(float2 (&x)[E], const Lds& lds, int t, const
   constexpr int REM1 = N / 16;
   stockham_pass<N, E, 16, 1, INV, REM1 == 1, WAVE>(x, lds, t, tw);
   if constexpr (REM1 > 1) {
-    constexpr int R2 = REM1 >= 16 ? 16 : REM1;
+    constexpr int R2 = second_radix<N, R2SEL>();
+    static_assert(REM1 % R2 == 0 && R2 <= 16 && REM1 / R2 <= 16, "unsupported radix plan");
     constexpr int REM2 = REM1 / R2;
     stockham_pass<N, E, R2, 16, INV, REM2 == 1, WAVE>(x, lds, t, tw);
-    if constexpr (REM2 > 1) stockham_pass<N, E, REM2, 256, INV, true, WAVE>(x, lds, t, tw);
+    if constexpr (REM2 > 1) stockham_pass<N, E, REM2, 16 * R2, INV, true, WAVE>(x, lds, t, tw);
   }
 }
 
@@ -231,13 +246,11 @@ __device__ __forceinline__ const float2* stage_twiddles(float2* lds_tw, const fl
 
 // Barriers executed by fft<N, 16, ...>: a group with no transform to do calls
 // this so that every thread of a block passes the same barrier sequence.
-template <int N, bool WAVE = false>
+template <int N, bool WAVE = false, int R2SEL = 0>
 __device__ __forceinline__ void idle_fft() {
   if constexpr (WAVE) return;
-  constexpr int REM1 = N / 16;
-  constexpr int PASSES = REM1 == 1 ? 1 : (REM1 <= 16 ? 2 : 3);
 #pragma unroll
-  for (int i = 0; i < 2 * (PASSES - 1); ++i) __syncthreads();
+  for (int i = 0; i < 2 * (fft_passes<N, R2SEL>() - 1); ++i) __syncthreads();
 }
 
 }  // namespace turpy

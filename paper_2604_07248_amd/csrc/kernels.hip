@@ -221,8 +221,8 @@ __global__ __launch_bounds__(row_block<N>()) void row_pass_kernel(RowArgs a) {
 // conjugate phase) and transform forward.  Both halves pass the same barrier
 // sequence: a half with no transform at a stage runs idle_fft.
 // ---------------------------------------------------------------------------
-template <int N, int SCREEN, bool BWD>
-__global__ __launch_bounds__(pair_block<N>()) __attribute__((amdgpu_waves_per_eu(3, 0)))
+template <int N, int SCREEN, bool BWD, int W>
+__global__ __launch_bounds__(pair_block<N>()) __attribute__((amdgpu_waves_per_eu(W, 0)))
 void row_pair_kernel(RowArgs a) {
   constexpr int T = N / kE;
   constexpr int G = pair_rows<N>();
@@ -451,8 +451,8 @@ void row_pair_kernel(RowArgs a) {
 // barriers a stage whose two transforms differ in kind passes the same
 // barriers on both sides (idle_fft).
 // ---------------------------------------------------------------------------
-template <int N>
-__global__ __launch_bounds__(relay_block<N>()) __attribute__((amdgpu_waves_per_eu(3, 0)))
+template <int N, int W>
+__global__ __launch_bounds__(relay_block<N>()) __attribute__((amdgpu_waves_per_eu(W, 0)))
 void row_relay_kernel(RowArgs a) {
   constexpr int T = N / kE;
   constexpr int G = relay_rows<N>();
@@ -623,7 +623,7 @@ __device__ __forceinline__ float2 angular_correction(const ColArgs& a, int k0, i
   }
 }
 
-template <int N, int ANGULAR, int K>
+template <int N, int ANGULAR, int K, int R2SEL>
 __global__ __launch_bounds__(K * (N / kE))
 void col_pass_kernel(ColArgs a) {
   constexpr int T = N / kE;
@@ -645,7 +645,7 @@ void col_pass_kernel(ColArgs a) {
   float2 x[kE];
 #pragma unroll
   for (int m = 0; m < kE; ++m) x[m] = (src + static_cast<size_t>(t) * N)[static_cast<size_t>(T * m) * N];
-  fft<N, kE, false>(x, lds, t, tw);
+  fft<N, kE, false, false, R2SEL>(x, lds, t, tw);
 #pragma unroll
   for (int m = 0; m < kE; ++m) {
     const int k0 = t + T * m;
@@ -653,7 +653,7 @@ void col_pass_kernel(ColArgs a) {
     if constexpr (ANGULAR != TF_FRESNEL_ONLY) h = c_mul(h, angular_correction<ANGULAR>(a, k0, k1, N));
     x[m] = a.conj_table ? c_mulc(x[m], h) : c_mul(x[m], h);
   }
-  fft<N, kE, true>(x, lds, t, tw);
+  fft<N, kE, true, false, R2SEL>(x, lds, t, tw);
   float2* dst = a.out + r * static_cast<int64_t>(N) * N + k1;
 #pragma unroll
   for (int m = 0; m < kE; ++m) (dst + static_cast<size_t>(t) * N)[static_cast<size_t>(T * m) * N] = x[m];
@@ -663,7 +663,7 @@ void col_pass_kernel(ColArgs a) {
 // Column half of the screen synthesis: noise x PSD weight (Eq. S16/S17), or a
 // stored spectrum, then the unnormalised inverse transform along y.
 // ---------------------------------------------------------------------------
-template <int N, int K>
+template <int N, int K, int R2SEL>
 __global__ __launch_bounds__(K * (N / kE))
 void synth_col_kernel(SynthArgs a) {
   constexpr int T = N / kE;
@@ -738,7 +738,7 @@ void synth_col_kernel(SynthArgs a) {
       x[m + kE / 2] = c_scale(box_muller(v.z, v.w), w_hi);
     }
   }
-  fft<N, kE, true>(x, lds, t, tw);
+  fft<N, kE, true, false, R2SEL>(x, lds, t, tw);
   float2* dst = a.scratch + j * static_cast<int64_t>(N) * N + k1;
 #pragma unroll
   for (int m = 0; m < kE; ++m) (dst + static_cast<size_t>(t) * N)[static_cast<size_t>(T * m) * N] = x[m];
@@ -1073,20 +1073,54 @@ __global__ __launch_bounds__(256) void copy_kernel(const float2* in, int64_t in_
   out[idx] = in[r * in_stride + p];
 }
 
+// Occupancy hints of the screen row passes (minimum waves per SIMD the
+// register allocation must allow): 3 by default; the tuner also times 2 and 4
+// for N >= 256.
+constexpr int kRowWaves = 3;
+constexpr bool row_waves_built(int n, int w) { return w == kRowWaves || (n >= 256 && (w == 2 || w == 4)); }
+
 // The relay kernel for forward passes with synthesised screens and no
 // checkpoint output, where its workers are whole waves and it keeps three
 // waves per SIMD (N <= 1024); false: not launched.  With checkpoint writes
 // and in the adjoint the pair schedule measured as fast or faster.
+// A hint not built for N launches the default one (the host refuses such
+// choices before they reach a plan).
+template <int N, int W>
+void relay_launch_w(const RowArgs& a, int64_t pairs, hipStream_t s) {
+  constexpr int WB = row_waves_built(N, W) ? W : kRowWaves;
+  const dim3 grid(N / (2 * relay_rows<N>()), static_cast<uint32_t>(pairs));
+  hipLaunchKernelGGL((row_relay_kernel<N, WB>), grid, dim3(relay_block<N>()), 0, s, a);
+}
+
 template <int N>
 bool relay_launch(const RowArgs& a, int64_t pairs, hipStream_t s) {
   if constexpr (!relay_fits<N>() || N > 1024) {
     return false;
   } else {
     if (a.screen_mode != ROW_SCRATCH || a.backward || a.conj_tables || a.ckpt_out || a.pre) return false;
-    const dim3 grid(N / (2 * relay_rows<N>()), static_cast<uint32_t>(pairs));
-    hipLaunchKernelGGL((row_relay_kernel<N>), grid, dim3(relay_block<N>()), 0, s, a);
+    switch (a.waves ? a.waves : kRowWaves) {
+      case 2: relay_launch_w<N, 2>(a, pairs, s); break;
+      case 4: relay_launch_w<N, 4>(a, pairs, s); break;
+      default: relay_launch_w<N, kRowWaves>(a, pairs, s); break;
+    }
     return true;
   }
+}
+
+template <int N, int SCREEN, bool BWD, int W>
+void pair_launch_w(const RowArgs& a, int64_t pairs, hipStream_t s) {
+  constexpr int WB = row_waves_built(N, W) && SCREEN == ROW_SCRATCH ? W : kRowWaves;
+  constexpr int GP = pair_rows<N>();
+  const dim3 pgrid(N / GP, static_cast<uint32_t>(pairs));
+  hipLaunchKernelGGL((row_pair_kernel<N, SCREEN, BWD, WB>), pgrid, dim3(pair_block<N>()), 0, s, a);
+}
+
+template <int N, int SCREEN, bool BWD>
+void pair_launch(const RowArgs& a, int64_t pairs, hipStream_t s) {
+  const int w = SCREEN == ROW_SCRATCH && a.waves ? a.waves : kRowWaves;
+  if (w == 2) pair_launch_w<N, SCREEN, BWD, 2>(a, pairs, s);
+  else if (w == 4) pair_launch_w<N, SCREEN, BWD, 4>(a, pairs, s);
+  else pair_launch_w<N, SCREEN, BWD, kRowWaves>(a, pairs, s);
 }
 
 template <int N>
@@ -1109,40 +1143,49 @@ hipError_t row_launch(const RowArgs& a, int64_t pairs, hipStream_t s) {
   } else if (relay_launch<N>(a, pairs, s)) {
     // synthesised screens on the relay schedule
   } else {
-    constexpr int GP = pair_rows<N>();
-    const dim3 pgrid(N / GP, static_cast<uint32_t>(pairs));
-    const dim3 pblock(pair_block<N>());
-    if (a.screen_mode == ROW_SCRATCH && !a.backward)
-      hipLaunchKernelGGL((row_pair_kernel<N, ROW_SCRATCH, false>), pgrid, pblock, 0, s, a);
-    else if (a.screen_mode == ROW_SCRATCH)
-      hipLaunchKernelGGL((row_pair_kernel<N, ROW_SCRATCH, true>), pgrid, pblock, 0, s, a);
-    else if (!a.backward)
-      hipLaunchKernelGGL((row_pair_kernel<N, ROW_MATERIALIZED, false>), pgrid, pblock, 0, s, a);
-    else
-      hipLaunchKernelGGL((row_pair_kernel<N, ROW_MATERIALIZED, true>), pgrid, pblock, 0, s, a);
+    if (a.screen_mode == ROW_SCRATCH && !a.backward) pair_launch<N, ROW_SCRATCH, false>(a, pairs, s);
+    else if (a.screen_mode == ROW_SCRATCH) pair_launch<N, ROW_SCRATCH, true>(a, pairs, s);
+    else if (!a.backward) pair_launch<N, ROW_MATERIALIZED, false>(a, pairs, s);
+    else pair_launch<N, ROW_MATERIALIZED, true>(a, pairs, s);
   }
   return hipGetLastError();
 }
 
-template <int N, int K>
-hipError_t col_launch_k(const ColArgs& a, hipStream_t s) {
-  if constexpr (!strip_fits<N, K>()) {
+// Second-pass radices built for the column pass and the synthesis: the
+// default plan, and for N = 512..2048 the alternatives the tuner times.
+constexpr bool radix_built(int n, int r2) {
+  return r2 == 0 || ((n == 512 || n == 1024) && (r2 == 8 || r2 == 4)) || (n == 2048 && r2 == 8);
+}
+
+template <int N, int K, int R2SEL>
+hipError_t col_launch_kr(const ColArgs& a, hipStream_t s) {
+  if constexpr (!strip_fits<N, K>() || !radix_built(N, R2SEL)) {
     return hipErrorInvalidValue;
   } else {
     const uint64_t blocks = static_cast<uint64_t>(N / K) * a.R;
     const dim3 grid(static_cast<uint32_t>(blocks)), block(K * (N / kE));
     if (!a.angular)
-      hipLaunchKernelGGL((col_pass_kernel<N, TF_FRESNEL_ONLY, K>), grid, block, 0, s, a);
+      hipLaunchKernelGGL((col_pass_kernel<N, TF_FRESNEL_ONLY, K, R2SEL>), grid, block, 0, s, a);
     else if (a.as_table)
-      hipLaunchKernelGGL((col_pass_kernel<N, TF_AS_TABLE, K>), grid, block, 0, s, a);
+      hipLaunchKernelGGL((col_pass_kernel<N, TF_AS_TABLE, K, R2SEL>), grid, block, 0, s, a);
     else
-      hipLaunchKernelGGL((col_pass_kernel<N, TF_AS_FP32, K>), grid, block, 0, s, a);
+      hipLaunchKernelGGL((col_pass_kernel<N, TF_AS_FP32, K, R2SEL>), grid, block, 0, s, a);
     return hipGetLastError();
   }
 }
 
+template <int N, int K>
+hipError_t col_launch_k(const ColArgs& a, hipStream_t s) {
+  switch (a.radix) {
+    case 0: return col_launch_kr<N, K, 0>(a, s);
+    case 4: return col_launch_kr<N, K, 4>(a, s);
+    case 8: return col_launch_kr<N, K, 8>(a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 // Strip width a.width (4, 8 or 16 columns per block), or the built-in choice
-// for N when a.width is 0.
+// for N when a.width is 0; second-pass radix a.radix (0: the default plan).
 template <int N>
 hipError_t col_launch(const ColArgs& a, hipStream_t s) {
   switch (a.width ? a.width : col_width<N>()) {
@@ -1153,14 +1196,25 @@ hipError_t col_launch(const ColArgs& a, hipStream_t s) {
   }
 }
 
-template <int N, int K>
-hipError_t synth_launch_k(const SynthArgs& a, hipStream_t s) {
-  if constexpr (!strip_fits<N, K>()) {
+template <int N, int K, int R2SEL>
+hipError_t synth_launch_kr(const SynthArgs& a, hipStream_t s) {
+  if constexpr (!strip_fits<N, K>() || !radix_built(N, R2SEL)) {
     return hipErrorInvalidValue;
   } else {
     const uint64_t blocks = static_cast<uint64_t>(N / K) * a.P;
-    hipLaunchKernelGGL((synth_col_kernel<N, K>), dim3(static_cast<uint32_t>(blocks)), dim3(K * (N / kE)), 0, s, a);
+    hipLaunchKernelGGL((synth_col_kernel<N, K, R2SEL>), dim3(static_cast<uint32_t>(blocks)), dim3(K * (N / kE)), 0, s,
+                       a);
     return hipGetLastError();
+  }
+}
+
+template <int N, int K>
+hipError_t synth_launch_k(const SynthArgs& a, hipStream_t s) {
+  switch (a.radix) {
+    case 0: return synth_launch_kr<N, K, 0>(a, s);
+    case 4: return synth_launch_kr<N, K, 4>(a, s);
+    case 8: return synth_launch_kr<N, K, 8>(a, s);
+    default: return hipErrorInvalidValue;
   }
 }
 

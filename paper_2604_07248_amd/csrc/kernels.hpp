@@ -43,6 +43,7 @@ struct RowArgs {
   int ckpt_single;          // 1: ckpt_out / ckpt_in hold this screen only, [R][N][N]
   float* grad_screens;      // backward: [R][M][N][N] dL/dphi, or NULL
   float* phase_out;         // [R][M][N][N] radians: write the screens themselves, or NULL
+  int waves;                // occupancy hint of the screen row passes (2, 3, 4; 0: the default)
 };
 
 struct ColArgs {
@@ -58,6 +59,7 @@ struct ColArgs {
   float as_b;               // (2 pi df)^2 / k^2: kappa^2 / k^2 per unit of q
   float as_c;               // -dz (2 pi df)^4 / (4 pi k^3): revolutions per q^2 / (1 + sqrt(1 - B q))^2
   int width;                // columns per block (4, 8, 16), 0: the built-in choice for N
+  int radix;                // radix of the transforms' second pass (0: the default plan)
 };
 
 struct SynthArgs {
@@ -78,6 +80,7 @@ struct SynthArgs {
   const float2* spectra;    // [P][M][N][N] radians, or NULL for synthesis
   int M;
   int width;                // columns per block (4, 8, 16), 0: the built-in choice for N
+  int radix;                // radix of the transform's second pass (0: the default plan)
   // AR step fused into the read of the stored spectra (Eq. 4 then Eq. 5 with
   // innovations drawn at the time step): the evolved spectrum is written back
   // to `state` (the same array as `spectra`) and transformed

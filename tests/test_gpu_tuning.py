@@ -1,8 +1,10 @@
-"""Strip-width tuning on the GPU.  Every column-pass and synthesis width built
-for a grid size gives bit-identical fields and adjoints (the width sets the
-block shape, not the arithmetic), so the parity of the default widths against
-the oracle carries over to every tuned plan.  The tuner keeps a measured
-width, caches it per key and hands it to plans created later."""
+"""Launch-configuration tuning on the GPU.  Every column-pass and synthesis
+width built for a grid size, and every occupancy hint of the screen row
+passes, gives bit-identical fields and adjoints (they set the block shape and
+the register budget, not the arithmetic), so the parity of the default
+choices against the oracle carries over.  The other radix plans round
+differently: each is checked against the oracle.  The tuner keeps the fastest
+measured configuration, caches it per key and hands it to plans created later."""
 import ctypes
 
 import numpy as np
@@ -89,37 +91,99 @@ def test_every_width_bit_identical(api, case):
     plan.close()
 
 
+RADICES = {512: (8, 4), 1024: (8, 4), 2048: (8,)}
+
+
+@pytest.mark.parametrize("n", [512, 1024, 2048])
+def test_radix_plans_match_oracle(api, n):
+    """The second-pass radices built besides the default plan, in the column
+    pass and the synthesis: forward and adjoint within 1e-4 of the oracle and
+    within rounding of the default plan."""
+    r = 2
+    path = sized_path(n, r, 2)
+    plan = api.Plan(path)
+    u0 = c64(workloads.seeded_field((r, n, n), 41))
+    g = c64(workloads.seeded_field((r, n, n), 42))
+    ref, ck = plan.propagate(u0, seed=6, checkpoints=True)
+    ref_gin, _ = plan.propagate_backward(g, ck, seed=6)
+    ora = oracle_propagate(path, 6, u0.cpu().numpy())[0]
+    for radix in RADICES[n]:
+        plan.set_config(col_radix=radix, synth_radix=radix)
+        assert plan.config["col_radix"] == radix and plan.config["synth_radix"] == radix
+        out, ck2 = plan.propagate(u0, seed=6, checkpoints=True)
+        gin, _ = plan.propagate_backward(g, ck2, seed=6)
+        e_def = rel_l2(out.cpu().numpy(), ref.cpu().numpy())
+        e_ora = rel_l2(out.cpu().numpy(), ora)
+        e_g = rel_l2(gin.cpu().numpy(), ref_gin.cpu().numpy())
+        say(f"[radix] n={n} R2={radix}: vs default {e_def:.2e}, vs oracle {e_ora:.2e}, adjoint vs default {e_g:.2e}")
+        assert e_ora < TOL and e_def < 1e-5 and e_g < 1e-5
+    with pytest.raises(B.TurpyError):
+        plan.set_config(col_radix=2)
+    plan.close()
+
+
+@pytest.mark.parametrize("n", [256, 1024])
+def test_row_occupancy_hints_bit_identical(api, n):
+    """The occupancy hints 2, 3, 4 of the forward (relay) and adjoint (pair)
+    screen row passes change the register budget only."""
+    r = 4
+    path = sized_path(n, r, 2, sh=3)
+    plan = api.Plan(path)
+    u0 = c64(workloads.seeded_field((r, n, n), 51))
+    g = c64(workloads.seeded_field((r, n, n), 52))
+    ref = plan.propagate(u0, seed=2)
+    _, ck = plan.propagate(u0, seed=2, checkpoints=True)
+    ref_gin, ref_gphi = plan.propagate_backward(g, ck, seed=2)
+    for w in (2, 4):
+        plan.set_config(row_waves=w, row_waves_bwd=w)
+        assert plan.config["row_waves"] == w and plan.config["row_waves_bwd"] == w
+        assert torch.equal(plan.propagate(u0, seed=2), ref)
+        gin, gphi = plan.propagate_backward(g, ck, seed=2)
+        assert torch.equal(gin, ref_gin) and torch.equal(gphi, ref_gphi)
+    plan.set_config()
+    assert plan.config["row_waves"] == 3
+    with pytest.raises(B.TurpyError):
+        api.Plan(sized_path(64, 2, 1)).set_config(row_waves=2)  # hints 2 and 4 are built from N = 256
+    plan.close()
+
+
 def test_tune_measures_caches_and_hands_on(api):
     path = sized_path(512, 8, 2)
     plan = api.Plan(path)
     u0 = c64(workloads.seeded_field((8, 512, 512), 31))
     ref = plan.propagate(u0, seed=4)
-    w = plan.tune()
-    say(f"[tune] n=512 R=8 chose {w}; cache {api.tune_cache()}")
-    assert w == plan.widths and w["col"] in built(512) and w["synth"] in built(512)
+    cfg = plan.tune()
+    say(f"[tune] n=512 R=8 chose {cfg}; cache {api.tune_cache()}")
+    assert cfg == plan.config and cfg["col_width"] in built(512) and cfg["synth_width"] in built(512)
     entries = api.tune_cache()
     arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
     keys = {(e["arch"], e["kernel"], e["n"], e["batch_class"]) for e in entries}
-    assert keys == {(arch, "col_fresnel", 512, 4), (arch, "synth", 512, 3)}  # R = 8, 4 pairs
+    # R = 8: 4 pairs
+    assert keys == {(arch, "col_fresnel", 512, 4), (arch, "synth", 512, 3), (arch, "row_fwd", 512, 3),
+                    (arch, "row_bwd", 512, 3)}
     for e in entries:
-        times = {k: us for k, us in zip((4, 8, 16), e["us"]) if us > 0}
-        assert sorted(times) == built(512)
-        assert times[e["width"]] == min(times.values())
-        assert e["width"] == w["col" if e["kernel"] == "col_fresnel" else "synth"]
-    assert torch.equal(plan.propagate(u0, seed=4), ref)
+        assert 0 < e["us"] <= e["us_default"] * (1 + 1e-6)
+        if e["kernel"] in ("col_fresnel", "synth"):
+            assert e["configs"] == len(built(512)) * 3 and e["waves"] == 0
+        else:
+            assert e["configs"] == 3 and e["width"] == 0 and e["waves"] in (2, 3, 4)
+    by = {e["kernel"]: e for e in entries}
+    assert (cfg["col_width"], cfg["col_radix"]) == (by["col_fresnel"]["width"], by["col_fresnel"]["radix"])
+    assert (cfg["synth_width"], cfg["synth_radix"]) == (by["synth"]["width"], by["synth"]["radix"])
+    assert (cfg["row_waves"], cfg["row_waves_bwd"]) == (by["row_fwd"]["waves"], by["row_bwd"]["waves"])
+    assert rel_l2(plan.propagate(u0, seed=4).cpu().numpy(), ref.cpu().numpy()) < 1e-5
     # a later plan with the same keys starts from the cache; tuning it measures nothing
     plan2 = api.Plan(path)
-    assert plan2.widths == w
-    assert plan2.tune() == w and api.tune_cache() == entries
+    assert plan2.config == cfg
+    assert plan2.tune() == cfg and api.tune_cache() == entries
     # an entry put by the caller is what the next plan uses
-    other = 4 if w["col"] != 4 else 8
+    other = 4 if cfg["col_width"] != 4 else 8
     B.tune_cache_put([{"arch": arch, "kernel": "col_fresnel", "n": 512, "batch_class": 4, "width": other}])
     plan3 = api.Plan(path)
-    assert plan3.widths["col"] == other and plan2.widths == w
-    assert torch.equal(plan3.propagate(u0, seed=4), ref)
+    assert plan3.config["col_width"] == other and plan3.config["col_radix"] == 0 and plan2.config == cfg
     # forced: measured again
-    assert plan3.tune(force=True)["col"] in built(512)
-    assert next(e for e in api.tune_cache() if e["kernel"] == "col_fresnel")["us"][0] > 0
+    assert plan3.tune(force=True)["col_width"] in built(512)
+    assert next(e for e in api.tune_cache() if e["kernel"] == "col_fresnel")["configs"] > 0
     for p in (plan, plan2, plan3):
         p.close()
 
@@ -134,7 +198,8 @@ def test_batch_tune_keeps_results(api):
     kinds = {(e["kernel"], e["n"]) for e in api.tune_cache()}
     assert {("col_fresnel", n) for n in (256, 1024, 2048)} <= kinds
     assert {("synth", n) for n in (256, 1024, 2048)} <= kinds
-    assert torch.equal(batch.propagate(u_in, seed=9), ref)
+    # widths and occupancy hints keep the arithmetic; a tuned radix plan rounds differently
+    assert rel_l2(batch.propagate(u_in, seed=9).cpu().numpy(), ref.cpu().numpy()) < 1e-5
     batch.close()
 
 

@@ -1,6 +1,6 @@
-"""The strip-width tuning cache of the C-ABI library (host memory only: no
-GPU is touched): entries go in and come out by key, invalid ones are refused,
-and the JSON file form round-trips."""
+"""The launch-configuration tuning cache of the C-ABI library (host memory
+only: no GPU is touched): entries go in and come out by key, invalid ones are
+refused, and the JSON file form round-trips."""
 import json
 import os
 
@@ -19,29 +19,35 @@ def cache():
     api.tune_cache_clear()
 
 
-def entry(kernel="col_fresnel", n=1024, batch_class=7, width=8, arch="gfx950", us=(300.0, 240.0, 280.0)):
-    return {"arch": arch, "kernel": kernel, "n": n, "batch_class": batch_class, "width": width, "us": list(us)}
+def entry(kernel="col_fresnel", n=1024, batch_class=7, width=8, arch="gfx950", us=240.0, radix=0, waves=0,
+          us_default=300.0, configs=9):
+    return {"arch": arch, "kernel": kernel, "n": n, "batch_class": batch_class, "width": width, "radix": radix,
+            "waves": waves, "configs": configs, "us": us, "us_default": us_default}
 
 
 def test_put_get_in_key_order_and_replace(cache):
     assert cache.tune_cache() == []
-    es = [entry("synth", 1024, 6, 4, us=(87.0, 92.0, 126.0)), entry(), entry("col_angular", 256, 3, 16)]
+    es = [entry("synth", 1024, 6, 4, us=87.0), entry(), entry("col_angular", 256, 3, 16),
+          entry("row_fwd", 1024, 6, 0, waves=4, radix=0)]
     B.tune_cache_put(es)
     got = cache.tune_cache()
-    assert len(got) == 3
+    assert len(got) == 4
     # key order: arch, kernel, n, batch class
-    assert [(g["kernel"], g["n"]) for g in got] == [("col_fresnel", 1024), ("col_angular", 256), ("synth", 1024)]
+    assert [(g["kernel"], g["n"]) for g in got] == [("col_fresnel", 1024), ("col_angular", 256), ("synth", 1024),
+                                                   ("row_fwd", 1024)]
     for g in got:
         ref = next(e for e in es if e["kernel"] == g["kernel"])
-        assert g["width"] == ref["width"] and g["batch_class"] == ref["batch_class"] and g["arch"] == "gfx950"
-        assert g["us"] == pytest.approx(ref["us"])
+        for f in ("width", "batch_class", "radix", "waves", "configs"):
+            assert g[f] == ref[f]
+        assert g["arch"] == "gfx950"
+        assert g["us"] == pytest.approx(ref["us"]) and g["us_default"] == pytest.approx(ref["us_default"])
     # same key: replaced, not added
-    B.tune_cache_put([entry(width=4, us=(1.0, 2.0, 3.0))])
+    B.tune_cache_put([entry(width=4, radix=8, us=1.0)])
     got = cache.tune_cache()
-    assert len(got) == 3 and got[0]["width"] == 4
+    assert len(got) == 4 and (got[0]["width"], got[0]["radix"]) == (4, 8)
     # another architecture or batch class is another key
     B.tune_cache_put([entry(arch="gfx942"), entry(batch_class=5)])
-    assert len(cache.tune_cache()) == 5
+    assert len(cache.tune_cache()) == 6
 
 
 @pytest.mark.parametrize("bad,needle", [
@@ -51,6 +57,12 @@ def test_put_get_in_key_order_and_replace(cache):
     (dict(n=4096, width=4), "not built"),
     (dict(kernel=9), "unknown kernel"),
     (dict(batch_class=0), "batch class"),
+    (dict(radix=2), "not built"),             # second-pass radices 8 and 4 only
+    (dict(n=256, radix=8), "not built"),      # alternative plans from N = 512
+    (dict(waves=3), "not built"),             # column kernels take no occupancy hint
+    (dict(kernel="row_fwd", width=0, waves=5), "not built"),
+    (dict(kernel="row_bwd", n=128, width=0, waves=2), "not built"),
+    (dict(kernel="row_fwd", width=8, waves=3), "not built"),
 ])
 def test_invalid_entries_refused(cache, bad, needle):
     B.tune_cache_put([entry(batch_class=3)])
@@ -77,21 +89,24 @@ def test_widths_built_per_grid_size(cache):
 
 
 def test_json_round_trip(cache, tmp_path):
-    es = [entry(), entry("synth", 2048, 2, 4, us=(98.0, 129.0, 0.0)), entry("col_as_table", 64, 2, 16)]
+    es = [entry(), entry("synth", 2048, 2, 4, us=98.0, radix=8), entry("col_as_table", 64, 2, 16),
+          entry("row_bwd", 512, 3, 0, waves=2)]
     B.tune_cache_put(es)
     path = tmp_path / "tune.json"
     cache.tune_cache_save(str(path))
     doc = json.loads(path.read_text())
-    assert doc["format"] == "turpy-tune-cache" and doc["version"] == 1 and len(doc["entries"]) == 3
+    assert doc["format"] == "turpy-tune-cache" and doc["version"] == 2 and len(doc["entries"]) == 4
     before = cache.tune_cache()
     cache.tune_cache_clear()
     assert cache.tune_cache() == []
-    assert cache.tune_cache_load(str(path)) == 3
+    assert cache.tune_cache_load(str(path)) == 4
     assert cache.tune_cache() == before
     bad = tmp_path / "bad.json"
-    bad.write_text(json.dumps({"format": "other", "version": 1, "entries": []}))
-    with pytest.raises(ValueError):
-        cache.tune_cache_load(str(bad))
+    for doc in ({"format": "other", "version": 2, "entries": []},
+                {"format": "turpy-tune-cache", "version": 1, "entries": []}):  # the strip-width-only form
+        bad.write_text(json.dumps(doc))
+        with pytest.raises(ValueError):
+            cache.tune_cache_load(str(bad))
 
 
 def test_cache_file_from_environment(cache, tmp_path, monkeypatch):
