@@ -8,14 +8,16 @@ of the whole path over one batch:
 
   forward  (value): headline workload, 64 realizations x 8 fresh screens per
            step (t advances every step), screens synthesised inside the passes,
-           ensemble moments accumulated (turpy_propagate + turpy_stats);
+           ensemble moments taken inside the final row pass (turpy_propagate
+           on a plan bound to the moment sums);
   fwd+bwd: the same with screen-plane checkpoints (fields and the screens'
            column halves) and the adjoint (turpy_propagate_backward, dL/du_in
            of the shared source and dL/dphi);
   ar:      the N = 1024 autoregressive workload, one time step =
            turpy_evolve_propagate (the AR step of 8 screens x 16 pairs fused
-           into the propagation's screen synthesis) + turpy_stats (256
-           screen-steps); also timed as turpy_evolve + turpy_propagate;
+           into the propagation's screen synthesis, moments inside the final
+           row pass; 256 screen-steps); also timed as turpy_evolve +
+           turpy_propagate;
   plain:   the same physics one op per kernel: Philox normals (turpy_noise),
            torch elementwise ops and torch.fft for the screens and Eq. 1,
            forward and forward + backward (torch autograd).
@@ -82,8 +84,8 @@ def step_bytes(path, leg):
     # evolved and writes the scratch (the evolution fused into it)
     spec = 2 * p if leg == "ar" else 0
     out = {
-        # source row transform (1 plane in, 1 out) and the final inverse row pass
-        "row_plain": (2 + 2 * r) * plane,
+        # source row transform (1 plane in, 1 out)
+        "row_plain": 2 * plane,
         # column pass 0 diffracts the single shared source plane in place
         "col": (2 + 2 * r * m) * plane,
         # the first screen pass reads that one plane for every realization
@@ -91,7 +93,10 @@ def step_bytes(path, leg):
         "synth": m * (p + spec) * plane,
     }
     if leg in ("fwd", "ar"):
-        out["stats"] = r * plane + moments
+        # the final inverse row pass, with the moments taken inside it
+        out["row_moments"] = 2 * r * plane + moments
+    else:
+        out["row_plain"] += 2 * r * plane
     if leg == "fwdbwd":
         # first row pass (g in and out), M column passes on R planes, M screen
         # passes reading g, scratch and checkpoint and writing g and dL/dphi;
@@ -496,7 +501,8 @@ def main():
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     binding.lib()
-    fams = ["row_fwd", "row_bwd", "row_plain", "col", "synth", "sh", "evolve", "stats", "finalize", "copy", "sum"]
+    fams = ["row_fwd", "row_bwd", "row_plain", "row_moments", "col", "synth", "sh", "evolve", "stats", "finalize",
+            "copy", "sum"]
 
     if args.tune_cache and os.path.exists(args.tune_cache):
         api.tune_cache_load(args.tune_cache)
@@ -520,11 +526,12 @@ def main():
                          "screen_steps_per_step": ss_per_step, "launch_config": widths}}
 
     def fwd(i):
-        plan.propagate(u0, seed=w.seed, t=i, out=u_out)
-        moments.add(u_out)
+        plan.propagate(u0, seed=w.seed, t=i, out=u_out)  # moments taken inside
 
     if args.only in ("all", "fwd"):
+        plan.bind_moments(moments)
         sec, ktab, dom = measure(torch, fwd, args.steps, args.warmup, binding, fams, path, "fwd")
+        plan.bind_moments(None)
         result["value"] = ss_per_step / sec
         result["ms_per_step"] = 1e3 * sec
         result["kernels"] = ktab
@@ -545,10 +552,10 @@ def main():
         pas = path.with_(tf_kind=workloads.TF_ANGULAR_SPECTRUM)
         plan_as = api.Plan(pas)
         plan_as.tune()
+        plan_as.bind_moments(moments)
 
         def fwd_as(i):
             plan_as.propagate(u0, seed=w.seed, t=i, out=u_out)
-            moments.add(u_out)
 
         sec, ktab, dom = measure(torch, fwd_as, args.steps, args.warmup, binding, fams, pas, "fwd")
         result["fwd_angular_spectrum"] = {"value": ss_per_step / sec, "unit": "screen-steps/s",
@@ -598,17 +605,16 @@ def main():
         u3 = torch.from_numpy(w3.source_field().astype(np.complex64)).to(dev)
         o3 = torch.empty((p3.realizations, p3.n, p3.n), dtype=torch.complex64, device=dev)
         m3 = api.Moments(p3.n, p3.dx)
+        plan3.bind_moments(m3)  # the moments of every step, inside its final row pass
         ex = w3.extra
 
         def ar(i):
             # one AR time step: the evolution fused into the screen synthesis
             plan3.evolve_propagate(spec, w3.seed, i + 1, ex["alpha"], ex["shift_x"], ex["shift_y"], u_in=u3, out=o3)
-            m3.add(o3)
 
         def ar_two_calls(i):
             plan3.evolve(spec, w3.seed, i + 1, ex["alpha"], ex["shift_x"], ex["shift_y"])
             plan3.propagate(u3, spectra=spec, out=o3)
-            m3.add(o3)
 
         run_steps(torch, ar_two_calls, 0, 2)
         t0 = time.perf_counter()

@@ -223,6 +223,18 @@ turpy_status turpy_evolve_propagate(turpy_plan* plan, uint64_t seed, int64_t t, 
  * caller's. */
 turpy_status turpy_plan_bind_time(turpy_plan* plan, const void* dev_t);
 
+/* Ensemble moments taken inside the forward pass (Sec. 3.3).  With moments
+ * set (float [4][N][N] in device memory, the layout of turpy_stats), every
+ * forward call of this plan (turpy_propagate, turpy_evolve_propagate,
+ * turpy_propagate_static) also adds its R output fields to those sums, with
+ * the same bits as a turpy_stats(N, dx, R, u_out, moments, 0, 0, ...) call
+ * after it.  Where the pass ends with a plain inverse row transform (a
+ * distance after the last screen) the sums are taken inside that transform
+ * and the output planes are not read back; otherwise the moment kernel runs
+ * after it.  The caller keeps the realization count for the finalize call.
+ * NULL unbinds.  The pointer is kept; the memory stays the caller's. */
+turpy_status turpy_plan_bind_moments(turpy_plan* plan, float* moments);
+
 /* Bytes of the plan's AR state (see turpy_evolve). */
 turpy_status turpy_state_size(const turpy_plan* plan, size_t* bytes);
 
@@ -275,8 +287,11 @@ turpy_status turpy_propagate_backward_reversible(turpy_plan* plan, uint64_t seed
 /* Ensemble statistics of received fields (Sec. 3.2-3.3, Eq. S25; Sec. 4.1).
  *  If batch > 0: accumulate I = |u|^2 of u[batch][n][n] into
  *  moments float [4][n][n] = (sum I, its compensation, sum I^2, its
- *  compensation), Kahan-compensated, in batch order; zero `moments` before the
- *  first batch.
+ *  compensation), Kahan-compensated; zero `moments` before the first batch.
+ *  The batch is summed in C = clamp(256 / (n / 16), 4, 64) contiguous chunks,
+ *  chunk c holding entries [c batch / C, (c + 1) batch / C) in order, and the
+ *  compensated sums of the non-empty chunks join the stored ones in chunk
+ *  order: a fixed order for a given (n, batch), bitwise reproducible.
  *  If finalize != 0: with count = total realizations accumulated and
  *  m = sums / count, write si_map float [n][n] = m2/m1^2 - 1 (may be NULL)
  *  and summary double[8] (device):

@@ -87,6 +87,20 @@ class Plan:
         self._t_dev = t_dev  # kept alive while bound
         B.plan_bind_time(self.handle, _ptr(t_dev))
 
+    def bind_moments(self, moments):
+        """Take the ensemble moments inside every forward call (a Moments of
+        this plan's N on its device, or None to stop): each call adds its R
+        output fields, with the bits of moments.add(u_out), and counts them."""
+        if moments is not None:
+            if not isinstance(moments, Moments) or moments.n != self.n or moments.device != self.device:
+                raise ValueError("bind_moments: a Moments of the plan's grid size on its device")
+        self._moments = moments  # kept alive while bound
+        B.plan_bind_moments(self.handle, _ptr(moments.buf) if moments is not None else None)
+
+    def _counted(self):
+        if getattr(self, "_moments", None) is not None:
+            self._moments.count += self.r
+
     def workspace(self, op):
         size = B.workspace_size(self.handle, op)
         buf = self._ws.get(op)
@@ -209,6 +223,7 @@ class Plan:
         ws, size = self.workspace(B.OP_PROPAGATE)
         B.propagate(self.handle, seed, t, _ptr(u_in), stride, src, _ptr(sbuf), _ptr(u_out), _ptr(ck), _ptr(ws), size,
                     _stream())
+        self._counted()
         return (u_out, ck) if ck is not None else u_out
 
     def evolve_propagate(self, spectra, seed, t, alpha, shift_x=0.0, shift_y=0.0, u_in=None, checkpoints=False,
@@ -232,6 +247,7 @@ class Plan:
         ws, size = self.workspace(B.OP_PROPAGATE)
         B.evolve_propagate(self.handle, seed, t, alpha, shift_x, shift_y, _ptr(spectra), _ptr(u_in), stride,
                            _ptr(u_out), _ptr(ck), _ptr(ws), size, _stream())
+        self._counted()
         return (u_out, ck) if ck is not None else u_out
 
     def propagate_backward(self, grad_out, checkpoints, seed=0, t=0, screens=None, spectra=None, want_input=True,
@@ -437,7 +453,7 @@ class Moments:
 
     def __init__(self, n, dx, device=None):
         self.n, self.dx = n, dx
-        self.device = torch.device(device) if device is not None else torch.device("cuda")
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.buf = torch.zeros((4, n, n), dtype=torch.float32, device=self.device)
         self.count = 0
 

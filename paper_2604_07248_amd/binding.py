@@ -34,6 +34,7 @@ EXPORTS = [
     "turpy_batch_propagate", "turpy_batch_propagate_backward", "turpy_plan_tune", "turpy_plan_widths",
     "turpy_plan_set_widths", "turpy_tune_cache_get", "turpy_tune_cache_put", "turpy_tune_cache_clear",
     "turpy_batch_tune", "turpy_plan_config", "turpy_plan_set_config", "turpy_receiver_setup", "turpy_noise", "turpy_propagate_static", "turpy_checkpoint_size", "turpy_evolve_propagate",
+    "turpy_plan_bind_moments",
 ]
 
 
@@ -129,6 +130,7 @@ def lib():
         L.turpy_profile_read.argtypes = [c_char_p, POINTER(c_int64), POINTER(c_double)]
         L.turpy_state_size.argtypes = [c_void_p, POINTER(c_size_t)]
         L.turpy_plan_bind_time.argtypes = [c_void_p, c_void_p]
+        L.turpy_plan_bind_moments.argtypes = [c_void_p, c_void_p]
         L.turpy_batch_create.argtypes = [POINTER(c_void_p), POINTER(CPath), POINTER(c_int64), c_int32, c_uint32]
         L.turpy_batch_destroy.argtypes = [c_void_p]
         L.turpy_batch_bind_time.argtypes = [c_void_p, c_void_p]
@@ -221,6 +223,10 @@ def batch_propagate_backward(handle, seed, t, gout_ptr, ckpt_ptr, gin_ptr, gscre
 
 def plan_bind_time(handle, dev_ptr):
     check(lib().turpy_plan_bind_time(handle, dev_ptr))
+
+
+def plan_bind_moments(handle, moments_ptr):
+    check(lib().turpy_plan_bind_moments(handle, moments_ptr))
 
 
 def state_size(handle):

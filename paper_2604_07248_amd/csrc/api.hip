@@ -176,6 +176,7 @@ struct turpy_plan {
   float* d_sh_amp = nullptr;     // [M][3][2]
   float* d_amp_rad = nullptr;    // [M]
   const uint32_t* d_t = nullptr; // bound device time step (turpy_plan_bind_time), or NULL
+  float* d_moments = nullptr;    // bound moment sums [4][N][N] (turpy_plan_bind_moments), or NULL
   // strip widths of the column pass and the synthesis (0: built-in choice for n)
   int col_width = 0, synth_width = 0;
   // second-pass radix of their transforms (0: the default plan) and the
@@ -829,9 +830,24 @@ turpy_status propagate_impl(turpy_plan* pl, uint64_t seed, int64_t t, const void
     a.out = uout;
     a.in_spectral = 1;
     a.scale = inv_n;
-    TURPY_HIP(timed(row_family(a), st, [&] { return launch_row(n, a, pl->P, st); }), "propagate: final row pass");
-  } else if (M == 0) {
-    TURPY_HIP(timed("copy", st, [&] { return launch_copy(uin, u_in_stride, uout, plane, pl->R, st); }), "propagate: copy");
+    if (pl->d_moments)
+      TURPY_HIP(timed("row_moments", st, [&] { return launch_row_moments(n, a, pl->d_moments, st); }),
+                "propagate: final row pass with moments");
+    else
+      TURPY_HIP(timed(row_family(a), st, [&] { return launch_row(n, a, pl->P, st); }), "propagate: final row pass");
+  } else {
+    if (M == 0)
+      TURPY_HIP(timed("copy", st, [&] { return launch_copy(uin, u_in_stride, uout, plane, pl->R, st); }),
+                "propagate: copy");
+    if (pl->d_moments) {
+      // the output comes from a screen row pass or a copy: the sums read it back
+      StatsArgs a{};
+      a.u = uout;
+      a.batch = pl->R;
+      a.n = n;
+      a.moments = pl->d_moments;
+      TURPY_HIP(timed("stats", st, [&] { return launch_stats(a, st); }), "propagate: moments");
+    }
   }
   return TURPY_OK;
 }
@@ -1208,6 +1224,12 @@ turpy_status turpy_plan_bind_time(turpy_plan* pl, const void* dev_t) {
   if (!pl) return fail(TURPY_E_INVALID, "plan_bind_time: NULL plan");
   if (reinterpret_cast<uintptr_t>(dev_t) % 4 != 0) return fail(TURPY_E_INVALID, "plan_bind_time: misaligned");
   pl->d_t = static_cast<const uint32_t*>(dev_t);
+  return TURPY_OK;
+}
+
+turpy_status turpy_plan_bind_moments(turpy_plan* pl, float* moments) {
+  if (!pl) return fail(TURPY_E_INVALID, "plan_bind_moments: NULL plan");
+  pl->d_moments = moments;
   return TURPY_OK;
 }
 

@@ -862,32 +862,106 @@ __global__ __launch_bounds__(256) void stats_kernel(StatsArgs a) {
   if (p >= np) return;
   float s1 = a.moments[p], c1 = a.moments[np + p];
   float s2 = a.moments[2 * np + p], c2 = a.moments[3 * np + p];
-  auto add = [&](float2 u) {
-    const float i = u.x * u.x + u.y * u.y;
-    float y = i - c1;
-    float tt = s1 + y;
-    c1 = (tt - s1) - y;
-    s1 = tt;
-    y = i * i - c2;
-    tt = s2 + y;
-    c2 = (tt - s2) - y;
-    s2 = tt;
-  };
-  // U loads in flight per thread; the sums stay in batch order
-  constexpr int U = 16;
-  int64_t b = 0;
-  for (; b + U <= a.batch; b += U) {
-    float2 u[U];
+  const int C = moment_chunks(a.n);
+  for (int c = 0; c < C; ++c) {
+    const int64_t lo = c * a.batch / C, hi = (c + 1) * a.batch / C;
+    if (lo == hi) continue;
+    float ps1 = 0.0f, pc1 = 0.0f, ps2 = 0.0f, pc2 = 0.0f;
+    // U loads in flight per thread; the sums stay in realization order
+    constexpr int U = 16;
+    int64_t b = lo;
+    for (; b + U <= hi; b += U) {
+      float2 u[U];
 #pragma unroll
-    for (int q = 0; q < U; ++q) u[q] = ld_s<true>(a.u + (b + q) * np + p);
+      for (int q = 0; q < U; ++q) u[q] = ld_s<true>(a.u + (b + q) * np + p);
 #pragma unroll
-    for (int q = 0; q < U; ++q) add(u[q]);
+      for (int q = 0; q < U; ++q) moment_add(ps1, pc1, ps2, pc2, u[q]);
+    }
+    for (; b < hi; ++b) moment_add(ps1, pc1, ps2, pc2, ld_s<true>(a.u + b * np + p));
+    kahan_join(s1, c1, ps1, pc1);
+    kahan_join(s2, c2, ps2, pc2);
   }
-  for (; b < a.batch; ++b) add(ld_s<true>(a.u + b * np + p));
   a.moments[p] = s1;
   a.moments[np + p] = c1;
   a.moments[2 * np + p] = s2;
   a.moments[3 * np + p] = c2;
+}
+
+// ---------------------------------------------------------------------------
+// Final row pass with the ensemble moments (Sec. 3.3).  The inverse row
+// transform of each realization's spectral row is the output field: it is
+// stored and, still in registers, added into the per-pixel moment sums, so
+// the output planes are not read a second time.  A block is one row by C
+// chunks of realizations (moment_chunks): thread group c transforms the
+// realizations of chunk c in order into sums of its own, and the chunk sums
+// are joined into the stored ones in chunk order through LDS.  The field is
+// the plain final row pass's and the sums are the stats kernel's, bit for
+// bit.  Groups past the end of their chunk transform a valid row and keep
+// nothing, so every group passes the same barriers.
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ __launch_bounds__(moment_chunks(N) * (N / kE)) void row_moments_kernel(RowArgs a, float* moments) {
+  constexpr int T = N / kE;
+  constexpr int C = moment_chunks(N);
+  constexpr bool WV = T <= 64;  // each row's transform lives in one wavefront
+  static_assert(2 * N <= 2 * RowLds::words(N), "a chunk's partial sums fit in its transform's LDS");
+  __shared__ float2 smem[C * RowLds::words(N)];
+  __shared__ float2 tw_lds[N];
+  const int c = threadIdx.x / T;
+  const int t = threadIdx.x % T;
+  const RowLds lds{smem + c * RowLds::words(N)};
+  const float2* tw = stage_twiddles<N>(tw_lds, a.tw);
+  const size_t plane = static_cast<size_t>(N) * N;
+  const size_t row_off = static_cast<size_t>(blockIdx.x) * N;
+  const int64_t lo = c * a.R / C, hi = (c + 1) * a.R / C;
+  const int64_t iters = (a.R + C - 1) / C;
+
+  float s1[kE], c1[kE], s2[kE], c2[kE];
+#pragma unroll
+  for (int m = 0; m < kE; ++m) s1[m] = c1[m] = s2[m] = c2[m] = 0.0f;
+  for (int64_t i = 0; i < iters; ++i) {
+    const int64_t r = lo + i;
+    const bool live = r < hi;
+    const float2* src = a.in + (live ? r : a.R - 1) * a.in_stride + row_off;
+    float2 x[kE];
+#pragma unroll
+    for (int m = 0; m < kE; ++m) x[m] = (src + t)[T * m];
+    fft<N, kE, true, WV>(x, lds, t, tw);
+    if (a.scale != 1.0f) {
+#pragma unroll
+      for (int m = 0; m < kE; ++m) x[m] = c_scale(x[m], a.scale);
+    }
+    if (live) {
+      float2* dst = a.out + r * plane + row_off;
+#pragma unroll
+      for (int m = 0; m < kE; ++m) (dst + t)[T * m] = x[m];
+#pragma unroll
+      for (int m = 0; m < kE; ++m) moment_add(s1[m], c1[m], s2[m], c2[m], x[m]);
+    }
+  }
+
+  // non-empty chunks, bit q for chunk q (C <= 64)
+  uint64_t filled = 0;
+  for (int q = 0; q < C; ++q)
+    if (q * a.R / C != (q + 1) * a.R / C) filled |= uint64_t(1) << q;
+  float* part = reinterpret_cast<float*>(smem);  // [C][2][N]: one moment's s and c per chunk
+  for (int k = 0; k < 2; ++k) {
+    __syncthreads();  // the transforms' (or the last round's) LDS reads are done
+#pragma unroll
+    for (int m = 0; m < kE; ++m) {
+      part[(2 * c) * N + t + T * m] = k ? s2[m] : s1[m];
+      part[(2 * c + 1) * N + t + T * m] = k ? c2[m] : c1[m];
+    }
+    __syncthreads();
+    for (int p = threadIdx.x; p < N; p += C * T) {
+      float* ms = moments + static_cast<size_t>(2 * k) * plane + row_off + p;
+      float s = ms[0], cc = ms[plane];
+      for (int q = 0; q < C; ++q)
+        if (filled >> q & 1) kahan_join(s, cc, part[(2 * q) * N + p], part[(2 * q + 1) * N + p]);
+      ms[0] = s;
+      ms[plane] = cc;
+    }
+  }
 }
 
 template <int NT>
@@ -1245,6 +1319,14 @@ hipError_t synth_launch(const SynthArgs& a, hipStream_t s) {
 
 hipError_t launch_row(int n, const RowArgs& a, int64_t pairs, hipStream_t s) {
   TURPY_DISPATCH_N(n, row_launch, a, pairs, s)
+}
+template <int N>
+hipError_t row_moments_launch(const RowArgs& a, float* moments, hipStream_t s) {
+  hipLaunchKernelGGL(row_moments_kernel<N>, dim3(N), dim3(moment_chunks(N) * (N / kE)), 0, s, a, moments);
+  return hipGetLastError();
+}
+hipError_t launch_row_moments(int n, const RowArgs& a, float* moments, hipStream_t s) {
+  TURPY_DISPATCH_N(n, row_moments_launch, a, moments, s)
 }
 hipError_t launch_col(int n, const ColArgs& a, hipStream_t s) { TURPY_DISPATCH_N(n, col_launch, a, s) }
 hipError_t launch_synth(int n, const SynthArgs& a, hipStream_t s) { TURPY_DISPATCH_N(n, synth_launch, a, s) }

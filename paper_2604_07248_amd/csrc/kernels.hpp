@@ -166,6 +166,9 @@ struct RecvArgs {
 };
 
 hipError_t launch_row(int n, const RowArgs& a, int64_t pairs, hipStream_t s);
+// The plain final row pass (in spectral, out real, no screen, no pre/post
+// factor) with the ensemble moments added into moments [4][n][n].
+hipError_t launch_row_moments(int n, const RowArgs& a, float* moments, hipStream_t s);
 hipError_t launch_col(int n, const ColArgs& a, hipStream_t s);
 hipError_t launch_synth(int n, const SynthArgs& a, hipStream_t s);
 hipError_t launch_sh(const ShArgs& a, hipStream_t s);

@@ -41,6 +41,16 @@ constexpr bool strip_fits_rt(int n, int k) {
          (static_cast<long>(k) * n + 2L * n) * 8 <= 160L * 1024;
 }
 
+// Ensemble moments: the R realizations are summed in C contiguous chunks,
+// chunk c holding realizations [c R / C, (c + 1) R / C), and the compensated
+// sums of the non-empty chunks are joined into the stored ones in chunk order.
+// C = 256 / (N / 16) clamped to [4, 64] depends on N alone: a block of the
+// fused final row pass (one row, C chunks of N / 16 threads) then has 256
+// threads for N = 64..1024.
+constexpr int moment_chunks(int n) {
+  return (256 / (n / kE)) < 4 ? 4 : ((256 / (n / kE)) > 64 ? 64 : 256 / (n / kE));
+}
+
 // Row-pair pass: each half of a block (whole waves for N >= 64) carries one
 // realization of a pair over `pair_rows` rows.
 template <int N>
