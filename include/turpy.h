@@ -45,7 +45,8 @@ typedef enum {
   TURPY_E_ALIASING = 3,     /* a step exceeds the transfer-function sampling limit (Sec. 2.4, Eq. 7) */
   TURPY_E_WORKSPACE = 4,    /* workspace NULL or smaller than turpy_workspace_size() */
   TURPY_E_HIP = 5,          /* a HIP runtime call failed (message has the HIP error) */
-  TURPY_E_CAPACITY = 6      /* a host output array is smaller than the result */
+  TURPY_E_CAPACITY = 6,     /* a host output array is smaller than the result */
+  TURPY_E_NONFINITE = 7     /* TURPY_CHECK_FINITE: an output holds a NaN or an infinity */
 } turpy_status;
 
 typedef enum { TURPY_TF_FRESNEL = 0, TURPY_TF_ANGULAR_SPECTRUM = 1 } turpy_tf_kind;
@@ -63,6 +64,12 @@ typedef enum {
 #define TURPY_SCREEN_CHECKPOINTS 2u  /* checkpoints also keep each screen's column half, so that the
                                         adjoint reads the screens instead of synthesising them again
                                         (turpy_checkpoint_size) */
+#define TURPY_CHECK_FINITE 4u        /* every call of the plan counts the NaN and infinite values in
+                                        its outputs (fields, checkpoints, gradients, screens) and
+                                        returns TURPY_E_NONFINITE, naming the output, when there are
+                                        any.  The check synchronises the stream, so such calls cannot
+                                        be captured in a graph (TURPY_E_INVALID on a capturing
+                                        stream); the outputs are written either way */
 
 /* One propagation path (Sec. 2.1, Fig. 1A inputs). */
 typedef struct turpy_path {
@@ -528,9 +535,9 @@ turpy_status turpy_batch_tune(turpy_batch* batch, uint32_t flags, void* ws, size
 /* Per-kernel timing for benchmarking.  turpy_profile(1) clears the record and
  * starts bracketing every kernel the library enqueues with a pair of HIP events
  * on that kernel's stream; turpy_profile(0) stops recording.  Kernel families:
- * "row_fwd", "row_bwd", "row_plain", "col", "synth", "sh", "evolve", "stats",
- * "finalize", "copy", "sum", "noise", "recv_row", "recv_col", "recv_col_grad", "recv_row_grad",
- * "recv_reduce".  turpy_profile_read waits for the recorded events and
+ * "row_fwd", "row_bwd", "row_plain", "row_moments", "col", "synth", "sh", "evolve",
+ * "stats", "finalize", "copy", "sum", "noise", "nonfinite", "recv_row", "recv_col",
+ * "recv_col_grad", "recv_row_grad", "recv_reduce".  turpy_profile_read waits for the recorded events and
  * returns the launch count and summed duration (ms) of one family (zero when it
  * never ran).  turpy_profile_only(family) restricts the bracketing to one
  * family (the others launch with no events around them, so that timing one
@@ -540,6 +547,15 @@ turpy_status turpy_batch_tune(turpy_batch* batch, uint32_t flags, void* ws, size
 turpy_status turpy_profile(int32_t enable);
 turpy_status turpy_profile_only(const char* family);
 turpy_status turpy_profile_read(const char* family, int64_t* launches, double* total_ms);
+
+/* Launch-failure injection, for testing error handling from the host: with
+ * k > 0, the k-th kernel launch the library enqueues from now on (any plan,
+ * batch or thread; counting from 1) is not enqueued, and the entry point that
+ * enqueues it returns TURPY_E_HIP with a message saying the failure was
+ * injected, exactly as it would for a failed launch.  The countdown then
+ * disarms; k = 0 disarms it at once.  The outputs of the failed call (and an
+ * AR state it was updating) are undefined; plans and batches stay usable. */
+turpy_status turpy_debug_fail_launch(int64_t k);
 
 #ifdef __cplusplus
 }

@@ -12,12 +12,13 @@ from ctypes import POINTER, c_char_p, c_double, c_float, c_int32, c_int64, c_siz
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libturpy.so")
 
-OK, E_INVALID, E_UNSUPPORTED, E_ALIASING, E_WORKSPACE, E_HIP, E_CAPACITY = range(7)
+OK, E_INVALID, E_UNSUPPORTED, E_ALIASING, E_WORKSPACE, E_HIP, E_CAPACITY, E_NONFINITE = range(8)
 CN2_UNIFORM, CN2_HUFNAGEL_VALLEY, CN2_TABLE = 0, 1, 2
 TF_FRESNEL, TF_ANGULAR_SPECTRUM = 0, 1
 SCREENS_SYNTH, SCREENS_MATERIALIZED, SCREENS_SPECTRA = 0, 1, 2
 ALLOW_ALIASING = 1
 SCREEN_CHECKPOINTS = 2
+CHECK_FINITE = 4
 OP_SCREEN_GENERATE, OP_PROPAGATE, OP_PROPAGATE_BACKWARD, OP_EVOLVE, OP_PROPAGATE_BACKWARD_REVERSIBLE, OP_TUNE = range(6)
 TUNE_COL_FRESNEL, TUNE_COL_ANGULAR, TUNE_COL_AS_TABLE, TUNE_SYNTH, TUNE_ROW_FWD, TUNE_ROW_BWD = range(6)
 TUNE_KERNELS = ("col_fresnel", "col_angular", "col_as_table", "synth", "row_fwd", "row_bwd")
@@ -34,7 +35,7 @@ EXPORTS = [
     "turpy_batch_propagate", "turpy_batch_propagate_backward", "turpy_plan_tune", "turpy_plan_widths",
     "turpy_plan_set_widths", "turpy_tune_cache_get", "turpy_tune_cache_put", "turpy_tune_cache_clear",
     "turpy_batch_tune", "turpy_plan_config", "turpy_plan_set_config", "turpy_receiver_setup", "turpy_noise", "turpy_propagate_static", "turpy_checkpoint_size", "turpy_evolve_propagate",
-    "turpy_plan_bind_moments",
+    "turpy_plan_bind_moments", "turpy_debug_fail_launch",
 ]
 
 
@@ -131,6 +132,7 @@ def lib():
         L.turpy_state_size.argtypes = [c_void_p, POINTER(c_size_t)]
         L.turpy_plan_bind_time.argtypes = [c_void_p, c_void_p]
         L.turpy_plan_bind_moments.argtypes = [c_void_p, c_void_p]
+        L.turpy_debug_fail_launch.argtypes = [c_int64]
         L.turpy_batch_create.argtypes = [POINTER(c_void_p), POINTER(CPath), POINTER(c_int64), c_int32, c_uint32]
         L.turpy_batch_destroy.argtypes = [c_void_p]
         L.turpy_batch_bind_time.argtypes = [c_void_p, c_void_p]
@@ -227,6 +229,10 @@ def plan_bind_time(handle, dev_ptr):
 
 def plan_bind_moments(handle, moments_ptr):
     check(lib().turpy_plan_bind_moments(handle, moments_ptr))
+
+
+def debug_fail_launch(k):
+    check(lib().turpy_debug_fail_launch(k))
 
 
 def state_size(handle):

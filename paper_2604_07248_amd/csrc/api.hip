@@ -1,13 +1,16 @@
 // Host runtime of the C ABI declared in include/turpy.h: validation, plans
 // with FP64-generated tables, workspace layout and the pass schedule of each
 // entry point.  Every kernel is enqueued on the caller's stream; nothing here
-// synchronises except plan creation / destruction (table upload / free).
+// synchronises except plan creation / destruction (table upload / free), the
+// tuner and the output checks of TURPY_CHECK_FINITE plans.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <initializer_list>
 #include <map>
 #include <mutex>
 #include <string>
@@ -22,33 +25,29 @@ using namespace turpy;
 
 namespace {
 
-thread_local std::string g_last_error;
-
 turpy_status fail(turpy_status st, const char* fmt, ...) {
-  char buf[512];
   va_list ap;
   va_start(ap, fmt);
-  std::vsnprintf(buf, sizeof(buf), fmt, ap);
+  const turpy_status r = turpy::vreport(st, fmt, ap);
   va_end(ap);
-  g_last_error = buf;
-  return st;
+  return r;
 }
 
 }  // namespace
 
-turpy_status turpy::report(turpy_status st, const char* fmt, ...) {
-  char buf[512];
-  va_list ap;
-  va_start(ap, fmt);
-  std::vsnprintf(buf, sizeof(buf), fmt, ap);
-  va_end(ap);
-  g_last_error = buf;
-  return st;
-}
-
 namespace {
 
+// Launch-failure injection (turpy_debug_fail_launch): launches left before
+// the one that fails, 0 when disarmed; g_injected marks a failure that came
+// from it, for the message.
+std::atomic<int64_t> g_fail_countdown{0};
+thread_local bool g_injected = false;
+
 turpy_status hip_fail(hipError_t e, const char* where) {
+  if (g_injected) {
+    g_injected = false;
+    return fail(TURPY_E_HIP, "%s: launch failure injected by turpy_debug_fail_launch", where);
+  }
   return fail(TURPY_E_HIP, "%s: %s", where, hipGetErrorString(e));
 }
 
@@ -110,6 +109,10 @@ Profiler g_prof;
 // Launch `fn` (returning hipError_t) bracketed by events when profiling is on.
 template <class Fn>
 hipError_t timed(const char* family, hipStream_t st, Fn&& fn) {
+  if (g_fail_countdown.load(std::memory_order_relaxed) > 0 && g_fail_countdown.fetch_sub(1) == 1) {
+    g_injected = true;
+    return hipErrorUnknown;
+  }
   if (!g_prof.on || (!g_prof.only.empty() && g_prof.only != family)) return fn();
   EventPair e = g_prof.take();
   (void)hipEventRecord(e.start, st);
@@ -177,6 +180,9 @@ struct turpy_plan {
   float* d_amp_rad = nullptr;    // [M]
   const uint32_t* d_t = nullptr; // bound device time step (turpy_plan_bind_time), or NULL
   float* d_moments = nullptr;    // bound moment sums [4][N][N] (turpy_plan_bind_moments), or NULL
+  // TURPY_CHECK_FINITE: non-finite count on the device and its pinned host copy
+  unsigned long long* d_nonfinite = nullptr;
+  unsigned long long* h_nonfinite = nullptr;
   // strip widths of the column pass and the synthesis (0: built-in choice for n)
   int col_width = 0, synth_width = 0;
   // second-pass radix of their transforms (0: the default plan) and the
@@ -209,48 +215,12 @@ extern "C" {
 
 const char* turpy_version(void) { return "turpy-mi355x 0.1 (gfx950)"; }
 
-const char* turpy_last_error(void) { return g_last_error.c_str(); }
 
 turpy_status turpy_plan_create(turpy_plan** out, const turpy_path* p, uint32_t flags) {
   if (!out || !p) return fail(TURPY_E_INVALID, "plan_create: NULL argument");
   *out = nullptr;
-  if (flags & ~(TURPY_ALLOW_ALIASING | TURPY_SCREEN_CHECKPOINTS))
-    return fail(TURPY_E_INVALID, "plan_create: unknown flags 0x%x", flags);
-  if (!pow2(p->n)) return fail(TURPY_E_INVALID, "plan_create: n=%d is not a power of two", p->n);
-  if (p->n < 16 || p->n > 2048) return fail(TURPY_E_UNSUPPORTED, "plan_create: n=%d outside 16..2048", p->n);
-  if (p->num_screens < 0) return fail(TURPY_E_INVALID, "plan_create: num_screens < 0");
-  if (p->num_screens > (1 << 20)) return fail(TURPY_E_UNSUPPORTED, "plan_create: num_screens too large");
-  if (!(p->dx > 0) || !std::isfinite(p->dx)) return fail(TURPY_E_INVALID, "plan_create: dx must be > 0");
-  if (!(p->wavelength > 0) || !std::isfinite(p->wavelength))
-    return fail(TURPY_E_INVALID, "plan_create: wavelength must be > 0");
-  if (!(p->n0 > 0) || !std::isfinite(p->n0)) return fail(TURPY_E_INVALID, "plan_create: n0 must be > 0");
-  if (!p->dz) return fail(TURPY_E_INVALID, "plan_create: dz is NULL");
-  if (p->num_screens > 0 && !p->cn2dz) return fail(TURPY_E_INVALID, "plan_create: cn2dz is NULL");
-  if (p->sh_levels < 0 || p->sh_levels > 3)
-    return fail(TURPY_E_UNSUPPORTED, "plan_create: sh_levels=%d outside 0..3", p->sh_levels);
-  if (p->tf_kind != TURPY_TF_FRESNEL && p->tf_kind != TURPY_TF_ANGULAR_SPECTRUM)
-    return fail(TURPY_E_INVALID, "plan_create: unknown tf_kind %d", p->tf_kind);
-  if (p->inner_scale_conv != 0 && p->inner_scale_conv != 1)
-    return fail(TURPY_E_INVALID, "plan_create: inner_scale_conv must be 0 or 1");
-  if (p->realizations < 1 || p->realizations > (int64_t(1) << 31))
-    return fail(TURPY_E_INVALID, "plan_create: realizations=%lld out of range", (long long)p->realizations);
-  if (std::isnan(p->l0) || std::isnan(p->L0)) return fail(TURPY_E_INVALID, "plan_create: l0/L0 is NaN");
-  if (p->psd_alpha != 0.0 && !(p->psd_alpha > 2.0 && p->psd_alpha < 6.0))
-    return fail(TURPY_E_INVALID, "plan_create: psd_alpha=%g outside (2, 6) (0 selects 11/3)", p->psd_alpha);
+  if (turpy_status s_ = turpy::validate_path(p, flags)) return s_;
   const int M = p->num_screens, n = p->n;
-  const double limit = n * p->dx * p->dx * p->n0 / p->wavelength;  // Eq. 7 at the Nyquist frequency
-  for (int i = 0; i <= M; ++i) {
-    const double d = p->dz[i];
-    if (!(d >= 0) || !std::isfinite(d)) return fail(TURPY_E_INVALID, "plan_create: dz[%d] must be >= 0", i);
-    if (i > 0 && i < M && d == 0)
-      return fail(TURPY_E_UNSUPPORTED, "plan_create: dz[%d] = 0 between two screens (merge them)", i);
-    if (d > limit && !(flags & TURPY_ALLOW_ALIASING))
-      return fail(TURPY_E_ALIASING, "plan_create: dz[%d] = %g m exceeds the sampling limit N dx^2 n0/lambda = %g m",
-                  i, d, limit);
-  }
-  for (int i = 0; i < M; ++i)
-    if (!(p->cn2dz[i] >= 0) || !std::isfinite(p->cn2dz[i]))
-      return fail(TURPY_E_INVALID, "plan_create: cn2dz[%d] must be >= 0", i);
 
   turpy_plan* pl = new turpy_plan();
   (void)hipGetDevice(&pl->device);
@@ -387,6 +357,10 @@ turpy_status turpy_plan_create(turpy_plan** out, const turpy_path* p, uint32_t f
   std::vector<float> amp_rad = pl->amp_rad;
   if (amp_rad.empty()) amp_rad.push_back(0.0f);
   if (e == hipSuccess) e = upload(&pl->d_amp_rad, amp_rad.data(), amp_rad.size() * sizeof(float));
+  if (e == hipSuccess && (flags & TURPY_CHECK_FINITE)) {
+    e = hipMalloc(reinterpret_cast<void**>(&pl->d_nonfinite), sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&pl->h_nonfinite), sizeof(unsigned long long));
+  }
   if (e != hipSuccess) {
     turpy_plan_destroy(pl);
     return hip_fail(e, "plan_create: table upload");
@@ -411,6 +385,8 @@ turpy_status turpy_plan_destroy(turpy_plan* pl) {
   (void)hipFree(pl->d_sh_phasor);
   (void)hipFree(pl->d_sh_amp);
   (void)hipFree(pl->d_amp_rad);
+  (void)hipFree(pl->d_nonfinite);
+  if (pl->h_nonfinite) (void)hipHostFree(pl->h_nonfinite);
   delete pl;
   return TURPY_OK;
 }
@@ -642,6 +618,43 @@ turpy_status check_device(const turpy_plan* pl) {
 
 constexpr int64_t kRecvChunks = 16;
 
+// TURPY_CHECK_FINITE: its checks synchronise, so a checked call refuses a
+// capturing stream before it enqueues anything.
+turpy_status check_capture(const turpy_plan* pl, hipStream_t st, const char* where) {
+  if (!pl->d_nonfinite) return TURPY_OK;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  TURPY_HIP(hipStreamIsCapturing(st, &cs), where);
+  if (cs != hipStreamCaptureStatusNone)
+    return fail(TURPY_E_INVALID, "%s: a TURPY_CHECK_FINITE plan synchronises; not on a capturing stream", where);
+  return TURPY_OK;
+}
+
+// One output of a call: `floats` FP32 words at p (complex values count two).
+struct Output {
+  const void* p;
+  int64_t floats;
+  const char* name;
+};
+
+// TURPY_CHECK_FINITE: count the NaN and infinite values of each output, wait
+// for the count, and report the first output that has any.
+turpy_status check_outputs(const turpy_plan* pl, hipStream_t st, const char* where, std::initializer_list<Output> outs) {
+  if (!pl->d_nonfinite) return TURPY_OK;
+  for (const Output& o : outs) {
+    if (!o.p || o.floats <= 0) continue;
+    TURPY_HIP(timed("nonfinite", st, [&] {
+                return launch_nonfinite(static_cast<const float*>(o.p), o.floats, pl->d_nonfinite, st);
+              }),
+              where);
+    TURPY_HIP(hipMemcpyAsync(pl->h_nonfinite, pl->d_nonfinite, sizeof(unsigned long long), hipMemcpyDeviceToHost, st),
+              where);
+    TURPY_HIP(hipStreamSynchronize(st), where);
+    if (*pl->h_nonfinite)
+      return fail(TURPY_E_NONFINITE, "%s: %llu non-finite values in %s", where, *pl->h_nonfinite, o.name);
+  }
+  return TURPY_OK;
+}
+
 turpy_status check_receiver_shape(int32_t n, int64_t batch) {
   if (!pow2(n)) return fail(TURPY_E_INVALID, "receiver: n=%d is not a power of two", n);
   if (n < 16 || n > 2048) return fail(TURPY_E_UNSUPPORTED, "receiver: n=%d outside 16..2048", n);
@@ -710,6 +723,7 @@ turpy_status turpy_screen_generate(turpy_plan* pl, uint64_t seed, int64_t t, flo
   if (!ws || ws_bytes < pl->ws_forward())
     return fail(TURPY_E_WORKSPACE, "screen_generate: workspace %zu < %zu bytes", ws_bytes, pl->ws_forward());
   hipStream_t st = static_cast<hipStream_t>(stream);
+  if (turpy_status s_ = check_capture(pl, st, "screen_generate")) return s_;
   const Ws w = carve(pl, ws);
   if (pl->sh_levels > 0) TURPY_HIP(enqueue_sh(pl, seed, static_cast<uint32_t>(t), w, st), "screen_generate: sh");
   for (int s = 0; s < pl->M; ++s) {
@@ -721,7 +735,8 @@ turpy_status turpy_screen_generate(turpy_plan* pl, uint64_t seed, int64_t t, flo
     a.phase_out = screens;
     TURPY_HIP(timed(row_family(a), st, [&] { return launch_row(pl->n, a, pl->P, st); }), "screen_generate: row");
   }
-  return TURPY_OK;
+  return check_outputs(pl, st, "screen_generate",
+                       {{screens, pl->R * pl->M * static_cast<int64_t>(pl->n) * pl->n, "screens"}});
 }
 
 }  // extern "C"
@@ -745,6 +760,7 @@ turpy_status propagate_impl(turpy_plan* pl, uint64_t seed, int64_t t, const void
   if (!ws || ws_bytes < pl->ws_forward())
     return fail(TURPY_E_WORKSPACE, "propagate: workspace %zu < %zu bytes", ws_bytes, pl->ws_forward());
   hipStream_t st = static_cast<hipStream_t>(stream);
+  if (turpy_status s_ = check_capture(pl, st, "propagate")) return s_;
   Ws w = carve(pl, ws);
   keep_screens(pl, checkpoints, src, &w);
   const int n = pl->n, M = pl->M;
@@ -849,7 +865,12 @@ turpy_status propagate_impl(turpy_plan* pl, uint64_t seed, int64_t t, const void
       TURPY_HIP(timed("stats", st, [&] { return launch_stats(a, st); }), "propagate: moments");
     }
   }
-  return TURPY_OK;
+  const int64_t fields = 2 * pl->R * plane;
+  return check_outputs(pl, st, "propagate",
+                       {{u_out, fields, "u_out"},
+                        {checkpoints, fields * M, "checkpoints"},
+                        {ev ? screens_or_spectra : nullptr, 2 * pl->P * M * plane, "the AR state"},
+                        {pl->d_moments, 4 * plane, "the bound moments"}});
 }
 
 }  // namespace
@@ -877,6 +898,7 @@ turpy_status turpy_evolve_propagate(turpy_plan* pl, uint64_t seed, int64_t t, do
   if (!ws || ws_bytes < pl->ws_forward())
     return fail(TURPY_E_WORKSPACE, "evolve_propagate: workspace %zu < %zu bytes", ws_bytes, pl->ws_forward());
   hipStream_t st = static_cast<hipStream_t>(stream);
+  if (turpy_status s_ = check_capture(pl, st, "evolve_propagate")) return s_;
   if (pl->sh_levels > 0 && pl->M > 0) {
     // the subharmonic coefficients: the same translation and blend at their frequencies
     ShArgs b = sh_args(pl, seed, static_cast<uint32_t>(t), state_sh(pl, state));
@@ -909,10 +931,10 @@ turpy_status turpy_propagate_static(turpy_plan* pl, uint64_t seed, int64_t t, co
                          kStaticScratchBytes, stream);
 }
 
-turpy_status turpy_propagate_backward(turpy_plan* pl, uint64_t seed, int64_t t, const void* grad_u_out,
-                                      const void* checkpoints, int32_t src, const void* screens_or_spectra,
-                                      void* grad_u_in, int64_t grad_u_in_stride, float* grad_screens, void* ws,
-                                      size_t ws_bytes, void* stream) {
+static turpy_status backward_checkpointed(turpy_plan* pl, uint64_t seed, int64_t t, const void* grad_u_out,
+                                          const void* checkpoints, int32_t src, const void* screens_or_spectra,
+                                          void* grad_u_in, int64_t grad_u_in_stride, float* grad_screens, void* ws,
+                                          size_t ws_bytes, void* stream) {
   if (!pl || !grad_u_out) return fail(TURPY_E_INVALID, "propagate_backward: NULL argument");
   if (turpy_status s_ = check_t(t)) return s_;
   if (turpy_status s_ = check_device(pl)) return s_;
@@ -1030,10 +1052,10 @@ turpy_status turpy_propagate_backward(turpy_plan* pl, uint64_t seed, int64_t t, 
   return TURPY_OK;
 }
 
-turpy_status turpy_propagate_backward_reversible(turpy_plan* pl, uint64_t seed, int64_t t, const void* grad_u_out,
-                                                 const void* u_out, int32_t src, const void* screens_or_spectra,
-                                                 void* grad_u_in, int64_t grad_u_in_stride, float* grad_screens,
-                                                 void* ws, size_t ws_bytes, void* stream) {
+static turpy_status backward_reversible(turpy_plan* pl, uint64_t seed, int64_t t, const void* grad_u_out,
+                                        const void* u_out, int32_t src, const void* screens_or_spectra,
+                                        void* grad_u_in, int64_t grad_u_in_stride, float* grad_screens, void* ws,
+                                        size_t ws_bytes, void* stream) {
   if (!pl || !grad_u_out) return fail(TURPY_E_INVALID, "propagate_backward_reversible: NULL argument");
   if (turpy_status s_ = check_t(t)) return s_;
   if (turpy_status s_ = check_device(pl)) return s_;
@@ -1148,6 +1170,43 @@ turpy_status turpy_propagate_backward_reversible(turpy_plan* pl, uint64_t seed, 
               "propagate_backward_reversible: last row pass");
   }
   return TURPY_OK;
+}
+
+// TURPY_CHECK_FINITE around an adjoint: no capturing stream, then the
+// gradients checked.
+extern "C++" template <class Body>
+static turpy_status checked_backward(turpy_plan* pl, void* stream, const char* where, void* grad_u_in,
+                                     int64_t grad_u_in_stride, float* grad_screens, Body&& body) {
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (pl)
+    if (turpy_status s_ = check_capture(pl, st, where)) return s_;
+  if (turpy_status s_ = body()) return s_;
+  const int64_t plane = static_cast<int64_t>(pl->n) * pl->n;
+  return check_outputs(pl, st, where,
+                       {{grad_u_in, 2 * (grad_u_in_stride ? pl->R : 1) * plane, "grad_u_in"},
+                        {grad_screens, pl->R * pl->M * plane, "grad_screens"}});
+}
+
+turpy_status turpy_propagate_backward(turpy_plan* pl, uint64_t seed, int64_t t, const void* grad_u_out,
+                                      const void* checkpoints, int32_t src, const void* screens_or_spectra,
+                                      void* grad_u_in, int64_t grad_u_in_stride, float* grad_screens, void* ws,
+                                      size_t ws_bytes, void* stream) {
+  return checked_backward(pl, stream, "propagate_backward", grad_u_in, grad_u_in_stride, grad_screens, [&] {
+    return backward_checkpointed(pl, seed, t, grad_u_out, checkpoints, src, screens_or_spectra, grad_u_in,
+                                 grad_u_in_stride, grad_screens, ws, ws_bytes, stream);
+  });
+}
+
+turpy_status turpy_propagate_backward_reversible(turpy_plan* pl, uint64_t seed, int64_t t, const void* grad_u_out,
+                                                 const void* u_out, int32_t src, const void* screens_or_spectra,
+                                                 void* grad_u_in, int64_t grad_u_in_stride, float* grad_screens,
+                                                 void* ws, size_t ws_bytes, void* stream) {
+  return checked_backward(pl, stream, "propagate_backward_reversible", grad_u_in, grad_u_in_stride, grad_screens,
+                          [&] {
+                            return backward_reversible(pl, seed, t, grad_u_out, u_out, src, screens_or_spectra,
+                                                       grad_u_in, grad_u_in_stride, grad_screens, ws, ws_bytes,
+                                                       stream);
+                          });
 }
 
 turpy_status turpy_evolve(turpy_plan* pl, uint64_t seed, int64_t t, double alpha, double shift_x, double shift_y,
@@ -1272,6 +1331,13 @@ turpy_status turpy_profile(int32_t enable) {
 
 turpy_status turpy_profile_only(const char* family) {
   g_prof.only = family ? family : "";
+  return TURPY_OK;
+}
+
+turpy_status turpy_debug_fail_launch(int64_t k) {
+  if (k < 0) return fail(TURPY_E_INVALID, "debug_fail_launch: k < 0");
+  g_injected = false;
+  g_fail_countdown.store(k);
   return TURPY_OK;
 }
 

@@ -17,6 +17,8 @@
 // Strided accesses are written (p + t)[T * m]: one address per row or column
 // for the thread, then compile-time offsets per element (the index form
 // p[t + T * m] made the compiler build a 64-bit address per element).
+#include <algorithm>
+
 #include "fft.hpp"
 #include "kernels.hpp"
 #include "layout.hpp"
@@ -964,6 +966,22 @@ __global__ __launch_bounds__(moment_chunks(N) * (N / kE)) void row_moments_kerne
   }
 }
 
+// ---------------------------------------------------------------------------
+// Output check of TURPY_CHECK_FINITE plans: the number of NaN and infinite
+// values among `count` floats, added to *counter (cleared first by the
+// one-thread kernel before it).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1) void clear_counter_kernel(unsigned long long* counter) { *counter = 0; }
+
+__global__ __launch_bounds__(256) void nonfinite_kernel(const float* x, int64_t count, unsigned long long* counter) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  unsigned bad = 0;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < count; i += stride)
+    bad += __builtin_isfinite(x[i]) ? 0u : 1u;
+  for (int off = 32; off > 0; off >>= 1) bad += __shfl_xor(bad, off);
+  if ((threadIdx.x & 63) == 0 && bad) atomicAdd(counter, static_cast<unsigned long long>(bad));
+}
+
 template <int NT>
 __device__ double block_sum(double v, double* red) {
   red[threadIdx.x] = v;
@@ -1345,6 +1363,13 @@ hipError_t launch_evolve(const EvolveArgs& a, hipStream_t s) {
 hipError_t launch_stats(const StatsArgs& a, hipStream_t s) {
   const int64_t np = static_cast<int64_t>(a.n) * a.n;
   hipLaunchKernelGGL(stats_kernel, dim3(static_cast<uint32_t>((np + 255) / 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_nonfinite(const float* x, int64_t count, unsigned long long* counter, hipStream_t s) {
+  hipLaunchKernelGGL(clear_counter_kernel, dim3(1), dim3(1), 0, s, counter);
+  const int64_t blocks = std::min<int64_t>((count + 255) / 256, 8192);
+  hipLaunchKernelGGL(nonfinite_kernel, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, s, x, count, counter);
   return hipGetLastError();
 }
 

@@ -174,6 +174,8 @@ hipError_t launch_synth(int n, const SynthArgs& a, hipStream_t s);
 hipError_t launch_sh(const ShArgs& a, hipStream_t s);
 hipError_t launch_evolve(const EvolveArgs& a, hipStream_t s);
 hipError_t launch_stats(const StatsArgs& a, hipStream_t s);
+// Count of NaN and infinite values among x[0..count) into *counter (cleared first).
+hipError_t launch_nonfinite(const float* x, int64_t count, unsigned long long* counter, hipStream_t s);
 hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s);
 // receiver passes (receiver.hip)
 hipError_t launch_recv_row_in(const RecvArgs& a, hipStream_t s);     // U1 = A u e^{i th1}, FFT along x

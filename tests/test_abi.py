@@ -103,3 +103,25 @@ def test_receiver_needs_setup(L):
     assert st in (B.E_INVALID, B.E_HIP)
     if st == B.E_INVALID:
         assert "turpy_receiver_setup" in B.last_error()
+
+
+def test_status_and_flag_values_match_header(L):
+    text = open(os.path.join(ROOT, "include", "turpy.h")).read()
+    status = dict((k, int(v)) for k, v in re.findall(r"TURPY_(E_[A-Z]+|OK) = (\d+)", text))
+    for name, value in status.items():
+        assert getattr(B, name) == value, name
+    flags = dict((k, int(v)) for k, v in re.findall(r"#define TURPY_([A-Z_]+) (\d+)u", text))
+    for name in ("ALLOW_ALIASING", "SCREEN_CHECKPOINTS", "CHECK_FINITE"):
+        assert getattr(B, name) == flags[name], name
+    assert len(set(flags[n] for n in ("ALLOW_ALIASING", "SCREEN_CHECKPOINTS", "CHECK_FINITE"))) == 3
+
+
+def test_unknown_plan_flags_rejected(L):
+    st, msg = _status(workloads.config1().path, flags=8)
+    assert st == B.E_INVALID and "flags" in msg
+
+
+def test_debug_fail_launch_arguments(L):
+    assert L.turpy_debug_fail_launch(-1) == B.E_INVALID
+    assert L.turpy_debug_fail_launch(0) == B.OK
+    assert L.turpy_plan_bind_moments(None, None) == B.E_INVALID
