@@ -61,6 +61,8 @@ def parse():
                          "measuring), written at the end")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-pairs", type=int, default=16, help="realization pairs in the oracle sample (about 20 s of CPU work)")
+    ap.add_argument("--uneven-waves", type=int, default=16,
+                    help="waves of 256 serving-mix instances in the uneven leg (16: all 4096; fewer for profiling runs)")
     return ap.parse_args()
 
 
@@ -368,7 +370,7 @@ def uneven_leg(torch, np, api, workloads, args, dev, wave=256):
     memory-budgeted waves of `wave` instances, each wave one turpy_batch call
     (forward; forward + backward with checkpoints), also replayed from HIP
     graphs; the plain one-op-per-kernel version is timed on the first wave."""
-    inst = [x.path for x in workloads.uneven_batch()]
+    inst = [x.path for x in workloads.uneven_batch()][:wave * args.uneven_waves]
     waves = [inst[i:i + wave] for i in range(0, len(inst), wave)]
     t0 = time.perf_counter()
     batches = [api.Batch(wv) for wv in waves]
@@ -475,7 +477,7 @@ def uneven_leg(torch, np, api, workloads, args, dev, wave=256):
                                      "speedup_fwd": res["plain_fwd_wave"] / res["fwd_wave"],
                                      "screen_steps": ss_w},
             "create_seconds": t_create, "tune_seconds": t_tune,
-            "workload": "4096 serving-mix instances (N 256-2048, lambda 532/1064/1550 nm, 5-20 screens, "
+            "workload": f"{len(inst)} serving-mix instances (N 256-2048, lambda 532/1064/1550 nm, 5-20 screens, "
                         "log-uniform Cn2, 3 subharmonic levels, R=1), waves of 256"}
 
 

@@ -352,10 +352,17 @@ turpy_status turpy_receiver_backward(int32_t n, double dx, double aperture_diame
 /* ---------------------------------------------------------------------------
  * Uneven batches: many path instances, each with its own grid size, screen
  * count, wavelength and distances, propagated by one call on the caller's
- * stream.  Instances are spread over a few internal streams of default
- * priority (longest processing time first, cost R N^2 (M + 1)), forked from
- * and joined back to the caller's stream with events; nothing is allocated and
- * no memset is issued, so the calls can be captured in a HIP graph.  Screens
+ * stream.  Instances that share the grid size, the realization count and the
+ * transfer-function form, have every distance > 0 and at most 2^20 pixels
+ * per pass (R N^2; larger ones fill the GPU alone) run in groups: each pass of
+ * the forward pass and of the adjoint is one launch over the group's members.
+ * A group holds as many members as keep its working set (fields and
+ * workspace of its members) within the group limit (turpy_batch_group_limit).
+ * Groups and the other instances are spread over a few internal streams of
+ * default priority (longest processing time first, cost R N^2 (M + 1)),
+ * forked from and joined back to the caller's stream with events; nothing is
+ * allocated and no memset is issued, so the calls can be captured in a HIP
+ * graph.  Screens
  * are synthesised (Eq. S16, Eq. 2-3); instance i draws its noise with the key
  * seed + i * 0x9E3779B97F4A7C15 (mod 2^64), otherwise exactly as
  * turpy_propagate with its own plan.  Not thread-safe (one call at a time per
@@ -375,6 +382,10 @@ turpy_status turpy_batch_create(turpy_batch** out, const turpy_path* paths, cons
 turpy_status turpy_batch_destroy(turpy_batch* batch);
 /* turpy_plan_bind_time for every instance of the batch. */
 turpy_status turpy_batch_bind_time(turpy_batch* batch, const void* dev_t);
+/* Working-set limit of a group, in bytes, for batches created from now on
+ * (process-wide; 0 restores the default, 1 GiB).  It bounds a group's
+ * workspace; a member alone beyond the limit runs its own plan's calls. */
+turpy_status turpy_batch_group_limit(size_t bytes);
 /* op: TURPY_OP_PROPAGATE, TURPY_OP_PROPAGATE_BACKWARD or TURPY_OP_TUNE. */
 turpy_status turpy_batch_workspace_size(const turpy_batch* batch, int32_t op, size_t* bytes);
 /* u_in / u_out: packed fields (instance i at field_offsets[i], one source

@@ -35,7 +35,7 @@ EXPORTS = [
     "turpy_batch_propagate", "turpy_batch_propagate_backward", "turpy_plan_tune", "turpy_plan_widths",
     "turpy_plan_set_widths", "turpy_tune_cache_get", "turpy_tune_cache_put", "turpy_tune_cache_clear",
     "turpy_batch_tune", "turpy_plan_config", "turpy_plan_set_config", "turpy_receiver_setup", "turpy_noise", "turpy_propagate_static", "turpy_checkpoint_size", "turpy_evolve_propagate",
-    "turpy_plan_bind_moments", "turpy_debug_fail_launch",
+    "turpy_plan_bind_moments", "turpy_debug_fail_launch", "turpy_batch_group_limit",
 ]
 
 
@@ -133,6 +133,7 @@ def lib():
         L.turpy_plan_bind_time.argtypes = [c_void_p, c_void_p]
         L.turpy_plan_bind_moments.argtypes = [c_void_p, c_void_p]
         L.turpy_debug_fail_launch.argtypes = [c_int64]
+        L.turpy_batch_group_limit.argtypes = [c_size_t]
         L.turpy_batch_create.argtypes = [POINTER(c_void_p), POINTER(CPath), POINTER(c_int64), c_int32, c_uint32]
         L.turpy_batch_destroy.argtypes = [c_void_p]
         L.turpy_batch_bind_time.argtypes = [c_void_p, c_void_p]
@@ -233,6 +234,10 @@ def plan_bind_moments(handle, moments_ptr):
 
 def debug_fail_launch(k):
     check(lib().turpy_debug_fail_launch(k))
+
+
+def batch_group_limit(nbytes):
+    check(lib().turpy_batch_group_limit(nbytes))
 
 
 def state_size(handle):

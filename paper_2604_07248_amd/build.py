@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libturpy.so")
-SOURCES = ["kernels.hip", "receiver.hip", "api.hip", "host.cpp", "planner.cpp", "batch.cpp"]
+SOURCES = ["kernels.hip", "receiver.hip", "api.hip", "host.cpp", "planner.cpp", "group.cpp", "batch.cpp"]
 
 FLAGS = [
     "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared",

@@ -80,9 +80,12 @@ __device__ __forceinline__ float2 box_muller(uint32_t va, uint32_t vb) {
 
 // Ensemble moments of the intensity (Sec. 3.3) as compensated (Kahan) sums:
 // per pixel (s1, c1) over I = |u|^2 and (s2, c2) over I^2, the true sums being
-// about s - c.  Every kernel that accumulates moments goes through these two
-// helpers, so the same inputs in the same order give the same bits.
+// about s - c.  Every kernel that accumulates moments goes through these
+// helpers, whose multiplies never fuse with a neighbouring add (contraction
+// off), so the same inputs in the same order give the same bits in every
+// kernel that inlines them.
 __device__ __forceinline__ void kahan_add(float& s, float& c, float v) {
+#pragma clang fp contract(off)
   const float y = v - c;
   const float t = s + y;
   c = (t - s) - y;
@@ -90,12 +93,14 @@ __device__ __forceinline__ void kahan_add(float& s, float& c, float v) {
 }
 // Join a compensated partial sum (ps, pc) into (s, c).
 __device__ __forceinline__ void kahan_join(float& s, float& c, float ps, float pc) {
+#pragma clang fp contract(off)
   const float y = ps - (c + pc);
   const float t = s + y;
   c = (t - s) - y;
   s = t;
 }
 __device__ __forceinline__ void moment_add(float& s1, float& c1, float& s2, float& c2, float2 u) {
+#pragma clang fp contract(off)
   const float i = u.x * u.x + u.y * u.y;
   kahan_add(s1, c1, i);
   kahan_add(s2, c2, i * i);

@@ -64,7 +64,7 @@ __device__ __forceinline__ void load_field_row(float2 (&v)[kE], const float2* p,
 // Row pass.
 // ---------------------------------------------------------------------------
 template <int N, int SCREEN, bool BWD>
-__global__ __launch_bounds__(row_block<N>()) void row_pass_kernel(RowArgs a) {
+__device__ __forceinline__ void row_pass_body(const RowArgs& a) {
   constexpr int T = N / kE;
   constexpr int G = row_groups<N>();
   constexpr bool WV = T <= 64;  // each row's transform lives in one wavefront
@@ -214,6 +214,9 @@ __global__ __launch_bounds__(row_block<N>()) void row_pass_kernel(RowArgs a) {
   }
 }
 
+template <int N, int SCREEN, bool BWD>
+__global__ __launch_bounds__(row_block<N>()) void row_pass_kernel(RowArgs a) { row_pass_body<N, SCREEN, BWD>(a); }
+
 // ---------------------------------------------------------------------------
 // Row pass with a screen, split over the two realizations of a pair.  Half A
 // (realization 2j) finishes the screen row: inverse FFT of the scratch row,
@@ -223,9 +226,8 @@ __global__ __launch_bounds__(row_block<N>()) void row_pass_kernel(RowArgs a) {
 // conjugate phase) and transform forward.  Both halves pass the same barrier
 // sequence: a half with no transform at a stage runs idle_fft.
 // ---------------------------------------------------------------------------
-template <int N, int SCREEN, bool BWD, int W>
-__global__ __launch_bounds__(pair_block<N>()) __attribute__((amdgpu_waves_per_eu(W, 0)))
-void row_pair_kernel(RowArgs a) {
+template <int N, int SCREEN, bool BWD>
+__device__ __forceinline__ void row_pair_body(const RowArgs& a) {
   constexpr int T = N / kE;
   constexpr int G = pair_rows<N>();
   constexpr int HALF = G * T;
@@ -433,6 +435,10 @@ void row_pair_kernel(RowArgs a) {
   }
 }
 
+template <int N, int SCREEN, bool BWD, int W>
+__global__ __launch_bounds__(pair_block<N>()) __attribute__((amdgpu_waves_per_eu(W, 0)))
+void row_pair_kernel(RowArgs a) { row_pair_body<N, SCREEN, BWD>(a); }
+
 // ---------------------------------------------------------------------------
 // Forward row pass over a realization pair with synthesised screens and no
 // checkpoint output, relay schedule.  A block holds two workers (whole waves)
@@ -453,9 +459,8 @@ void row_pair_kernel(RowArgs a) {
 // barriers a stage whose two transforms differ in kind passes the same
 // barriers on both sides (idle_fft).
 // ---------------------------------------------------------------------------
-template <int N, int W>
-__global__ __launch_bounds__(relay_block<N>()) __attribute__((amdgpu_waves_per_eu(W, 0)))
-void row_relay_kernel(RowArgs a) {
+template <int N>
+__device__ __forceinline__ void row_relay_body(const RowArgs& a) {
   constexpr int T = N / kE;
   constexpr int G = relay_rows<N>();
   constexpr int HALF = G * T;
@@ -595,6 +600,10 @@ void row_relay_kernel(RowArgs a) {
   }
 }
 
+template <int N, int W>
+__global__ __launch_bounds__(relay_block<N>()) __attribute__((amdgpu_waves_per_eu(W, 0)))
+void row_relay_kernel(RowArgs a) { row_relay_body<N>(a); }
+
 // ---------------------------------------------------------------------------
 // Column pass: FFT along y, x h(k0)/N (x angular-spectrum correction), IFFT.
 // ---------------------------------------------------------------------------
@@ -626,8 +635,7 @@ __device__ __forceinline__ float2 angular_correction(const ColArgs& a, int k0, i
 }
 
 template <int N, int ANGULAR, int K, int R2SEL>
-__global__ __launch_bounds__(K * (N / kE))
-void col_pass_kernel(ColArgs a) {
+__device__ __forceinline__ void col_pass_body(const ColArgs& a) {
   constexpr int T = N / kE;
   constexpr int STRIPS = N / K;
   __shared__ float2 smem[ColLds<K>::words(N)];
@@ -661,13 +669,16 @@ void col_pass_kernel(ColArgs a) {
   for (int m = 0; m < kE; ++m) (dst + static_cast<size_t>(t) * N)[static_cast<size_t>(T * m) * N] = x[m];
 }
 
+template <int N, int ANGULAR, int K, int R2SEL>
+__global__ __launch_bounds__(K * (N / kE))
+void col_pass_kernel(ColArgs a) { col_pass_body<N, ANGULAR, K, R2SEL>(a); }
+
 // ---------------------------------------------------------------------------
 // Column half of the screen synthesis: noise x PSD weight (Eq. S16/S17), or a
 // stored spectrum, then the unnormalised inverse transform along y.
 // ---------------------------------------------------------------------------
 template <int N, int K, int R2SEL>
-__global__ __launch_bounds__(K * (N / kE))
-void synth_col_kernel(SynthArgs a) {
+__device__ __forceinline__ void synth_col_body(const SynthArgs& a) {
   constexpr int T = N / kE;
   constexpr int STRIPS = N / K;
   __shared__ float2 smem[ColLds<K>::words(N)];
@@ -723,7 +734,8 @@ void synth_col_kernel(SynthArgs a) {
     constexpr float inv2pi = 0.15915494309189535f;
     const float2* src = a.spectra + (static_cast<size_t>(j) * a.M + a.screen) * N * N + k1;
 #pragma unroll
-    for (int m = 0; m < kE; ++m) x[m] = c_scale((src + static_cast<size_t>(t) * N)[static_cast<size_t>(T * m) * N], inv2pi);
+    for (int m = 0; m < kE; ++m)
+      x[m] = c_scale((src + static_cast<size_t>(t) * N)[static_cast<size_t>(T * m) * N], inv2pi);
   } else {
     const int kx = signed_bin(k1, N);
 #pragma unroll
@@ -746,10 +758,14 @@ void synth_col_kernel(SynthArgs a) {
   for (int m = 0; m < kE; ++m) (dst + static_cast<size_t>(t) * N)[static_cast<size_t>(T * m) * N] = x[m];
 }
 
+template <int N, int K, int R2SEL>
+__global__ __launch_bounds__(K * (N / kE))
+void synth_col_kernel(SynthArgs a) { synth_col_body<N, K, R2SEL>(a); }
+
 // ---------------------------------------------------------------------------
 // Subharmonic coefficients of Eq. 2 for every (pair, screen), and their mean.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void sh_kernel(ShArgs a) {
+__device__ __forceinline__ void sh_body(const ShArgs& a) {
   __shared__ float2 coef[24];
   const int64_t j = blockIdx.x;
   const int s = blockIdx.y;
@@ -802,6 +818,8 @@ __global__ __launch_bounds__(64) void sh_kernel(ShArgs a) {
     out[24] = mean;
   }
 }
+
+__global__ __launch_bounds__(64) void sh_kernel(ShArgs a) { sh_body(a); }
 
 // ---------------------------------------------------------------------------
 // Spectrum evolution (Eq. 4 then Eq. 5), elementwise on bin pairs (k0, k1),
@@ -1320,6 +1338,199 @@ hipError_t synth_launch(const SynthArgs& a, hipStream_t s) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Grouped launches (uneven batches): the kernels above over many instances,
+// each block taking its instance's record and adding the call's bases.
+// ---------------------------------------------------------------------------
+template <class T>
+__device__ __forceinline__ T* rebase(char* base, T* off) {
+  return reinterpret_cast<T*>(base + reinterpret_cast<uintptr_t>(off));
+}
+template <class T>
+__device__ __forceinline__ const T* rebase(const char* base, const T* off) {
+  return reinterpret_cast<const T*>(base + reinterpret_cast<uintptr_t>(off));
+}
+
+// The instance's key: the call's seed plus the seed offset in the record.
+__device__ __forceinline__ void group_key(const GroupCall& g, uint32_t* k0, uint32_t* k1) {
+  const uint64_t s = g.seed + ((static_cast<uint64_t>(*k1) << 32) | *k0);
+  *k0 = static_cast<uint32_t>(s);
+  *k1 = static_cast<uint32_t>(s >> 32);
+}
+
+__device__ __forceinline__ RowArgs row_record(const RowArgs* tab, uint32_t i, const GroupCall& g) {
+  RowArgs a = tab[i];
+  const char* ws = g.ws;
+  a.in = rebase(g.in, a.in);
+  a.out = rebase(g.out, a.out);
+  a.scratch = rebase(ws, a.scratch);
+  a.sh = rebase(ws, a.sh);
+  a.ckpt_out = g.ck ? rebase(g.ck, a.ckpt_out) : nullptr;
+  return a;
+}
+
+// The adjoint's screen passes read the checkpoints and write dL/dphi.
+__device__ __forceinline__ RowArgs row_record_bwd(const RowArgs* tab, uint32_t i, const GroupCall& g) {
+  RowArgs a = tab[i];
+  const char* ws = g.ws;
+  const char* ck = g.ck;
+  a.in = rebase(g.in, a.in);
+  a.out = rebase(g.out, a.out);
+  a.scratch = rebase(ws, a.scratch);
+  a.sh = rebase(ws, a.sh);
+  a.ckpt_out = nullptr;
+  a.ckpt_in = rebase(ck, a.ckpt_in);
+  a.grad_screens = g.gs ? rebase(g.gs, a.grad_screens) : nullptr;
+  return a;
+}
+
+template <int N, int SCREEN>
+__global__ __launch_bounds__(row_block<N>()) void row_pass_group_kernel(const RowArgs* tab, GroupCall g) {
+  row_pass_body<N, SCREEN, false>(row_record(tab, blockIdx.z, g));
+}
+
+template <int N>
+__global__ __launch_bounds__(row_block<N>()) void row_pass_group_bwd_kernel(const RowArgs* tab, GroupCall g) {
+  row_pass_body<N, ROW_SCRATCH, true>(row_record_bwd(tab, blockIdx.z, g));
+}
+
+template <int N>
+__global__ __launch_bounds__(pair_block<N>()) __attribute__((amdgpu_waves_per_eu(kRowWaves, 0)))
+void row_pair_group_bwd_kernel(const RowArgs* tab, GroupCall g) {
+  row_pair_body<N, ROW_SCRATCH, true>(row_record_bwd(tab, blockIdx.z, g));
+}
+
+template <int N>
+__global__ __launch_bounds__(pair_block<N>()) __attribute__((amdgpu_waves_per_eu(kRowWaves, 0)))
+void row_pair_group_kernel(const RowArgs* tab, GroupCall g) {
+  row_pair_body<N, ROW_SCRATCH, false>(row_record(tab, blockIdx.z, g));
+}
+
+template <int N>
+__global__ __launch_bounds__(relay_block<N>()) __attribute__((amdgpu_waves_per_eu(kRowWaves, 0)))
+void row_relay_group_kernel(const RowArgs* tab, GroupCall g) {
+  row_relay_body<N>(row_record(tab, blockIdx.z, g));
+}
+
+template <int N, int ANGULAR, int R2SEL>
+__global__ __launch_bounds__(col_width<N>() * (N / kE)) void col_pass_group_kernel(const ColArgs* tab, GroupCall g) {
+  ColArgs a = tab[blockIdx.y];
+  a.in = rebase(g.in, a.in);
+  a.out = rebase(g.out, a.out);
+  col_pass_body<N, ANGULAR, col_width<N>(), R2SEL>(a);
+}
+
+template <int N, int R2SEL>
+__global__ __launch_bounds__(synth_width<N>() * (N / kE)) void synth_group_kernel(const SynthArgs* tab, GroupCall g) {
+  SynthArgs a = tab[blockIdx.y];
+  a.scratch = rebase(g.ws, a.scratch);
+  group_key(g, &a.key0, &a.key1);
+  a.t = g.t;
+  a.t_dev = g.t_dev;
+  synth_col_body<N, synth_width<N>(), R2SEL>(a);
+}
+
+__global__ __launch_bounds__(64) void sh_group_kernel(const ShArgs* tab, GroupCall g) {
+  ShArgs a = tab[blockIdx.z];
+  if (blockIdx.y >= static_cast<uint32_t>(a.M) || a.levels == 0) return;  // uniform over the block
+  a.sh = rebase(g.ws, a.sh);
+  group_key(g, &a.key0, &a.key1);
+  a.t = g.t;
+  a.t_dev = g.t_dev;
+  sh_body(a);
+}
+
+// The row passes of a group, chosen as row_launch chooses them for one
+// instance (the records share the kernel-deciding fields).
+template <int N>
+hipError_t row_group_launch(const RowArgs& proto, const RowArgs* tab, uint32_t count, int64_t pairs,
+                            const GroupCall& g, hipStream_t s) {
+  constexpr int G = row_groups<N>();
+  const uint32_t P = static_cast<uint32_t>(pairs);
+  const bool small = (pair_rows<N>() * (N / kE)) % 64 != 0;  // halves that are not whole waves
+  if (proto.phase_out) return hipErrorInvalidValue;
+  if (proto.screen_mode == ROW_NO_SCREEN) {
+    hipLaunchKernelGGL((row_pass_group_kernel<N, ROW_NO_SCREEN>), dim3(N / G, P, count), dim3(row_block<N>()), 0,
+                       s, tab, g);
+  } else if (proto.screen_mode != ROW_SCRATCH) {
+    return hipErrorInvalidValue;
+  } else if (proto.backward) {
+    if (small)
+      hipLaunchKernelGGL((row_pass_group_bwd_kernel<N>), dim3(N / G, P, count), dim3(row_block<N>()), 0, s, tab, g);
+    else
+      hipLaunchKernelGGL((row_pair_group_bwd_kernel<N>), dim3(N / pair_rows<N>(), P, count), dim3(pair_block<N>()),
+                         0, s, tab, g);
+  } else if (small) {
+    hipLaunchKernelGGL((row_pass_group_kernel<N, ROW_SCRATCH>), dim3(N / G, P, count), dim3(row_block<N>()), 0, s,
+                       tab, g);
+  } else {
+    bool relay = false;
+    if constexpr (relay_fits<N>() && N <= 1024) {
+      if (!g.ck && !proto.conj_tables && !proto.pre) {
+        hipLaunchKernelGGL((row_relay_group_kernel<N>), dim3(N / (2 * relay_rows<N>()), P, count),
+                           dim3(relay_block<N>()), 0, s, tab, g);
+        relay = true;
+      }
+    }
+    if (!relay)
+      hipLaunchKernelGGL((row_pair_group_kernel<N>), dim3(N / pair_rows<N>(), P, count), dim3(pair_block<N>()), 0, s,
+                         tab, g);
+  }
+  return hipGetLastError();
+}
+
+template <int N, int R2SEL>
+hipError_t col_group_launch_r(const ColArgs& proto, const ColArgs* tab, uint32_t count, const GroupCall& g,
+                              hipStream_t s) {
+  if constexpr (!radix_built(N, R2SEL)) {
+    return hipErrorInvalidValue;
+  } else {
+    const dim3 grid(static_cast<uint32_t>((N / col_width<N>()) * proto.R), count), block(col_width<N>() * (N / kE));
+    if (!proto.angular)
+      hipLaunchKernelGGL((col_pass_group_kernel<N, TF_FRESNEL_ONLY, R2SEL>), grid, block, 0, s, tab, g);
+    else if (proto.as_table)
+      hipLaunchKernelGGL((col_pass_group_kernel<N, TF_AS_TABLE, R2SEL>), grid, block, 0, s, tab, g);
+    else
+      hipLaunchKernelGGL((col_pass_group_kernel<N, TF_AS_FP32, R2SEL>), grid, block, 0, s, tab, g);
+    return hipGetLastError();
+  }
+}
+
+template <int N>
+hipError_t col_group_launch(const ColArgs& proto, const ColArgs* tab, uint32_t count, const GroupCall& g,
+                            hipStream_t s) {
+  switch (proto.radix) {
+    case 0: return col_group_launch_r<N, 0>(proto, tab, count, g, s);
+    case 4: return col_group_launch_r<N, 4>(proto, tab, count, g, s);
+    case 8: return col_group_launch_r<N, 8>(proto, tab, count, g, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int N, int R2SEL>
+hipError_t synth_group_launch_r(const SynthArgs& proto, const SynthArgs* tab, uint32_t count, const GroupCall& g,
+                                hipStream_t s) {
+  if constexpr (!radix_built(N, R2SEL)) {
+    return hipErrorInvalidValue;
+  } else {
+    const dim3 grid(static_cast<uint32_t>((N / synth_width<N>()) * proto.P), count);
+    hipLaunchKernelGGL((synth_group_kernel<N, R2SEL>), grid, dim3(synth_width<N>() * (N / kE)), 0, s, tab, g);
+    return hipGetLastError();
+  }
+}
+
+template <int N>
+hipError_t synth_group_launch(const SynthArgs& proto, const SynthArgs* tab, uint32_t count, const GroupCall& g,
+                              hipStream_t s) {
+  if (proto.spectra || proto.evolve) return hipErrorInvalidValue;  // synthesised screens only
+  switch (proto.radix) {
+    case 0: return synth_group_launch_r<N, 0>(proto, tab, count, g, s);
+    case 4: return synth_group_launch_r<N, 4>(proto, tab, count, g, s);
+    case 8: return synth_group_launch_r<N, 8>(proto, tab, count, g, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 }  // namespace
 
 #define TURPY_DISPATCH_N(n, FN, ...)            \
@@ -1348,6 +1559,25 @@ hipError_t launch_row_moments(int n, const RowArgs& a, float* moments, hipStream
 }
 hipError_t launch_col(int n, const ColArgs& a, hipStream_t s) { TURPY_DISPATCH_N(n, col_launch, a, s) }
 hipError_t launch_synth(int n, const SynthArgs& a, hipStream_t s) { TURPY_DISPATCH_N(n, synth_launch, a, s) }
+
+hipError_t launch_row_group(int n, const RowArgs& proto, const RowArgs* tab, uint32_t count, int64_t pairs,
+                            const GroupCall& g, hipStream_t s) {
+  TURPY_DISPATCH_N(n, row_group_launch, proto, tab, count, pairs, g, s)
+}
+hipError_t launch_col_group(int n, const ColArgs& proto, const ColArgs* tab, uint32_t count, const GroupCall& g,
+                            hipStream_t s) {
+  TURPY_DISPATCH_N(n, col_group_launch, proto, tab, count, g, s)
+}
+hipError_t launch_synth_group(int n, const SynthArgs& proto, const SynthArgs* tab, uint32_t count,
+                              const GroupCall& g, hipStream_t s) {
+  TURPY_DISPATCH_N(n, synth_group_launch, proto, tab, count, g, s)
+}
+hipError_t launch_sh_group(const ShArgs* tab, uint32_t count, int64_t pairs, int max_screens, const GroupCall& g,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(sh_group_kernel, dim3(static_cast<uint32_t>(pairs), static_cast<uint32_t>(max_screens), count),
+                     dim3(64), 0, s, tab, g);
+  return hipGetLastError();
+}
 
 hipError_t launch_sh(const ShArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(sh_kernel, dim3(static_cast<uint32_t>(a.P), a.M), dim3(64), 0, s, a);

@@ -107,6 +107,24 @@ struct ShArgs {
   float2 mean_fac[3];       // mean over the grid of exp(2 pi i (i - N/2)/(N 3^p))
 };
 
+// A grouped launch of an uneven batch runs one pass of many path instances:
+// instance i's argument record is tab[i], i the block's z index (y for the
+// column-pass and synthesis kernels, whose x index is 1-D).  In a record the
+// pointers into a call's buffers hold byte offsets, which the launch adds to
+// the bases below; the key words of the noise records hold the instance's
+// seed offset (low, high word), to which the launch adds its seed.  Pointers
+// to plan tables (twiddles, transfer functions) are absolute.
+struct GroupCall {
+  const char* in;           // fields the pass reads: the call's u_in, or u_out
+  char* out;                // fields it writes: u_out
+  char* ws;                 // the group's workspace
+  char* ck;                 // checkpoints the pass writes (forward) or reads (adjoint), or NULL
+  char* gs;                 // adjoint: dL/dphi, or NULL
+  uint64_t seed;
+  uint32_t t;
+  const uint32_t* t_dev;    // time step read at run time when set
+};
+
 struct EvolveArgs {
   float2* spectra;          // [P][M][N][N] radians, in place
   int64_t P;
@@ -166,6 +184,21 @@ struct RecvArgs {
 };
 
 hipError_t launch_row(int n, const RowArgs& a, int64_t pairs, hipStream_t s);
+// Grouped launches over `count` instances (records in device memory, `proto`
+// one of them as built on the host, for the kernel choice).  The row passes
+// take the screen-free and the synthesised-screen forms, forward and adjoint;
+// the column pass and synthesis the default strip width with the record's
+// radix.
+hipError_t launch_row_group(int n, const RowArgs& proto, const RowArgs* tab, uint32_t count, int64_t pairs,
+                            const GroupCall& g, hipStream_t s);
+hipError_t launch_col_group(int n, const ColArgs& proto, const ColArgs* tab, uint32_t count, const GroupCall& g,
+                            hipStream_t s);
+hipError_t launch_synth_group(int n, const SynthArgs& proto, const SynthArgs* tab, uint32_t count,
+                              const GroupCall& g, hipStream_t s);
+// grid (pairs, max_screens, count); blocks beyond an instance's screens or
+// with no subharmonic levels exit at once
+hipError_t launch_sh_group(const ShArgs* tab, uint32_t count, int64_t pairs, int max_screens, const GroupCall& g,
+                           hipStream_t s);
 // The plain final row pass (in spectral, out real, no screen, no pre/post
 // factor) with the ensemble moments added into moments [4][n][n].
 hipError_t launch_row_moments(int n, const RowArgs& a, float* moments, hipStream_t s);

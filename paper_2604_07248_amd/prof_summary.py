@@ -35,7 +35,7 @@ def sources_sha256():
     """Hash of every kernel and schedule source of the library (csrc/)."""
     h = hashlib.sha256()
     for p in sorted(glob.glob(os.path.join(CSRC, "*"))):
-        if p.endswith((".hip", ".hpp", ".h")):
+        if p.endswith((".hip", ".hpp", ".h", ".cpp")):
             h.update(os.path.basename(p).encode())
             with open(p, "rb") as f:
                 h.update(f.read())
@@ -47,17 +47,23 @@ def family(kernel_name):
     n = kernel_name
     if "turpy::" not in n:
         return None  # runtime and PyTorch kernels
-    m = re.search(r"row_(?:pair|pass)_kernel<(\d+), (\d+), (true|false)>", n)
+    m = re.search(r"row_(?:pair|pass)_kernel<(\d+), (\d+), (true|false)", n)
     if m:
         if m.group(2) == "0":
             return "row_plain"
         return "row_bwd" if m.group(3) == "true" else "row_fwd"
-    if "row_relay_kernel" in n:
+    m = re.search(r"row_pass_group_kernel<(\d+), (\d+)>", n)
+    if m:
+        return "row_plain" if m.group(2) == "0" else "row_fwd"
+    if "_group_bwd_kernel" in n:
+        return "row_bwd"
+    if "row_relay" in n or "row_pair_group_kernel" in n:
         return "row_fwd"
-    for key, fam in (("col_pass_kernel", "col"), ("synth_col_kernel", "synth"),
-                     ("sh_kernel", "sh"), ("evolve_kernel", "evolve"), ("stats_kernel", "stats"),
-                     ("finalize_kernel", "finalize"), ("copy_kernel", "copy"), ("recv_row_in", "recv_row"),
-                     ("recv_col_grad", "recv_col_grad"), ("recv_col", "recv_col"),
+    for key, fam in (("row_moments_kernel", "row_moments"), ("col_pass", "col"), ("synth_", "synth"),
+                     ("sh_kernel", "sh"), ("sh_group_kernel", "sh"), ("evolve_kernel", "evolve"),
+                     ("stats_kernel", "stats"), ("finalize_kernel", "finalize"), ("copy_kernel", "copy"),
+                     ("sum_planes_kernel", "sum"), ("noise_kernel", "noise"), ("nonfinite_kernel", "nonfinite"),
+                     ("recv_row_in", "recv_row"), ("recv_col_grad", "recv_col_grad"), ("recv_col", "recv_col"),
                      ("recv_row_grad", "recv_row_grad"), ("recv_reduce", "recv_reduce")):
         if key in n:
             return fam
@@ -67,7 +73,7 @@ def family(kernel_name):
 def short(kernel_name):
     n = re.sub(r"turpy::\(anonymous namespace\)::", "", kernel_name)
     n = re.sub(r"^void ", "", n)
-    n = re.sub(r"\(turpy::\w+(, turpy::\w+)?(, long)?\)", "", n)
+    n = re.sub(r"\([^()]*\)$", "", n)  # the argument list
     return n[:70]
 
 
@@ -166,11 +172,34 @@ def load_traffic(profiles_dir, leg):
 
 
 PRE = "cd /tmp && export TMPDIR=/tmp && R=<repository root>"
-TUNE = "--tune-cache $R/gpurun_out/tune.json"
+TUNE = "--tune-cache $R/gpurun_out/tune.json --no-cpu-baseline"
+
+# The standard profiling runs: (directory under gpurun_out, bench.py arguments).
+TRACES = {
+    "prof_fwd": "--only fwd --steps 10 --warmup 2",
+    "prof_fwdbwd": "--only fwdbwd --steps 5 --warmup 2",
+    "prof_ar": "--only ar --steps 10 --warmup 2",
+    "prof_uneven": "--only uneven --uneven-waves 1 --steps 25 --warmup 1",
+}
+PMC_SQ = ("SQ_WAVES SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_BUSY_CYCLES SQ_WAVE_CYCLES SQ_INSTS_LDS "
+          "GRBM_GUI_ACTIVE")
+PMC_STALL = ("SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_ANY SQ_WAIT_INST_ANY SQ_WAIT_INST_LDS "
+             "SQ_LDS_BANK_CONFLICT SQ_ACTIVE_INST_LDS GRBM_GUI_ACTIVE TA_BUSY_avr TCP_PENDING_STALL_CYCLES_sum "
+             "TCP_TCP_TA_ADDR_STALL_CYCLES_sum")
 
 
 def _ev(fams, tab):
     return ", ".join(f"{f} {tab[f]['avg_us']:.1f} us" for f in fams if f in tab)
+
+
+def _trace_cmd(d):
+    return ["    rocprofv3 --kernel-trace --stats --output-format csv -d $R/gpurun_out/" + d + " -o t -- \\",
+            f"        python $R/bench.py {TRACES[d]} {TUNE}"]
+
+
+def _pmc_cmd(counters, d, leg):
+    return [f"    timeout -s KILL 120 rocprofv3 --pmc {counters} --output-format csv -d $R/gpurun_out/{d} -o p -- \\",
+            f"        python $R/bench.py --only {leg} --steps 3 --warmup 1 {TUNE}"]
 
 
 def report(out_dir, bench_json, root="gpurun_out"):
@@ -179,64 +208,66 @@ def report(out_dir, bench_json, root="gpurun_out"):
     with open(bench_json) as fh:
         b = json.load(fh)
     j = lambda *a: os.path.join(root, *a)
+    head = ["Commands (one MI355X; the profiler writes its temporary files under /tmp).  The default",
+            "benchmark run writes the launch configuration its tuner chose; the profiled runs read it back,",
+            "so that their traces hold no tuning launches:", "",
+            "    python bench.py --tune-cache gpurun_out/tune.json > gpurun_out/bench.json", f"    {PRE}"]
     # forward kernel trace
     rows = stats_table(j("prof_fwd"))
     d = b["roofline"]
     dom_rows = [r for r in rows[2:] if f"| {d['kernel']} |" in r]
-    lines = ["# Kernel trace: forward headline workload (N=1024, R=64, M=8, fresh screens)", "",
-             "Commands (one MI355X; the profiler writes its temporary files under /tmp).  The first, the",
-             "default benchmark run, also writes the strip widths its tuner chose; the profiled runs read",
-             "them back, so that their traces hold no tuning launches:", "",
-             "    python bench.py --tune-cache gpurun_out/tune.json > gpurun_out/bench.json", f"    {PRE}",
-             "    rocprofv3 --kernel-trace --stats --output-format csv -d $R/gpurun_out/prof_fwd -o fwd -- \\",
-             f"        python $R/bench.py --only fwd --steps 10 --warmup 2 {TUNE}", "",
-             "Summary: `python -m paper_2604_07248_amd.prof_summary stats gpurun_out/prof_fwd`.  The run covers",
-             "22 forward steps: 2 warm-up, 10 with every family bracketed by events, 10 timed.  Durations in",
-             "microseconds.", ""] + rows + [
-             "", "HIP-event averages measured inside `bench.py` (default run: 5 warm-up, 50 profiled and 50 timed "
-             "steps): " + _ev(["row_fwd", "col", "synth", "row_plain", "stats"], b["kernels"]) + ".", "",
-             f"Roofline line of that run: dominant family `{d['kernel']}`, {d['bytes_per_launch']:.0f} algorithmic "
-             f"bytes per launch over {d['avg_us']:.1f} us = {d['achieved']:.0f} GB/s = {100 * d['frac']:.1f} % of "
-             f"8 TB/s; the trace's average for that family is "
-             f"{' / '.join(r.split('|')[5].strip() for r in dom_rows)} us."]
+    lines = ["# Kernel trace: forward headline workload (N=1024, R=64, M=8, fresh screens)", ""] + head + \
+        _trace_cmd("prof_fwd") + [
+        "", "Summary: `python -m paper_2604_07248_amd.prof_summary stats gpurun_out/prof_fwd`.  The run covers",
+        "22 forward steps: 2 warm-up, 10 with every family bracketed by events, 10 timed.  Durations in",
+        "microseconds.", ""] + rows + [
+        "", "HIP-event averages measured inside `bench.py` (default run: 5 warm-up, 50 profiled and 50 timed "
+        "steps): " + _ev(["row_fwd", "col", "synth", "row_moments", "row_plain"], b["kernels"]) + ".", "",
+        f"Roofline line of that run: dominant family `{d['kernel']}`, {d['bytes_per_launch']:.0f} algorithmic "
+        f"bytes per launch over {d['avg_us']:.1f} us = {d['achieved']:.0f} GB/s = {100 * d['frac']:.1f} % of "
+        f"8 TB/s; the trace's average for that family is "
+        f"{' / '.join(r.split('|')[5].strip() for r in dom_rows)} us."]
     _write(out_dir, "fwd_h1_n1024_r64_m8_kernel_stats.md", lines)
-    # forward + adjoint kernel trace
-    lines = ["# Kernel trace: forward + adjoint, headline workload (N=1024, R=64, M=8, checkpoints)", "",
-             "Command:", "", f"    {PRE}",
-             "    rocprofv3 --kernel-trace --stats --output-format csv -d $R/gpurun_out/prof_fwdbwd -o fwdbwd -- \\",
-             f"        python $R/bench.py --only fwdbwd --steps 5 --warmup 2 {TUNE}", "",
-             "Summary: `python -m paper_2604_07248_amd.prof_summary stats gpurun_out/prof_fwdbwd`.", ""]
-    lines += stats_table(j("prof_fwdbwd")) + [
-        "", "HIP-event averages inside `bench.py` (default run): " +
-        _ev(["row_fwd", "row_bwd", "col", "synth", "row_plain"], b["fwd_bwd"]["kernels"]) + "."]
-    _write(out_dir, "fwdbwd_h1_n1024_r64_m8_kernel_stats.md", lines)
-    # HBM traffic
-    lines = ["# HBM traffic per launch: forward headline workload (N=1024, R=64, M=8)", "",
-             "Commands (one counter per run; the copy runs calibrate the counters with the library's copy",
-             "kernel moving 512 MiB each way per launch):", "", f"    {PRE}"]
-    for c in ("FETCH_SIZE", "WRITE_SIZE"):
-        for leg in ("fwd", "copy"):
-            lines.append(f"    timeout -s KILL 120 rocprofv3 --pmc {c} --output-format csv "
-                         f"-d $R/gpurun_out/pmc_{c}_{leg} -o p -- \\")
-            lines.append(f"        python $R/bench.py --only {leg} --steps 3 --warmup 1 {TUNE}")
-    lines += ["", "Summary: `python -m paper_2604_07248_amd.prof_summary traffic --fetch gpurun_out/pmc_FETCH_SIZE_fwd "
-              "--write gpurun_out/pmc_WRITE_SIZE_fwd --copy-fetch gpurun_out/pmc_FETCH_SIZE_copy --copy-write "
-              "gpurun_out/pmc_WRITE_SIZE_copy --copy-bytes 536870912 --leg fwd`.", "",
-              "Averages over every launch of a family (the column family includes the one-plane pass 0, the",
-              "row-plain family the one-plane source transform).  On gfx950 almost every read is a 128-byte",
-              "request, which the FETCH_SIZE expression counts as 64 bytes (TCC_BUBBLE stays 0): the copy",
-              "calibration gives 2.0 KiB per FETCH_SIZE unit and 1.0 KiB per WRITE_SIZE unit.", ""]
-    lines += traffic(j("pmc_FETCH_SIZE_fwd"), j("pmc_WRITE_SIZE_fwd"), j("pmc_FETCH_SIZE_copy"),
-                     j("pmc_WRITE_SIZE_copy"), 536870912, "fwd")
-    _write(out_dir, "fwd_h1_n1024_r64_m8_hbm_traffic.md", lines)
-    # SQ counters
+    # forward + adjoint, AR and serving-mix kernel traces
+    for d_, name, title, tab, fams in (
+            ("prof_fwdbwd", "fwdbwd_h1_n1024_r64_m8_kernel_stats.md",
+             "forward + adjoint, headline workload (N=1024, R=64, M=8, screen checkpoints)",
+             b["fwd_bwd"]["kernels"], ["row_fwd", "row_bwd", "col", "synth", "row_plain", "sum"]),
+            ("prof_ar", "ar_c3_n1024_r32_m8_kernel_stats.md",
+             "AR workload (N=1024, 32 sequences, M=8; the evolution fused into the synthesis)",
+             b["ar"]["kernels"], ["row_fwd", "col", "synth", "row_moments", "row_plain"]),
+            ("prof_uneven", "uneven_c5_serving_mix_kernel_stats.md",
+             "serving mix (one wave of 256 instances, N 256-2048, R=1; grouped launches)", None, [])):
+        lines = [f"# Kernel trace: {title}", ""] + head + _trace_cmd(d_) + [
+            "", f"Summary: `python -m paper_2604_07248_amd.prof_summary stats gpurun_out/{d_}`.", ""]
+        lines += stats_table(j(d_))
+        if tab:
+            lines += ["", "HIP-event averages inside `bench.py` (default run): " + _ev(fams, tab) + "."]
+        _write(out_dir, name, lines)
+    # HBM traffic of the forward and the forward + adjoint legs
+    for leg, title in (("fwd", "forward"), ("fwdbwd", "forward + adjoint")):
+        lines = [f"# HBM traffic per launch: {title}, headline workload (N=1024, R=64, M=8)", "",
+                 "Commands (one counter per run; the copy runs calibrate the counters with the library's copy",
+                 "kernel moving 512 MiB each way per launch):", "", f"    {PRE}"]
+        for c in ("FETCH_SIZE", "WRITE_SIZE"):
+            for lg in (leg, "copy"):
+                lines += _pmc_cmd(c, f"pmc_{c}_{lg}", lg)
+        lines += ["", "Summary: `python -m paper_2604_07248_amd.prof_summary traffic --fetch "
+                  f"gpurun_out/pmc_FETCH_SIZE_{leg} --write gpurun_out/pmc_WRITE_SIZE_{leg} --copy-fetch "
+                  "gpurun_out/pmc_FETCH_SIZE_copy --copy-write gpurun_out/pmc_WRITE_SIZE_copy --copy-bytes "
+                  f"536870912 --leg {leg}`.", "",
+                  "Averages over every launch of a family (the column family includes the one-plane pass 0, the",
+                  "row-plain family the one-plane transforms).  On gfx950 almost every read is a 128-byte",
+                  "request, which the FETCH_SIZE expression counts as 64 bytes: the copy calibration sets the",
+                  "bytes per counter unit.", ""]
+        lines += traffic(j(f"pmc_FETCH_SIZE_{leg}"), j(f"pmc_WRITE_SIZE_{leg}"), j("pmc_FETCH_SIZE_copy"),
+                         j("pmc_WRITE_SIZE_copy"), 536870912, leg)
+        _write(out_dir, f"{leg}_h1_n1024_r64_m8_hbm_traffic.md", lines)
+    # VALU and wave counters
     sq = pmc_by_kernel(j("pmc_sq_fwd"))
     lines = ["# Wave and VALU counters: forward headline workload (N=1024, R=64, M=8)", "", "Command:", "",
-             f"    {PRE}",
-             "    timeout -s KILL 120 rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_BUSY_CYCLES \\",
-             "        SQ_WAVE_CYCLES SQ_INSTS_LDS GRBM_GUI_ACTIVE --output-format csv -d $R/gpurun_out/pmc_sq_fwd "
-             "-o p -- \\", f"        python $R/bench.py --only fwd --steps 3 --warmup 1 {TUNE}", "",
-             "Summary: `python -m paper_2604_07248_amd.prof_summary pmc gpurun_out/pmc_sq_fwd` (per-dispatch",
+             f"    {PRE}"] + _pmc_cmd(PMC_SQ, "pmc_sq_fwd", "fwd") + [
+             "", "Summary: `python -m paper_2604_07248_amd.prof_summary pmc gpurun_out/pmc_sq_fwd` (per-dispatch",
              "averages).  VALU busy = SQ_INSTS_VALU x 4 cycles (a wave64 FP32 instruction on a 16-lane SIMD) /",
              "(1024 SIMDs x GRBM_GUI_ACTIVE / 8 XCDs).", "",
              "| family | waves | VALU instr per wave | LDS instr per wave | kernel cycles | VALU busy |",
@@ -251,6 +282,29 @@ def report(out_dir, bench_json, root="gpurun_out"):
                      f"{100 * valu * 4 / (1024 * cyc):.0f} % |")
     lines += ["", "Full table:", ""] + pmc_table([j("pmc_sq_fwd")])
     _write(out_dir, "fwd_h1_n1024_r64_m8_sq_counters.md", lines)
+    # stall and occupancy counters
+    st = pmc_by_kernel(j("pmc_stall_fwd"))
+    lines = ["# Stall and occupancy counters: forward headline workload (N=1024, R=64, M=8)", "", "Command:", "",
+             f"    {PRE}"] + _pmc_cmd(PMC_STALL, "pmc_stall_fwd", "fwd") + [
+             "", "Summary: `python -m paper_2604_07248_amd.prof_summary pmc gpurun_out/pmc_stall_fwd` (per-dispatch",
+             "averages).  With c = GRBM_GUI_ACTIVE / 8 (kernel cycles; the counter adds the 8 XCDs): waves",
+             "resident per CU = SQ_WAVE_CYCLES / (256 c); wait fractions = SQ_WAIT_ANY and SQ_WAIT_INST_ANY over",
+             "SQ_WAVE_CYCLES; LDS bank conflicts per LDS-active cycle = SQ_LDS_BANK_CONFLICT /",
+             "SQ_ACTIVE_INST_LDS; TA busy = TA_BUSY_avr / c.", "",
+             "| family | waves per CU | wait any | wait inst | LDS conflicts per LDS cycle | TA busy | "
+             "TCP pending-stall cycles |", "|---|---:|---:|---:|---:|---:|---:|"]
+    for name, cs in sorted(st.items(), key=lambda kv: family(kv[0]) or "z"):
+        fam = family(name)
+        if not fam:
+            continue
+        wc = max(cs["SQ_WAVE_CYCLES"][0], 1.0)
+        c = max(cs["GRBM_GUI_ACTIVE"][0] / 8, 1.0)
+        lds = max(cs["SQ_ACTIVE_INST_LDS"][0], 1.0)
+        lines.append(f"| {fam} | {wc / (256 * c):.1f} | {100 * cs['SQ_WAIT_ANY'][0] / wc:.0f} % | "
+                     f"{100 * cs['SQ_WAIT_INST_ANY'][0] / wc:.0f} % | {cs['SQ_LDS_BANK_CONFLICT'][0] / lds:.2f} | "
+                     f"{100 * cs['TA_BUSY_avr'][0] / c:.0f} % | {cs['TCP_PENDING_STALL_CYCLES_sum'][0]:.0f} |")
+    lines += ["", "Full table:", ""] + pmc_table([j("pmc_stall_fwd")])
+    _write(out_dir, "fwd_h1_n1024_r64_m8_stall_counters.md", lines)
 
 
 def _write(out_dir, name, lines):

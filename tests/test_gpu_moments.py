@@ -1,9 +1,11 @@
 """Ensemble moments taken inside the forward pass (Sec. 3.3): a plan bound to
 a Moments buffer adds every forward call's output fields to it, inside the
-final inverse row transform where the pass ends with one.  The fields must
-equal an unbound plan's and the sums a separate moment pass over them, bit for
-bit, over chunk layouts with empty, uneven and multi-row chunks; the finalized
-statistics must match the FP64 oracle's."""
+final inverse row transform where the pass ends with one.  The sums must be
+those of a separate moment pass over the call's output bit for bit, over
+chunk layouts with empty, uneven and multi-row chunks; the output equals an
+unbound plan's to within rounding (its final transform runs in another
+kernel, whose multiply-adds the compiler may fuse differently); the
+finalized statistics must match the FP64 oracle's."""
 import numpy as np
 import pytest
 import torch
@@ -79,8 +81,8 @@ def test_fused_moments_bitwise(api, n, r, case, shared):
     for seed in (3, 4):  # the second call adds to non-zero sums
         a = fused.propagate(u, seed=seed)
         b = plain.propagate(u, seed=seed)
-        assert torch.equal(a, b)
-        mp.add(b)
+        assert float((a - b).abs().max()) <= 1e-6 * float(b.abs().max())
+        mp.add(a)
     torch.cuda.synchronize()
     assert mf.count == mp.count == 2 * r
     assert torch.equal(mf.buf, mp.buf)
@@ -102,8 +104,8 @@ def test_fused_moments_ar_step(api):
     for t in (1, 2):
         a = fused.evolve_propagate(sf, 21, t, 0.95, 0.4, -0.25, u_in=u)
         b = plain.evolve_propagate(sp, 21, t, 0.95, 0.4, -0.25, u_in=u)
-        assert torch.equal(a, b)
-        mp.add(b)
+        assert float((a - b).abs().max()) <= 1e-6 * float(b.abs().max())
+        mp.add(a)
     torch.cuda.synchronize()
     assert torch.equal(mf.buf, mp.buf) and mf.count == 2 * path.realizations
 
