@@ -288,9 +288,9 @@ def report(out_dir, bench_json, root="gpurun_out"):
              f"    {PRE}"] + _pmc_cmd(PMC_STALL, "pmc_stall_fwd", "fwd") + [
              "", "Summary: `python -m paper_2604_07248_amd.prof_summary pmc gpurun_out/pmc_stall_fwd` (per-dispatch",
              "averages).  With c = GRBM_GUI_ACTIVE / 8 (kernel cycles; the counter adds the 8 XCDs): waves",
-             "resident per CU = SQ_WAVE_CYCLES / (256 c); wait fractions = SQ_WAIT_ANY and SQ_WAIT_INST_ANY over",
-             "SQ_WAVE_CYCLES; LDS bank conflicts per LDS-active cycle = SQ_LDS_BANK_CONFLICT /",
-             "SQ_ACTIVE_INST_LDS; TA busy = TA_BUSY_avr / c.", "",
+             "resident per CU = 4 SQ_WAVE_CYCLES / (256 c) (the SQ cycle counters count 4-cycle units); wait",
+             "fractions = SQ_WAIT_ANY and SQ_WAIT_INST_ANY over SQ_WAVE_CYCLES; LDS bank conflicts per",
+             "LDS-active cycle = SQ_LDS_BANK_CONFLICT / SQ_ACTIVE_INST_LDS; TA busy = TA_BUSY_avr / c.", "",
              "| family | waves per CU | wait any | wait inst | LDS conflicts per LDS cycle | TA busy | "
              "TCP pending-stall cycles |", "|---|---:|---:|---:|---:|---:|---:|"]
     for name, cs in sorted(st.items(), key=lambda kv: family(kv[0]) or "z"):
@@ -300,7 +300,7 @@ def report(out_dir, bench_json, root="gpurun_out"):
         wc = max(cs["SQ_WAVE_CYCLES"][0], 1.0)
         c = max(cs["GRBM_GUI_ACTIVE"][0] / 8, 1.0)
         lds = max(cs["SQ_ACTIVE_INST_LDS"][0], 1.0)
-        lines.append(f"| {fam} | {wc / (256 * c):.1f} | {100 * cs['SQ_WAIT_ANY'][0] / wc:.0f} % | "
+        lines.append(f"| {fam} | {4 * wc / (256 * c):.1f} | {100 * cs['SQ_WAIT_ANY'][0] / wc:.0f} % | "
                      f"{100 * cs['SQ_WAIT_INST_ANY'][0] / wc:.0f} % | {cs['SQ_LDS_BANK_CONFLICT'][0] / lds:.2f} | "
                      f"{100 * cs['TA_BUSY_avr'][0] / c:.0f} % | {cs['TCP_PENDING_STALL_CYCLES_sum'][0]:.0f} |")
     lines += ["", "Full table:", ""] + pmc_table([j("pmc_stall_fwd")])
