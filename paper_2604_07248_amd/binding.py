@@ -10,7 +10,8 @@ import os
 from ctypes import POINTER, c_char_p, c_double, c_float, c_int32, c_int64, c_size_t, c_uint32, c_uint64, c_void_p
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libturpy.so")
+# TURPY_LIBRARY names another build to load (the tests load the LDS-poison build this way).
+LIB_PATH = os.environ.get("TURPY_LIBRARY") or os.path.join(HERE, "libturpy.so")
 
 OK, E_INVALID, E_UNSUPPORTED, E_ALIASING, E_WORKSPACE, E_HIP, E_CAPACITY, E_NONFINITE = range(8)
 CN2_UNIFORM, CN2_HUFNAGEL_VALLEY, CN2_TABLE = 0, 1, 2

@@ -7,6 +7,22 @@
 
 namespace turpy {
 
+// Poisoned-LDS test builds (TURPY_LDS_POISON, libturpy_poison.so): every LDS
+// array is filled with all-ones words (NaN as float and as double) before a
+// kernel uses it, so a read of LDS that no thread wrote turns the result into
+// NaN.  Other builds compile the macro to nothing.
+#ifdef TURPY_LDS_POISON
+template <class T, size_t S>
+__device__ __forceinline__ void poison_lds(T (&arr)[S]) {
+  uint32_t* w = reinterpret_cast<uint32_t*>(arr);
+  for (size_t i = threadIdx.x; i < sizeof(arr) / sizeof(uint32_t); i += blockDim.x) w[i] = 0xFFFFFFFFu;
+  __syncthreads();
+}
+#define TURPY_LDS_INIT(arr) ::turpy::poison_lds(arr)
+#else
+#define TURPY_LDS_INIT(arr) ((void)0)
+#endif
+
 // Global load of a complex value, with the non-temporal (nt) cache policy
 // when NT is set.
 typedef float float2_nt __attribute__((ext_vector_type(2)));

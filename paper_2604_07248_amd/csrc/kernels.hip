@@ -69,6 +69,7 @@ __device__ __forceinline__ void row_pass_body(const RowArgs& a) {
   constexpr int G = row_groups<N>();
   constexpr bool WV = T <= 64;  // each row's transform lives in one wavefront
   __shared__ float2 smem[G * RowLds::words(N)];
+  TURPY_LDS_INIT(smem);
   const int g = threadIdx.x / T;
   const int t = threadIdx.x % T;
   const int i0 = blockIdx.x * G + g;
@@ -233,6 +234,7 @@ __device__ __forceinline__ void row_pair_body(const RowArgs& a) {
   constexpr int HALF = G * T;
   constexpr bool WV = T <= 64;  // each row's transform lives in one wavefront
   __shared__ float2 smem[2 * G * RowLds::words(N)];
+  TURPY_LDS_INIT(smem);
   const int role = threadIdx.x / HALF;
   const int g = (threadIdx.x % HALF) / T;
   const int t = threadIdx.x % T;
@@ -467,7 +469,9 @@ __device__ __forceinline__ void row_relay_body(const RowArgs& a) {
   constexpr bool WV = T <= 64;  // each row's transform lives in one wavefront
   static_assert(HALF % 64 == 0 && 2 * G <= N, "a relay worker is whole waves over half the block's rows");
   __shared__ float2 smem[2 * G * RowLds::words(N)];
+  TURPY_LDS_INIT(smem);
   __shared__ float handoff_rows[G * N];
+  TURPY_LDS_INIT(handoff_rows);
   __shared__ float2 tw_lds[N];
   const int w = threadIdx.x / HALF;
   const int g = (threadIdx.x % HALF) / T;
@@ -639,6 +643,7 @@ __device__ __forceinline__ void col_pass_body(const ColArgs& a) {
   constexpr int T = N / kE;
   constexpr int STRIPS = N / K;
   __shared__ float2 smem[ColLds<K>::words(N)];
+  TURPY_LDS_INIT(smem);
   int strip;
   int64_t r;
   col_tile(blockIdx.x, gridDim.x, STRIPS, a.R, &strip, &r);
@@ -648,6 +653,7 @@ __device__ __forceinline__ void col_pass_body(const ColArgs& a) {
   const ColLds<K> lds{smem, c};
   __shared__ float2 tw_lds[N];
   __shared__ float2 h_lds[N];
+  TURPY_LDS_INIT(h_lds);
   for (int i = threadIdx.x; i < N; i += blockDim.x) h_lds[i] = a.table[i];
   const float2* chirp = h_lds;
   const float2* tw = stage_twiddles<N>(tw_lds, a.tw);
@@ -682,6 +688,7 @@ __device__ __forceinline__ void synth_col_body(const SynthArgs& a) {
   constexpr int T = N / kE;
   constexpr int STRIPS = N / K;
   __shared__ float2 smem[ColLds<K>::words(N)];
+  TURPY_LDS_INIT(smem);
   const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
   const int strip = b % STRIPS;
   const int64_t j = b / STRIPS;
@@ -767,6 +774,7 @@ void synth_col_kernel(SynthArgs a) { synth_col_body<N, K, R2SEL>(a); }
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void sh_body(const ShArgs& a) {
   __shared__ float2 coef[24];
+  TURPY_LDS_INIT(coef);
   const int64_t j = blockIdx.x;
   const int s = blockIdx.y;
   const int l = threadIdx.x;
@@ -926,6 +934,7 @@ __global__ __launch_bounds__(moment_chunks(N) * (N / kE)) void row_moments_kerne
   constexpr bool WV = T <= 64;  // each row's transform lives in one wavefront
   static_assert(2 * N <= 2 * RowLds::words(N), "a chunk's partial sums fit in its transform's LDS");
   __shared__ float2 smem[C * RowLds::words(N)];
+  TURPY_LDS_INIT(smem);
   __shared__ float2 tw_lds[N];
   const int c = threadIdx.x / T;
   const int t = threadIdx.x % T;
@@ -1035,6 +1044,7 @@ __device__ __forceinline__ float mean_intensity(const FinalizeArgs& a, int64_t p
 __global__ __launch_bounds__(1024) void finalize_kernel(FinalizeArgs a) {
   constexpr int NT = 1024;
   __shared__ double red[NT];
+  TURPY_LDS_INIT(red);
   const int n = a.n;
   const int64_t np = static_cast<int64_t>(n) * n;
   double m1_sum = 0, r2m1 = 0, m1_max = 0, m1f_sum = 0;

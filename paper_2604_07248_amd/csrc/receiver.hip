@@ -36,6 +36,7 @@ __global__ __launch_bounds__(row_block<N>()) void recv_row_in_kernel(RecvArgs a)
   constexpr int T = N / kE;
   constexpr int G = row_groups<N>();
   __shared__ float2 smem[G * RowLds::words(N)];
+  TURPY_LDS_INIT(smem);
   const int g = threadIdx.x / T, t = threadIdx.x % T;
   const int i0 = blockIdx.x * G + g;
   const int64_t b = blockIdx.y;
@@ -63,6 +64,7 @@ __global__ __launch_bounds__(col_block<N>()) void recv_col_kernel(RecvArgs a) {
   constexpr int K = col_width<N>();
   constexpr int STRIPS = N / K;
   __shared__ float2 smem[ColLds<K>::words(N)];
+  TURPY_LDS_INIT(smem);
   const uint32_t bid = xcd_remap(blockIdx.x, gridDim.x);
   const int strip = bid % STRIPS;
   const int64_t b = bid / STRIPS;
@@ -101,6 +103,7 @@ __global__ __launch_bounds__(col_block<N>()) void recv_col_grad_kernel(RecvArgs 
   constexpr int K = col_width<N>();
   constexpr int STRIPS = N / K;
   __shared__ float2 smem[ColLds<K>::words(N)];
+  TURPY_LDS_INIT(smem);
   const int strip = blockIdx.x % STRIPS;
   const int chunk = blockIdx.x / STRIPS;
   const int c = threadIdx.x % K, t = threadIdx.x / K;
@@ -153,6 +156,7 @@ __global__ __launch_bounds__(row_block<N>()) void recv_row_grad_kernel(RecvArgs 
   constexpr int T = N / kE;
   constexpr int G = row_groups<N>();
   __shared__ float2 smem[G * RowLds::words(N)];
+  TURPY_LDS_INIT(smem);
   const int g = threadIdx.x / T, t = threadIdx.x % T;
   const int i0 = blockIdx.x * G + g;
   const int chunk = blockIdx.y;

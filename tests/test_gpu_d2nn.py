@@ -69,7 +69,8 @@ def test_training_gradients_match_oracle(mods):
     e_loss = abs(float(loss) - ref_loss) / abs(ref_loss)
     e1, e2 = rel_l2(g1, r1), rel_l2(g2, r2)
     say(f"[d2nn] loss {float(loss):.6f} vs {ref_loss:.6f} ({e_loss:.1e}); dtheta1 {e1:.2e} dtheta2 {e2:.2e}")
-    assert e_loss < TOL and e1 < 1e-3 and e2 < 1e-3
+    # the mask gradients to the adjoint bound of every other test (measured: a few 1e-6)
+    assert e_loss < TOL and e1 < TOL and e2 < TOL
 
     # central differences (FP64 oracle) on central 8x8 subsets, 4 realizations
     sub = slice(p.n // 2 - 4, p.n // 2 + 4)
