@@ -1199,6 +1199,17 @@ __global__ __launch_bounds__(256) void copy_kernel(const float2* in, int64_t in_
 constexpr int kRowWaves = 3;
 constexpr bool row_waves_built(int n, int w) { return w == kRowWaves || (n >= 256 && (w == 2 || w == 4)); }
 
+// A forward screen pass of a single realization without checkpoints, where
+// the relay schedule is not built (N > 1024): the pair schedule would leave
+// half of every block transforming rows nobody keeps, so one group of threads
+// per row takes it (the serving mix's 252 instances at N = 2048: 274 -> 213 ms
+// forward; at N <= 1024 the relay schedule stays, and with checkpoints and in
+// the adjoint the pair schedule).
+template <int N>
+constexpr bool solo_forward(int64_t R, int backward, const void* ckpt) {
+  return N > 1024 && R == 1 && !backward && !ckpt;
+}
+
 // The relay kernel for forward passes with synthesised screens and no
 // checkpoint output, where its workers are whole waves and it keeps three
 // waves per SIMD (N <= 1024); false: not launched.  With checkpoint writes
@@ -1250,8 +1261,9 @@ hipError_t row_launch(const RowArgs& a, int64_t pairs, hipStream_t s) {
   dim3 block(row_block<N>());
   if (a.screen_mode == ROW_NO_SCREEN)
     hipLaunchKernelGGL((row_pass_kernel<N, ROW_NO_SCREEN, false>), grid, block, 0, s, a);
-  else if (a.phase_out || (pair_rows<N>() * (N / kE)) % 64 != 0) {
-    // screen output, or grids too small for the two halves to sit in separate waves
+  else if (a.phase_out || (pair_rows<N>() * (N / kE)) % 64 != 0 || solo_forward<N>(a.R, a.backward, a.ckpt_out)) {
+    // screen output, grids too small for the two halves to sit in separate
+    // waves, or a single realization on the pair schedule
     if (a.screen_mode == ROW_SCRATCH && !a.backward)
       hipLaunchKernelGGL((row_pass_kernel<N, ROW_SCRATCH, false>), grid, block, 0, s, a);
     else if (a.screen_mode == ROW_SCRATCH)
@@ -1457,7 +1469,9 @@ hipError_t row_group_launch(const RowArgs& proto, const RowArgs* tab, uint32_t c
                             const GroupCall& g, hipStream_t s) {
   constexpr int G = row_groups<N>();
   const uint32_t P = static_cast<uint32_t>(pairs);
-  const bool small = (pair_rows<N>() * (N / kE)) % 64 != 0;  // halves that are not whole waves
+  // halves that are not whole waves, or a single realization on the pair
+  // schedule: one group of threads per row (as row_launch chooses)
+  const bool small = (pair_rows<N>() * (N / kE)) % 64 != 0 || solo_forward<N>(proto.R, proto.backward, g.ck);
   if (proto.phase_out) return hipErrorInvalidValue;
   if (proto.screen_mode == ROW_NO_SCREEN) {
     hipLaunchKernelGGL((row_pass_group_kernel<N, ROW_NO_SCREEN>), dim3(N / G, P, count), dim3(row_block<N>()), 0,
