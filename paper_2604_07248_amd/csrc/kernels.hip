@@ -1199,15 +1199,17 @@ __global__ __launch_bounds__(256) void copy_kernel(const float2* in, int64_t in_
 constexpr int kRowWaves = 3;
 constexpr bool row_waves_built(int n, int w) { return w == kRowWaves || (n >= 256 && (w == 2 || w == 4)); }
 
-// A forward screen pass of a single realization without checkpoints, where
-// the relay schedule is not built (N > 1024): the pair schedule would leave
-// half of every block transforming rows nobody keeps, so one group of threads
-// per row takes it (the serving mix's 252 instances at N = 2048: 274 -> 213 ms
-// forward; at N <= 1024 the relay schedule stays, and with checkpoints and in
-// the adjoint the pair schedule).
+// A forward screen pass of a single realization where the relay schedule is
+// not built (N > 1024): the pair schedule would leave half of every block
+// transforming rows nobody keeps, so one group of threads per row takes it
+// (serving mix: the 252 instances at N = 2048 274 -> 213 ms forward; all 4096
+// forward + adjoint with checkpoints 3.11 -> 2.94 s).  At N <= 1024 the relay
+// schedule stays, and in the adjoint the pair schedule (one group per row
+// measured 3.11 -> 3.28 s there).
 template <int N>
 constexpr bool solo_forward(int64_t R, int backward, const void* ckpt) {
-  return N > 1024 && R == 1 && !backward && !ckpt;
+  (void)ckpt;
+  return N > 1024 && R == 1 && !backward;
 }
 
 // The relay kernel for forward passes with synthesised screens and no

@@ -263,11 +263,20 @@ def report(out_dir, bench_json, root="gpurun_out"):
         lines += traffic(j(f"pmc_FETCH_SIZE_{leg}"), j(f"pmc_WRITE_SIZE_{leg}"), j("pmc_FETCH_SIZE_copy"),
                          j("pmc_WRITE_SIZE_copy"), 536870912, leg)
         _write(out_dir, f"{leg}_h1_n1024_r64_m8_hbm_traffic.md", lines)
-    # VALU and wave counters
-    sq = pmc_by_kernel(j("pmc_sq_fwd"))
-    lines = ["# Wave and VALU counters: forward headline workload (N=1024, R=64, M=8)", "", "Command:", "",
-             f"    {PRE}"] + _pmc_cmd(PMC_SQ, "pmc_sq_fwd", "fwd") + [
-             "", "Summary: `python -m paper_2604_07248_amd.prof_summary pmc gpurun_out/pmc_sq_fwd` (per-dispatch",
+    for leg, title in (("fwd", "forward"), ("fwdbwd", "forward + adjoint")):
+        _sq_summary(out_dir, j, leg, title)
+        _stall_summary(out_dir, j, leg, title)
+
+
+def _sq_summary(out_dir, j, leg, title):
+    """VALU and wave counters of one leg."""
+    d = f"pmc_sq_{leg}"
+    if not os.path.isdir(j(d)):
+        return
+    sq = pmc_by_kernel(j(d))
+    lines = [f"# Wave and VALU counters: {title}, headline workload (N=1024, R=64, M=8)", "", "Command:", "",
+             f"    {PRE}"] + _pmc_cmd(PMC_SQ, d, leg) + [
+             "", f"Summary: `python -m paper_2604_07248_amd.prof_summary pmc gpurun_out/{d}` (per-dispatch",
              "averages).  VALU busy = SQ_INSTS_VALU x 4 cycles (a wave64 FP32 instruction on a 16-lane SIMD) /",
              "(1024 SIMDs x GRBM_GUI_ACTIVE / 8 XCDs).", "",
              "| family | waves | VALU instr per wave | LDS instr per wave | kernel cycles | VALU busy |",
@@ -280,13 +289,19 @@ def report(out_dir, bench_json, root="gpurun_out"):
         cyc = cs["GRBM_GUI_ACTIVE"][0] / 8
         lines.append(f"| {fam} | {waves:.0f} | {valu / waves:.0f} | {lds / waves:.0f} | {cyc:.0f} | "
                      f"{100 * valu * 4 / (1024 * cyc):.0f} % |")
-    lines += ["", "Full table:", ""] + pmc_table([j("pmc_sq_fwd")])
-    _write(out_dir, "fwd_h1_n1024_r64_m8_sq_counters.md", lines)
-    # stall and occupancy counters
-    st = pmc_by_kernel(j("pmc_stall_fwd"))
-    lines = ["# Stall and occupancy counters: forward headline workload (N=1024, R=64, M=8)", "", "Command:", "",
-             f"    {PRE}"] + _pmc_cmd(PMC_STALL, "pmc_stall_fwd", "fwd") + [
-             "", "Summary: `python -m paper_2604_07248_amd.prof_summary pmc gpurun_out/pmc_stall_fwd` (per-dispatch",
+    lines += ["", "Full table:", ""] + pmc_table([j(d)])
+    _write(out_dir, f"{leg}_h1_n1024_r64_m8_sq_counters.md", lines)
+
+
+def _stall_summary(out_dir, j, leg, title):
+    """Stall and occupancy counters of one leg."""
+    d = f"pmc_stall_{leg}"
+    if not os.path.isdir(j(d)):
+        return
+    st = pmc_by_kernel(j(d))
+    lines = [f"# Stall and occupancy counters: {title}, headline workload (N=1024, R=64, M=8)", "", "Command:", "",
+             f"    {PRE}"] + _pmc_cmd(PMC_STALL, d, leg) + [
+             "", f"Summary: `python -m paper_2604_07248_amd.prof_summary pmc gpurun_out/{d}` (per-dispatch",
              "averages).  With c = GRBM_GUI_ACTIVE / 8 (kernel cycles; the counter adds the 8 XCDs): waves",
              "resident per CU = 4 SQ_WAVE_CYCLES / (256 c) (the SQ cycle counters count 4-cycle units); wait",
              "fractions = SQ_WAIT_ANY and SQ_WAIT_INST_ANY over SQ_WAVE_CYCLES; LDS bank conflicts per",
@@ -303,8 +318,8 @@ def report(out_dir, bench_json, root="gpurun_out"):
         lines.append(f"| {fam} | {4 * wc / (256 * c):.1f} | {100 * cs['SQ_WAIT_ANY'][0] / wc:.0f} % | "
                      f"{100 * cs['SQ_WAIT_INST_ANY'][0] / wc:.0f} % | {cs['SQ_LDS_BANK_CONFLICT'][0] / lds:.2f} | "
                      f"{100 * cs['TA_BUSY_avr'][0] / c:.0f} % | {cs['TCP_PENDING_STALL_CYCLES_sum'][0]:.0f} |")
-    lines += ["", "Full table:", ""] + pmc_table([j("pmc_stall_fwd")])
-    _write(out_dir, "fwd_h1_n1024_r64_m8_stall_counters.md", lines)
+    lines += ["", "Full table:", ""] + pmc_table([j(d)])
+    _write(out_dir, f"{leg}_h1_n1024_r64_m8_stall_counters.md", lines)
 
 
 def _write(out_dir, name, lines):
