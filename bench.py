@@ -646,7 +646,7 @@ def main():
                         "workload": w3.name + " (32 sequences, alpha=0.99, shift 0.5 px/step)",
                         "seconds_for_1000_steps": 1000 * sec, "kernels": ktab, "dominant": dom,
                         "graph_replay_ms_per_step": 1e3 * sec_graph,
-                        "two_calls_ms_per_step": 1e3 * sec_two,
+                        "two_calls_ms_per_step": 1e3 * sec_two, "launch_config": plan3.config,
                         "graph_seconds_for_1000_steps": 1000 * sec_graph,
                         "path_effective_GBps": sum(step_bytes(p3, "ar").values()) / sec / 1e9}
         plan3.close()

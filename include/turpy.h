@@ -476,7 +476,10 @@ typedef enum {
   TURPY_TUNE_COL_AS_TABLE = 2,  /* column pass, angular spectrum with evanescent bins   */
   TURPY_TUNE_SYNTH = 3,         /* column half of the screen synthesis                  */
   TURPY_TUNE_ROW_FWD = 4,       /* forward screen row pass (no checkpoints)             */
-  TURPY_TUNE_ROW_BWD = 5        /* adjoint screen row pass                              */
+  TURPY_TUNE_ROW_BWD = 5,       /* adjoint screen row pass                              */
+  TURPY_TUNE_SYNTH_AR = 6       /* the synthesis with the AR step fused into it
+                                   (turpy_evolve_propagate): its own choice, since
+                                   the best strip differs from the plain synthesis's */
 } turpy_tune_kernel;
 
 #define TURPY_TUNE_FORCE 1u     /* measure even when the cache holds the key */
@@ -500,12 +503,14 @@ typedef struct turpy_launch_config {
   int32_t synth_width, synth_radix; /* column half of the synthesis              */
   int32_t row_waves;                /* forward screen row passes                 */
   int32_t row_waves_bwd;            /* adjoint screen row passes                 */
+  int32_t ar_width, ar_radix;       /* the synthesis with the AR step fused      */
 } turpy_launch_config;
 
 /* Time every launch configuration of the plan's column pass (its
  * transfer-function kind, distance 0, all R planes in place), and, when the
- * plan has screens, of its synthesis (all ceil(R/2) scratch planes) and of
- * its forward and adjoint row passes for screen 0 (workspace planes), with
+ * plan has screens, of its synthesis (all ceil(R/2) scratch planes; once
+ * plain and once with the AR step fused, on workspace planes as the state)
+ * and of its forward and adjoint row passes for screen 0 (workspace planes), with
  * HIP events on `stream`, and keep the fastest of each in the plan and in the
  * cache.  A key already in the cache is applied without measuring unless
  * flags has TURPY_TUNE_FORCE.  Each configuration: one launch, then 3

@@ -112,7 +112,8 @@ class Plan:
     # -- launch shapes -------------------------------------------------------
     def tune(self, force=False):
         """Time the launch configurations of the column pass, the synthesis
-        and the screen row passes (turpy_plan_tune; synchronises) and keep the
+        (plain and with the AR step fused) and the screen row passes
+        (turpy_plan_tune; synchronises) and keep the
         fastest, or take them from the tuning cache.  Returns the plan's
         launch configuration (config)."""
         size = B.workspace_size(self.handle, B.OP_TUNE)
@@ -125,7 +126,8 @@ class Plan:
     @property
     def config(self):
         """Every launch choice: col_width, col_radix, synth_width, synth_radix,
-        row_waves, row_waves_bwd."""
+        row_waves, row_waves_bwd, ar_width, ar_radix (the synthesis with the AR
+        step fused)."""
         return B.plan_config(self.handle)
 
     def set_config(self, **choices):

@@ -21,8 +21,8 @@ ALLOW_ALIASING = 1
 SCREEN_CHECKPOINTS = 2
 CHECK_FINITE = 4
 OP_SCREEN_GENERATE, OP_PROPAGATE, OP_PROPAGATE_BACKWARD, OP_EVOLVE, OP_PROPAGATE_BACKWARD_REVERSIBLE, OP_TUNE = range(6)
-TUNE_COL_FRESNEL, TUNE_COL_ANGULAR, TUNE_COL_AS_TABLE, TUNE_SYNTH, TUNE_ROW_FWD, TUNE_ROW_BWD = range(6)
-TUNE_KERNELS = ("col_fresnel", "col_angular", "col_as_table", "synth", "row_fwd", "row_bwd")
+TUNE_COL_FRESNEL, TUNE_COL_ANGULAR, TUNE_COL_AS_TABLE, TUNE_SYNTH, TUNE_ROW_FWD, TUNE_ROW_BWD, TUNE_SYNTH_AR = range(7)
+TUNE_KERNELS = ("col_fresnel", "col_angular", "col_as_table", "synth", "row_fwd", "row_bwd", "synth_ar")
 TUNE_FORCE = 1
 
 # Every symbol the header declares (checked by the CPU tests).
@@ -65,7 +65,7 @@ class CTuneEntry(ctypes.Structure):
 
 class CLaunchConfig(ctypes.Structure):
     _fields_ = [("col_width", c_int32), ("col_radix", c_int32), ("synth_width", c_int32), ("synth_radix", c_int32),
-                ("row_waves", c_int32), ("row_waves_bwd", c_int32)]
+                ("row_waves", c_int32), ("row_waves_bwd", c_int32), ("ar_width", c_int32), ("ar_radix", c_int32)]
 
 
 class CCn2Profile(ctypes.Structure):
@@ -357,7 +357,8 @@ def plan_set_widths(handle, col_width, synth_width):
     check(lib().turpy_plan_set_widths(handle, col_width, synth_width))
 
 
-CONFIG_FIELDS = ("col_width", "col_radix", "synth_width", "synth_radix", "row_waves", "row_waves_bwd")
+CONFIG_FIELDS = ("col_width", "col_radix", "synth_width", "synth_radix", "row_waves", "row_waves_bwd", "ar_width",
+                 "ar_radix")
 
 
 def plan_config(handle):

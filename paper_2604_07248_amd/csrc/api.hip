@@ -1278,6 +1278,7 @@ int col_kernel_id(const turpy_plan* pl) {
 TuneKey col_key(const turpy_plan* pl) { return TuneKey{pl->arch, col_kernel_id(pl), pl->n, bit_length(pl->R)}; }
 TuneKey synth_key(const turpy_plan* pl) { return TuneKey{pl->arch, TURPY_TUNE_SYNTH, pl->n, bit_length(pl->P)}; }
 TuneKey row_key(const turpy_plan* pl, int kernel) { return TuneKey{pl->arch, kernel, pl->n, bit_length(pl->P)}; }
+TuneKey ar_key(const turpy_plan* pl) { return TuneKey{pl->arch, TURPY_TUNE_SYNTH_AR, pl->n, bit_length(pl->P)}; }
 
 bool cached(const TuneKey& k, turpy_tune_entry* e) {
   std::lock_guard<std::mutex> lock(g_tune_mu);
@@ -1302,6 +1303,10 @@ void apply_cached_widths(turpy_plan* pl) {
   if (cached(synth_key(pl), &e)) {
     pl->synth_width = e.width;
     pl->synth_radix = e.radix;
+  }
+  if (cached(ar_key(pl), &e)) {
+    pl->ar_width = e.width;
+    pl->ar_radix = e.radix;
   }
   if (cached(row_key(pl, TURPY_TUNE_ROW_FWD), &e)) pl->row_waves = e.waves;
   if (cached(row_key(pl, TURPY_TUNE_ROW_BWD), &e)) pl->row_waves_bwd = e.waves;
@@ -1418,9 +1423,11 @@ turpy_status turpy_plan_tune(turpy_plan* pl, uint32_t flags, void* ws, size_t ws
   const bool screens = pl->M > 0;
   const bool need_col = force || !cached(ck, &e);
   const bool need_synth = screens && (force || !cached(sk, &e));
+  const TuneKey ak = ar_key(pl);
+  const bool need_ar = screens && (force || !cached(ak, &e));
   const bool need_rf = screens && (force || !cached(rf, &e));
   const bool need_rb = screens && (force || !cached(rb, &e));
-  if (need_col || need_synth || need_rf || need_rb)
+  if (need_col || need_synth || need_ar || need_rf || need_rb)
     TURPY_HIP(hipMemsetAsync(ws, 0, pl->ws_tune(), st), "plan_tune: clear workspace");
   const Ws wsp = carve(pl, ws);
   const int n = pl->n;
@@ -1438,6 +1445,21 @@ turpy_status turpy_plan_tune(turpy_plan* pl, uint32_t flags, void* ws, size_t ws
     SynthArgs a = synth_args(pl, 0, 0, 0, nullptr, wsp);
     a.t_dev = nullptr;
     if (turpy_status s = tune_key(sk, strip_choices(n), {default_synth_width(n), 0, 0}, st,
+                                  [&](const LaunchChoice& k) {
+                                    a.width = k.width;
+                                    a.radix = k.radix;
+                                    return launch_synth(n, a, st);
+                                  }))
+      return s;
+  }
+  if (need_ar) {
+    // the AR step of screen 0 with the workspace's R planes as the state
+    // (one screen per pair: the state of pair j at plane j)
+    const EvolveStep ev{0.99, 0.5, 0.25};
+    SynthArgs a = synth_args(pl, 0, 1, 0, wsp.gbuf, wsp, &ev);
+    a.t_dev = nullptr;
+    a.M = 1;
+    if (turpy_status s = tune_key(ak, strip_choices(n), {default_synth_width(n), 0, 0}, st,
                                   [&](const LaunchChoice& k) {
                                     a.width = k.width;
                                     a.radix = k.radix;
@@ -1511,16 +1533,18 @@ turpy_status turpy_plan_config(const turpy_plan* pl, turpy_launch_config* out) {
   out->synth_radix = pl->synth_radix;
   out->row_waves = pl->row_waves ? pl->row_waves : 3;
   out->row_waves_bwd = pl->row_waves_bwd ? pl->row_waves_bwd : 3;
+  out->ar_width = pl->ar_width ? pl->ar_width : default_synth_width(pl->n);
+  out->ar_radix = pl->ar_radix;
   return TURPY_OK;
 }
 
 turpy_status turpy_plan_set_config(turpy_plan* pl, const turpy_launch_config* c) {
   if (!pl || !c) return fail(TURPY_E_INVALID, "plan_set_config: NULL argument");
   const int n = pl->n;
-  for (int32_t k : {c->col_width, c->synth_width})
+  for (int32_t k : {c->col_width, c->synth_width, c->ar_width})
     if (k != 0 && !strip_fits_rt(n, k))
       return fail(TURPY_E_INVALID, "plan_set_config: %d columns per block is not built for n=%d", k, n);
-  for (int32_t r : {c->col_radix, c->synth_radix})
+  for (int32_t r : {c->col_radix, c->synth_radix, c->ar_radix})
     if (!radix_built_rt(n, r)) return fail(TURPY_E_INVALID, "plan_set_config: radix %d is not built for n=%d", r, n);
   for (int32_t w : {c->row_waves, c->row_waves_bwd})
     if (w != 0 && !waves_built_rt(n, w))
@@ -1531,6 +1555,8 @@ turpy_status turpy_plan_set_config(turpy_plan* pl, const turpy_launch_config* c)
   pl->synth_radix = c->synth_radix;
   pl->row_waves = c->row_waves;
   pl->row_waves_bwd = c->row_waves_bwd;
+  pl->ar_width = c->ar_width;
+  pl->ar_radix = c->ar_radix;
   return TURPY_OK;
 }
 
@@ -1551,7 +1577,7 @@ turpy_status turpy_tune_cache_put(const turpy_tune_entry* entries, int32_t count
   if (count < 0 || (count > 0 && !entries)) return fail(TURPY_E_INVALID, "tune_cache_put: NULL entries");
   for (int32_t i = 0; i < count; ++i) {
     const turpy_tune_entry& e = entries[i];
-    if (e.kernel < TURPY_TUNE_COL_FRESNEL || e.kernel > TURPY_TUNE_ROW_BWD)
+    if (e.kernel < TURPY_TUNE_COL_FRESNEL || e.kernel > TURPY_TUNE_SYNTH_AR)
       return fail(TURPY_E_INVALID, "tune_cache_put: entry %d has unknown kernel %d", i, e.kernel);
     if (e.n < 16 || e.n > 2048 || !pow2(e.n))
       return fail(TURPY_E_INVALID, "tune_cache_put: entry %d: n=%d is not built", i, e.n);

@@ -138,6 +138,8 @@ struct turpy_plan {
   // second-pass radix of their transforms (0: the default plan) and the
   // occupancy hints of the forward and adjoint screen row passes (0: default)
   int col_radix = 0, synth_radix = 0, row_waves = 0, row_waves_bwd = 0;
+  // strip width and radix of the synthesis with the AR step fused (0: built-in)
+  int ar_width = 0, ar_radix = 0;
   bool screen_ck = false;        // TURPY_SCREEN_CHECKPOINTS: checkpoints keep the screens' column halves
   std::string arch;              // device architecture (tuning-cache key)
 
@@ -246,8 +248,8 @@ inline SynthArgs synth_args(const turpy_plan* pl, uint64_t seed, uint32_t t, int
   a.q = pl->qexp;
   a.spectra = spectra;
   a.M = pl->M;
-  a.width = pl->synth_width;
-  a.radix = pl->synth_radix;
+  a.width = ev ? pl->ar_width : pl->synth_width;
+  a.radix = ev ? pl->ar_radix : pl->synth_radix;
   if (ev) {
     a.evolve = 1;
     a.state = const_cast<float2*>(spectra);

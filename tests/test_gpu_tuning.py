@@ -160,16 +160,17 @@ def test_tune_measures_caches_and_hands_on(api):
     keys = {(e["arch"], e["kernel"], e["n"], e["batch_class"]) for e in entries}
     # R = 8: 4 pairs
     assert keys == {(arch, "col_fresnel", 512, 4), (arch, "synth", 512, 3), (arch, "row_fwd", 512, 3),
-                    (arch, "row_bwd", 512, 3)}
+                    (arch, "row_bwd", 512, 3), (arch, "synth_ar", 512, 3)}
     for e in entries:
         assert 0 < e["us"] <= e["us_default"] * (1 + 1e-6)
-        if e["kernel"] in ("col_fresnel", "synth"):
+        if e["kernel"] in ("col_fresnel", "synth", "synth_ar"):
             assert e["configs"] == len(built(512)) * 3 and e["waves"] == 0
         else:
             assert e["configs"] == 3 and e["width"] == 0 and e["waves"] in (2, 3, 4)
     by = {e["kernel"]: e for e in entries}
     assert (cfg["col_width"], cfg["col_radix"]) == (by["col_fresnel"]["width"], by["col_fresnel"]["radix"])
     assert (cfg["synth_width"], cfg["synth_radix"]) == (by["synth"]["width"], by["synth"]["radix"])
+    assert (cfg["ar_width"], cfg["ar_radix"]) == (by["synth_ar"]["width"], by["synth_ar"]["radix"])
     assert (cfg["row_waves"], cfg["row_waves_bwd"]) == (by["row_fwd"]["waves"], by["row_bwd"]["waves"])
     assert rel_l2(plan.propagate(u0, seed=4).cpu().numpy(), ref.cpu().numpy()) < 1e-5
     # a later plan with the same keys starts from the cache; tuning it measures nothing
