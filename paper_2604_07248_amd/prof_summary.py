@@ -5,7 +5,7 @@
     python -m paper_2604_07248_amd.prof_summary pmc DIR [DIR ...]
         Per-kernel average of every counter of `--pmc ... --output-format csv` runs.
     python -m paper_2604_07248_amd.prof_summary report --bench BENCH_JSON [--out profiles]
-        All committed summaries of the standard profiling runs under gpurun_out/.
+        All summaries of the standard profiling runs under --root (the $OUT of their commands).
     python -m paper_2604_07248_amd.prof_summary traffic --fetch DIR --write DIR
             --copy-fetch DIR --copy-write DIR --copy-bytes B --leg NAME
         HBM bytes per launch of each kernel family: FETCH_SIZE and WRITE_SIZE
@@ -171,10 +171,10 @@ def load_traffic(profiles_dir, leg):
     return {}
 
 
-PRE = "cd /tmp && export TMPDIR=/tmp && R=<repository root>"
-TUNE = "--tune-cache $R/gpurun_out/tune.json --no-cpu-baseline"
+PRE = "cd /tmp && export TMPDIR=/tmp && R=<repository root> && OUT=<output directory>"
+TUNE = "--tune-cache $OUT/tune.json --no-cpu-baseline"
 
-# The standard profiling runs: (directory under gpurun_out, bench.py arguments).
+# The standard profiling runs: (directory under $OUT, bench.py arguments).
 TRACES = {
     "prof_fwd": "--only fwd --steps 10 --warmup 2",
     "prof_fwdbwd": "--only fwdbwd --steps 5 --warmup 2",
@@ -193,16 +193,16 @@ def _ev(fams, tab):
 
 
 def _trace_cmd(d):
-    return ["    rocprofv3 --kernel-trace --stats --output-format csv -d $R/gpurun_out/" + d + " -o t -- \\",
+    return ["    rocprofv3 --kernel-trace --stats --output-format csv -d $OUT/" + d + " -o t -- \\",
             f"        python $R/bench.py {TRACES[d]} {TUNE}"]
 
 
 def _pmc_cmd(counters, d, leg):
-    return [f"    timeout -s KILL 120 rocprofv3 --pmc {counters} --output-format csv -d $R/gpurun_out/{d} -o p -- \\",
+    return [f"    timeout -s KILL 120 rocprofv3 --pmc {counters} --output-format csv -d $OUT/{d} -o p -- \\",
             f"        python $R/bench.py --only {leg} --steps 3 --warmup 1 {TUNE}"]
 
 
-def report(out_dir, bench_json, root="gpurun_out"):
+def report(out_dir, bench_json, root):
     """Write the committed summaries of the standard profiling runs (the
     commands are printed in each file) into out_dir."""
     with open(bench_json) as fh:
@@ -211,14 +211,14 @@ def report(out_dir, bench_json, root="gpurun_out"):
     head = ["Commands (one MI355X; the profiler writes its temporary files under /tmp).  The default",
             "benchmark run writes the launch configuration its tuner chose; the profiled runs read it back,",
             "so that their traces hold no tuning launches:", "",
-            "    python bench.py --tune-cache gpurun_out/tune.json > gpurun_out/bench.json", f"    {PRE}"]
+            f"    {PRE}", "    python $R/bench.py --tune-cache $OUT/tune.json > $OUT/bench.json"]
     # forward kernel trace
     rows = stats_table(j("prof_fwd"))
     d = b["roofline"]
     dom_rows = [r for r in rows[2:] if f"| {d['kernel']} |" in r]
     lines = ["# Kernel trace: forward headline workload (N=1024, R=64, M=8, fresh screens)", ""] + head + \
         _trace_cmd("prof_fwd") + [
-        "", "Summary: `python -m paper_2604_07248_amd.prof_summary stats gpurun_out/prof_fwd`.  The run covers",
+        "", "Summary: `python -m paper_2604_07248_amd.prof_summary stats $OUT/prof_fwd`.  The run covers",
         "22 forward steps: 2 warm-up, 10 with every family bracketed by events, 10 timed.  Durations in",
         "microseconds.", ""] + rows + [
         "", "HIP-event averages measured inside `bench.py` (default run: 5 warm-up, 50 profiled and 50 timed "
@@ -239,7 +239,7 @@ def report(out_dir, bench_json, root="gpurun_out"):
             ("prof_uneven", "uneven_c5_serving_mix_kernel_stats.md",
              "serving mix (one wave of 256 instances, N 256-2048, R=1; grouped launches)", None, [])):
         lines = [f"# Kernel trace: {title}", ""] + head + _trace_cmd(d_) + [
-            "", f"Summary: `python -m paper_2604_07248_amd.prof_summary stats gpurun_out/{d_}`.", ""]
+            "", f"Summary: `python -m paper_2604_07248_amd.prof_summary stats $OUT/{d_}`.", ""]
         lines += stats_table(j(d_))
         if tab:
             lines += ["", "HIP-event averages inside `bench.py` (default run): " + _ev(fams, tab) + "."]
@@ -253,8 +253,8 @@ def report(out_dir, bench_json, root="gpurun_out"):
             for lg in (leg, "copy"):
                 lines += _pmc_cmd(c, f"pmc_{c}_{lg}", lg)
         lines += ["", "Summary: `python -m paper_2604_07248_amd.prof_summary traffic --fetch "
-                  f"gpurun_out/pmc_FETCH_SIZE_{leg} --write gpurun_out/pmc_WRITE_SIZE_{leg} --copy-fetch "
-                  "gpurun_out/pmc_FETCH_SIZE_copy --copy-write gpurun_out/pmc_WRITE_SIZE_copy --copy-bytes "
+                  f"$OUT/pmc_FETCH_SIZE_{leg} --write $OUT/pmc_WRITE_SIZE_{leg} --copy-fetch "
+                  "$OUT/pmc_FETCH_SIZE_copy --copy-write $OUT/pmc_WRITE_SIZE_copy --copy-bytes "
                   f"536870912 --leg {leg}`.", "",
                   "Averages over every launch of a family (the column family includes the one-plane pass 0, the",
                   "row-plain family the one-plane transforms).  On gfx950 almost every read is a 128-byte",
@@ -276,7 +276,7 @@ def _sq_summary(out_dir, j, leg, title):
     sq = pmc_by_kernel(j(d))
     lines = [f"# Wave and VALU counters: {title}, headline workload (N=1024, R=64, M=8)", "", "Command:", "",
              f"    {PRE}"] + _pmc_cmd(PMC_SQ, d, leg) + [
-             "", f"Summary: `python -m paper_2604_07248_amd.prof_summary pmc gpurun_out/{d}` (per-dispatch",
+             "", f"Summary: `python -m paper_2604_07248_amd.prof_summary pmc $OUT/{d}` (per-dispatch",
              "averages).  VALU busy = SQ_INSTS_VALU x 4 cycles (a wave64 FP32 instruction on a 16-lane SIMD) /",
              "(1024 SIMDs x GRBM_GUI_ACTIVE / 8 XCDs).", "",
              "| family | waves | VALU instr per wave | LDS instr per wave | kernel cycles | VALU busy |",
@@ -301,7 +301,7 @@ def _stall_summary(out_dir, j, leg, title):
     st = pmc_by_kernel(j(d))
     lines = [f"# Stall and occupancy counters: {title}, headline workload (N=1024, R=64, M=8)", "", "Command:", "",
              f"    {PRE}"] + _pmc_cmd(PMC_STALL, d, leg) + [
-             "", f"Summary: `python -m paper_2604_07248_amd.prof_summary pmc gpurun_out/{d}` (per-dispatch",
+             "", f"Summary: `python -m paper_2604_07248_amd.prof_summary pmc $OUT/{d}` (per-dispatch",
              "averages).  With c = GRBM_GUI_ACTIVE / 8 (kernel cycles; the counter adds the 8 XCDs): waves",
              "resident per CU = 4 SQ_WAVE_CYCLES / (256 c) (the SQ cycle counters count 4-cycle units); wait",
              "fractions = SQ_WAIT_ANY and SQ_WAIT_INST_ANY over SQ_WAVE_CYCLES; LDS bank conflicts per",
@@ -342,7 +342,7 @@ def main(argv=None):
     r = sub.add_parser("report", help="write the committed summaries of the standard runs")
     r.add_argument("--bench", required=True, help="bench.py JSON of the same sources")
     r.add_argument("--out", default="profiles")
-    r.add_argument("--root", default="gpurun_out")
+    r.add_argument("--root", required=True, help="the output directory of the runs ($OUT)")
     a = ap.parse_args(argv)
     if a.cmd == "report":
         report(a.out, a.bench, a.root)
