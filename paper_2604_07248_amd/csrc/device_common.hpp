@@ -36,6 +36,28 @@ __device__ __forceinline__ float2 ld_s(const float2* p) {
   }
 }
 
+// Global stores with the non-temporal (nt) cache policy when NT is set: for
+// outputs that no kernel of the same pass sequence reads back soon
+// (checkpoints and dL/dphi, read by the adjoint or the caller), which then do
+// not displace the field planes the next pass reads from the last-level cache.
+template <bool NT>
+__device__ __forceinline__ void st_s(float2* p, float2 v) {
+  if constexpr (NT) {
+    const float2_nt w = {v.x, v.y};
+    __builtin_nontemporal_store(w, reinterpret_cast<float2_nt*>(p));
+  } else {
+    *p = v;
+  }
+}
+template <bool NT>
+__device__ __forceinline__ void st_f(float* p, float v) {
+  if constexpr (NT) {
+    __builtin_nontemporal_store(v, p);
+  } else {
+    *p = v;
+  }
+}
+
 __device__ __forceinline__ float2 c_add(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 c_sub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
 __device__ __forceinline__ float2 c_mul(float2 a, float2 b) {

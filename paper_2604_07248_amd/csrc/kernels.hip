@@ -172,7 +172,7 @@ __device__ __forceinline__ void row_pass_body(const RowArgs& a) {
         }
         if (a.ckpt_out) {
 #pragma unroll
-          for (int m = 0; m < kE; ++m) (a.ckpt_out + cw + t)[T * m] = x[m];
+          for (int m = 0; m < kE; ++m) st_s<true>(a.ckpt_out + cw + t + T * m, x[m]);
         }
       } else {
         if (a.ckpt_out) {  // the forward field at this screen, rebuilt by the adjoint chain
@@ -183,7 +183,7 @@ __device__ __forceinline__ void row_pass_body(const RowArgs& a) {
 #pragma unroll
           for (int m = 0; m < kE; ++m) {
             const float2 w = (a.ckpt_in + cw + t)[T * m];
-            (a.grad_screens + ck + t)[T * m] = w.x * x[m].y - w.y * x[m].x;  // Im(conj(W) g)
+            st_f<true>(a.grad_screens + ck + t + T * m, w.x * x[m].y - w.y * x[m].x);  // Im(conj(W) g)
           }
         }
 #pragma unroll
@@ -365,7 +365,7 @@ __device__ __forceinline__ void row_pair_body(const RowArgs& a) {
       }
       if (a.ckpt_out && writes) {
 #pragma unroll
-        for (int m = 0; m < kE; ++m) (a.ckpt_out + cw + t)[T * m] = x[m];
+        for (int m = 0; m < kE; ++m) st_s<true>(a.ckpt_out + cw + t + T * m, x[m]);
       }
     } else {
       if (a.ckpt_out && writes) {  // the forward field at this screen, rebuilt by the adjoint chain
@@ -376,7 +376,7 @@ __device__ __forceinline__ void row_pair_body(const RowArgs& a) {
 #pragma unroll
         for (int m = 0; m < kE; ++m) {
           const float2 w = wck[m];
-          (a.grad_screens + ck + t)[T * m] = w.x * x[m].y - w.y * x[m].x;  // Im(conj(W) g)
+          st_f<true>(a.grad_screens + ck + t + T * m, w.x * x[m].y - w.y * x[m].x);  // Im(conj(W) g)
         }
       }
 #pragma unroll
