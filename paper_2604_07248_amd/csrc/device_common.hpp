@@ -81,8 +81,11 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
     }
     const uint64_t p0 = static_cast<uint64_t>(0xD2511F53u) * c.x;
     const uint64_t p1 = static_cast<uint64_t>(0xCD9E8D57u) * c.z;
-    c = make_uint4(static_cast<uint32_t>(p1 >> 32) ^ c.y ^ k0, static_cast<uint32_t>(p1),
-                   static_cast<uint32_t>(p0 >> 32) ^ c.w ^ k1, static_cast<uint32_t>(p0));
+    // three-input exclusive or in one gfx950 instruction (truth table 0x96)
+    c = make_uint4(__builtin_amdgcn_bitop3_b32(static_cast<uint32_t>(p1 >> 32), c.y, k0, 0x96),
+                   static_cast<uint32_t>(p1),
+                   __builtin_amdgcn_bitop3_b32(static_cast<uint32_t>(p0 >> 32), c.w, k1, 0x96),
+                   static_cast<uint32_t>(p0));
   }
   return c;
 }
