@@ -734,7 +734,9 @@ __device__ __forceinline__ void synth_col_body(const SynthArgs& a) {
     }
 #pragma unroll
     for (int m = 0; m < kE; ++m) {
-      st[static_cast<size_t>(T * m) * N] = x[m];
+      // read back one time step later: non-temporal where a strip row is a
+      // whole 128-byte line (16 columns)
+      st_s<(K >= 16)>(st + static_cast<size_t>(T * m) * N, x[m]);
       x[m] = c_scale(x[m], inv2pi);
     }
   } else if (a.spectra) {
