@@ -119,3 +119,36 @@ def test_fused_ar_step_launch_choices(api, n, radix, width):
         a = plan.evolve_propagate(sa, 9, t, 0.95, 0.5, 0.25, u_in=u0)
         b = ref.evolve_propagate(sb, 9, t, 0.95, 0.5, 0.25, u_in=u0)
         assert torch.equal(a, b) and torch.equal(sa, sb), t
+
+
+def test_ar_full_size_sampled(api):
+    """The AR workload at full size (N = 1024, 32 sequences, 8 screens, the
+    frozen-flow shift and alpha of the workload) in the benchmark's launch
+    configuration (tuned), two fused steps; the first and the last pair's
+    spectra and received fields checked one by one against the oracle."""
+    w = workloads.config3()
+    path, ex = w.path, w.extra
+    say(f"[ar full] N={path.n} R={path.realizations} M={path.num_screens}")
+    plan = api.Plan(path)
+    plan.tune()
+    u0 = w.source_field().astype(np.complex64)
+    state = plan.init_spectra(seed=w.seed)
+    steps = 2
+    for t in range(1, steps + 1):
+        out = plan.evolve_propagate(state, w.seed, t, ex["alpha"], ex["shift_x"], ex["shift_y"], u_in=c64(u0))
+    out = out.cpu().numpy()
+    pairs = [0, path.realizations // 2 - 1]
+    for j in pairs:
+        ref = np.empty((1, path.num_screens, path.n, path.n), dtype=np.complex128)
+        for s_ in range(path.num_screens):
+            c = oev.initial_spectrum(path, w.seed, j, s_)
+            for t in range(1, steps + 1):
+                c = oev.evolve_step(c, path, w.seed, t, j, s_, ex["alpha"], ex["shift_x"], ex["shift_y"])
+            ref[0, s_] = c
+        e_spec = rel_l2(state[j].cpu().numpy(), ref[0])
+        phi = oev.screens_from_spectra(ref, 2)
+        ref_out, _ = opr.propagate(u0.astype(np.complex128), path, phi)
+        e_out = [rel_l2(out[2 * j + b], ref_out[b]) for b in (0, 1)]
+        say(f"[ar full] pair {j}: spectra {e_spec:.2e}, fields {e_out[0]:.2e} {e_out[1]:.2e}")
+        assert e_spec < TOL and max(e_out) < TOL
+
