@@ -352,6 +352,33 @@ def test_headline_full_size_sampled(api):
     assert np.max(np.abs(np.sum(np.abs(out.astype(np.complex128)) ** 2, axis=(1, 2)) / e0 - 1)) < 1e-4
 
 
+@pytest.mark.parametrize("cn2,source", [(1e-14, "gaussian"), (5e-14, "flat_top")])
+def test_config2_full_size_sampled(api, cn2, source):
+    """Config 2 at full size (N = 512, 256 realizations, 10 screens with
+    3-level subharmonics) at its middle and strongest points, in the tuned
+    launch configuration: forward and adjoint, sampled realizations (both of
+    the first pair, one inside, the last) against the oracle one by one."""
+    w = workloads.config2(cn2=cn2, source=source, seed=30)
+    say(f"[config2 full] N=512 R=256 M=10 sh=3 cn2={cn2:g} {source}")
+    plan = api.Plan(w.path)
+    plan.tune()
+    u0 = w.source_field().astype(np.complex64)
+    out, ck = plan.propagate(c64(u0), seed=w.seed, checkpoints=True)
+    g = torch.ones_like(out) * (1.0 / 512)
+    g_in, g_phi = plan.propagate_backward(g, ck, seed=w.seed)
+    out = out.cpu().numpy()
+    sample = [0, 1, 130, 255]
+    phi = oracle_screens(w.path, w.seed, sample)
+    ref, ref_ck = opr.propagate(u0.astype(np.complex128), w.path, phi)
+    ref_gin, ref_gphi = opr.propagate_adjoint(np.ones_like(ref) / 512, w.path, phi, ref_ck)
+    for i, r in enumerate(sample):
+        e = rel_l2(out[r], ref[i])
+        eg = rel_l2(g_in[r].cpu().numpy(), ref_gin[i])
+        ep = rel_l2(g_phi[r].cpu().numpy(), ref_gphi[i])
+        say(f"[config2 full] r={r} field {e:.2e} grad_in {eg:.2e} grad_phi {ep:.2e}")
+        assert e < TOL and eg < TOL and ep < TOL
+
+
 def test_library_loaded_by_host_call_before_gpu_work():
     """A host-only call (screen placement) may load the library before any GPU
     work; plans created afterwards must still find the device.  Run in a fresh
