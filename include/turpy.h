@@ -122,6 +122,10 @@ const char* turpy_last_error(void);
  * N dx^2 n0 / lambda, Eq. 7 with the Nyquist frequency, unless flags has
  * TURPY_ALLOW_ALIASING), HIP. */
 turpy_status turpy_plan_create(turpy_plan** out, const turpy_path* path, uint32_t flags);
+/* Releases the plan's device tables with hipFree, which waits for the device:
+ * not while any stream of the device is being captured into a graph (a
+ * capture in global mode is then invalidated), and not while the plan's work
+ * is still to run.  NULL is accepted. */
 turpy_status turpy_plan_destroy(turpy_plan* plan);
 
 /* Bytes of the checkpoint buffer of turpy_propagate / turpy_propagate_backward:
@@ -379,6 +383,8 @@ typedef struct turpy_batch turpy_batch;
  * (TURPY_E_INVALID). */
 turpy_status turpy_batch_create(turpy_batch** out, const turpy_path* paths, const int64_t* field_offsets,
                                 int32_t num_paths, uint32_t flags);
+/* Releases the batch's plans and device records (hipFree): the conditions
+ * of turpy_plan_destroy apply.  NULL is accepted. */
 turpy_status turpy_batch_destroy(turpy_batch* batch);
 /* turpy_plan_bind_time for every instance of the batch. */
 turpy_status turpy_batch_bind_time(turpy_batch* batch, const void* dev_t);

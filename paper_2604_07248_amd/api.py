@@ -18,6 +18,37 @@ def _stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
+# Library handles released while the current stream is being captured into a
+# graph (for instance by the garbage collector, inside a torch.cuda.graph
+# block) are destroyed after the capture: destroying one frees device memory,
+# which would invalidate the capture.
+_deferred = []
+
+
+def _capturing():
+    try:
+        return torch.cuda.is_current_stream_capturing()
+    except Exception:
+        return False
+
+
+def _flush_deferred():
+    if not _deferred or _capturing():
+        return
+    pending = list(_deferred)
+    del _deferred[:]
+    for destroy, handle in pending:
+        destroy(handle)
+
+
+def _release(destroy, handle):
+    if _capturing():
+        _deferred.append((destroy, handle))
+    else:
+        _flush_deferred()
+        destroy(handle)
+
+
 def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
@@ -35,6 +66,7 @@ class Plan:
         self.path = path
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         tune_cache_from_env()
+        _flush_deferred()
         with torch.cuda.device(self.device):
             self.handle = B.plan_create(path, flags)
         self.flags = flags
@@ -68,9 +100,10 @@ class Plan:
             _need(ck, torch.complex64, (self.r, self.m, self.n, self.n), "checkpoints")
 
     def close(self):
-        if getattr(self, "handle", None):
-            B.plan_destroy(self.handle)
+        handle = getattr(self, "handle", None)
+        if handle:
             self.handle = None
+            _release(B.plan_destroy, handle)
 
     def __del__(self):
         try:
@@ -307,14 +340,16 @@ class Batch:
         self.ck_total = sum(ck)
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         tune_cache_from_env()
+        _flush_deferred()
         with torch.cuda.device(self.device):
             self.handle = B.batch_create(self.paths, self.offsets, flags)
         self._ws = {}
 
     def close(self):
-        if getattr(self, "handle", None):
-            B.batch_destroy(self.handle)
+        handle = getattr(self, "handle", None)
+        if handle:
             self.handle = None
+            _release(B.batch_destroy, handle)
 
     def __del__(self):
         try:

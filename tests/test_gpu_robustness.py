@@ -72,6 +72,7 @@ def test_check_finite_refuses_capture(api):
     checked = api.Plan(path, flags=B.CHECK_FINITE)
     u = _source(path)
     out = checked.propagate(u, seed=1)  # workspace allocated outside the capture
+    torch.cuda.synchronize()
     graph = torch.cuda.CUDAGraph()
     err = None
     with torch.cuda.graph(graph):
@@ -81,6 +82,31 @@ def test_check_finite_refuses_capture(api):
             err = e
     del graph
     assert err is not None and err.status == B.E_INVALID and "capturing" in str(err)
+
+
+def test_release_during_capture_is_deferred(api):
+    """A plan or batch released inside a graph capture (as the garbage
+    collector may do) is destroyed after the capture: destroying it frees
+    device memory, which would invalidate the capture."""
+    path = _path()
+    plan, batch = api.Plan(path), api.Batch([path, _path(n=128)])
+    handles = (plan.handle, batch.handle)
+    x = torch.zeros(8, device="cuda")
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        x.add_(1.0)
+        plan.close()
+        batch.close()
+        pending = [h for _, h in api._deferred]
+        assert all(any(h is p for p in pending) for h in handles)
+    for _ in range(3):
+        graph.replay()
+    torch.cuda.synchronize()
+    assert float(x.sum()) == 8 * 3
+    api.Plan(path).close()  # a new plan destroys the deferred handles first
+    assert not api._deferred
+    del graph
 
 
 def _sweep(call, check, limit=400):
