@@ -76,7 +76,6 @@ void* static_scratch(int device) {
 
 }  // namespace
 
-
 namespace {
 void apply_cached_widths(turpy_plan* pl);
 std::string device_arch(int device);
@@ -85,7 +84,6 @@ std::string device_arch(int device);
 extern "C" {
 
 const char* turpy_version(void) { return "turpy-mi355x 0.1 (gfx950)"; }
-
 
 turpy_status turpy_plan_create(turpy_plan** out, const turpy_path* p, uint32_t flags) {
   if (!out || !p) return fail(TURPY_E_INVALID, "plan_create: NULL argument");
@@ -286,8 +284,6 @@ turpy_status turpy_workspace_size(const turpy_plan* pl, int32_t op, size_t* byte
 
 namespace {
 
-
-
 // With TURPY_SCREEN_CHECKPOINTS and a checkpoint buffer, the screens' column
 // halves live after the checkpointed fields: the forward pass writes them
 // there and the adjoint reads them instead of synthesising them again.
@@ -298,16 +294,10 @@ void keep_screens(const turpy_plan* pl, void* checkpoints, int32_t src, Ws* w) {
   w->screen_stride = static_cast<size_t>(pl->P) * plane;
 }
 
-
 turpy_status check_t(int64_t t) {
   if (t < 0 || t > 0xFFFFFFFFll) return fail(TURPY_E_INVALID, "time step t=%lld out of range", (long long)t);
   return TURPY_OK;
 }
-
-
-
-
-
 
 hipError_t enqueue_screen_col(const turpy_plan* pl, uint64_t seed, uint32_t t, int s, const float2* spectra,
                               const Ws& w, hipStream_t st, const EvolveStep* ev = nullptr) {
@@ -326,14 +316,11 @@ hipError_t enqueue_col(const turpy_plan* pl, int step, const float2* in, int64_t
   return hipSuccess;
 }
 
-
 // Fresh subharmonic coefficients of every pair and screen (revolutions) into ws.sh.
 hipError_t enqueue_sh(const turpy_plan* pl, uint64_t seed, uint32_t t, const Ws& w, hipStream_t st) {
   const ShArgs a = sh_args(pl, seed, t, w.sh);
   return timed("sh", st, [&] { return launch_sh(a, st); });
 }
-
-
 
 turpy_status check_src(const turpy_plan* pl, int32_t src, const void* screens_or_spectra) {
   if (src != TURPY_SCREENS_SYNTH && src != TURPY_SCREENS_MATERIALIZED && src != TURPY_SCREENS_SPECTRA)
