@@ -1440,16 +1440,22 @@ turpy_status turpy_plan_tune(turpy_plan* pl, uint32_t flags, void* ws, size_t ws
       return s;
   }
   if (need_ar) {
-    // the AR step of screen 0 with the workspace's R planes as the state
-    // (one screen per pair: the state of pair j at plane j)
+    // the AR step of screen 0 on a state of one screen per pair (pair j at
+    // plane j), alternating between two such states (the R-plane buffer and
+    // the buffer after it): as in a step over M screens, the state a launch
+    // reads is not the one the launch before it left in the last-level cache
     const EvolveStep ev{0.99, 0.5, 0.25};
+    float2* second = reinterpret_cast<float2*>(static_cast<char*>(ws) + pl->off_ubuf());
     SynthArgs a = synth_args(pl, 0, 1, 0, wsp.gbuf, wsp, &ev);
     a.t_dev = nullptr;
     a.M = 1;
+    bool flip = false;
     if (turpy_status s = tune_key(ak, strip_choices(n), {default_synth_width(n), 0, 0}, st,
                                   [&](const LaunchChoice& k) {
                                     a.width = k.width;
                                     a.radix = k.radix;
+                                    flip = !flip;
+                                    a.state = flip ? second : wsp.gbuf;
                                     return launch_synth(n, a, st);
                                   }))
       return s;
