@@ -125,3 +125,10 @@ def test_debug_fail_launch_arguments(L):
     assert L.turpy_debug_fail_launch(-1) == B.E_INVALID
     assert L.turpy_debug_fail_launch(0) == B.OK
     assert L.turpy_plan_bind_moments(None, None) == B.E_INVALID
+
+
+def test_empty_batch_rejected(L):
+    h = ctypes.c_void_p()
+    st = L.turpy_batch_create(ctypes.byref(h), None, None, 0, 0)
+    assert st == B.E_INVALID and "num_paths" in B.last_error()
+    assert not h.value
