@@ -152,3 +152,27 @@ def test_ar_full_size_sampled(api):
         say(f"[ar full] pair {j}: spectra {e_spec:.2e}, fields {e_out[0]:.2e} {e_out[1]:.2e}")
         assert e_spec < TOL and max(e_out) < TOL
 
+
+
+def test_ar_thousand_steps_error_bounded(api):
+    """1000 fused AR steps (the length of the AR workload's runs) at N = 64:
+    the recursion contracts (alpha < 1), so the FP32 state's error against the
+    FP64 oracle saturates at the error of one step over 1 - alpha instead of
+    growing with t."""
+    path = _path(64, 2, 2, 0)
+    plan = api.Plan(path)
+    u0 = c64(workloads.gaussian_source(64, path.dx, 0.1 * 64 * path.dx))
+    spec = plan.init_spectra(seed=5)
+    ref = oev.initial_spectra(path, 5)
+    errs = {}
+    for t in range(1, 1001):
+        out = plan.evolve_propagate(spec, 5, t, 0.99, 0.5, 0.25, u_in=u0)
+        ref = oev.evolve(ref, path, 5, t, 0.99, 0.5, 0.25)
+        if t in (1, 10, 100, 1000):
+            errs[t] = rel_l2(spec.cpu().numpy(), ref)
+    phi = oev.screens_from_spectra(ref, 2)
+    ref_out, _ = opr.propagate(u0.cpu().numpy().astype(np.complex128), path, phi)
+    e_out = rel_l2(out.cpu().numpy(), ref_out)
+    say(f"[ar long] spectra error at t=1/10/100/1000: {errs}; field at t=1000 {e_out:.2e}")
+    assert max(errs.values()) < TOL and e_out < TOL
+    assert errs[1000] < errs[1] / (1 - 0.99)
