@@ -328,15 +328,20 @@ def test_determinism(api):
 
 def test_headline_full_size_sampled(api):
     """Full headline workload (N=1024, R=64, M=8) in the benchmark's launch
-    configuration; sampled realizations checked one by one against the oracle."""
+    configuration; sampled realizations checked one by one against the oracle:
+    the forward fields, and the gradients of the checkpointed and of the
+    checkpoint-free adjoint."""
     w = workloads.headline()
     say("[headline] N=1024 R=64 M=8")
     plan = api.Plan(w.path)
     u0 = w.source_field().astype(np.complex64)
-    out, ck = plan.propagate(c64(u0), seed=w.seed, checkpoints=True)
-    g = torch.ones_like(out) * (1.0 / 1024)
+    out_t, ck = plan.propagate(c64(u0), seed=w.seed, checkpoints=True)
+    g = torch.ones_like(out_t) * (1.0 / 1024)
     g_in, g_phi = plan.propagate_backward(g, ck, seed=w.seed)
-    out = out.cpu().numpy()
+    del ck
+    # the checkpoint-free adjoint, rebuilding the screen-plane fields from the output
+    r_in, r_phi = plan.propagate_backward(g, None, seed=w.seed, u_out=out_t)
+    out = out_t.cpu().numpy()
     sample = [0, 1, 37, 63]
     phi = oracle_screens(w.path, w.seed, sample)
     ref, ref_ck = opr.propagate(u0.astype(np.complex128), w.path, phi)
@@ -345,8 +350,11 @@ def test_headline_full_size_sampled(api):
         e = rel_l2(out[r], ref[i])
         eg = rel_l2(g_in[r].cpu().numpy(), ref_gin[i])
         ep = rel_l2(g_phi[r].cpu().numpy(), ref_gphi[i])
-        say(f"[headline] r={r} field {e:.2e} grad_in {eg:.2e} grad_phi {ep:.2e}")
-        assert e < TOL and eg < TOL and ep < TOL
+        rg = rel_l2(r_in[r].cpu().numpy(), ref_gin[i])
+        rp = rel_l2(r_phi[r].cpu().numpy(), ref_gphi[i])
+        say(f"[headline] r={r} field {e:.2e} grad_in {eg:.2e} grad_phi {ep:.2e}; "
+            f"checkpoint-free grad_in {rg:.2e} grad_phi {rp:.2e}")
+        assert e < TOL and eg < TOL and ep < TOL and rg < TOL and rp < TOL
     # energy is conserved by every realization (unitary steps)
     e0 = np.sum(np.abs(u0.astype(np.complex128)) ** 2)
     assert np.max(np.abs(np.sum(np.abs(out.astype(np.complex128)) ** 2, axis=(1, 2)) / e0 - 1)) < 1e-4
