@@ -387,6 +387,24 @@ def test_config2_full_size_sampled(api, cn2, source):
         assert e < TOL and eg < TOL and ep < TOL
 
 
+def test_headline_angular_spectrum_sampled(api):
+    """The headline workload with the angular-spectrum transfer function (the
+    benchmark's fwd_angular_spectrum leg): sampled realizations against the
+    oracle one by one."""
+    w = workloads.headline()
+    path = w.path.with_(tf_kind=workloads.TF_ANGULAR_SPECTRUM)
+    say("[headline as] N=1024 R=64 M=8 angular spectrum")
+    plan = api.Plan(path)
+    u0 = w.source_field().astype(np.complex64)
+    out = plan.propagate(c64(u0), seed=w.seed).cpu().numpy()
+    sample = [0, 33, 63]
+    ref, _ = opr.propagate(u0.astype(np.complex128), path, oracle_screens(path, w.seed, sample))
+    for i, r in enumerate(sample):
+        e = rel_l2(out[r], ref[i])
+        say(f"[headline as] r={r} field {e:.2e}")
+        assert e < TOL
+
+
 def test_library_loaded_by_host_call_before_gpu_work():
     """A host-only call (screen placement) may load the library before any GPU
     work; plans created afterwards must still find the device.  Run in a fresh
