@@ -13,7 +13,7 @@ import torch
 from paper_2604_07248_amd import binding as B
 from paper_2604_07248_amd import workloads
 
-from gpu_helpers import say
+from gpu_helpers import TOL, oracle_propagate, rel_l2, say
 
 pytestmark = pytest.mark.gpu
 
@@ -144,7 +144,8 @@ def test_grouped_graph_replays(api):
 
 def test_grouped_mix_full_wave(api):
     """A full wave of the serving mix (256 instances, one realization each):
-    sampled instances of every grid size against their own plans."""
+    sampled instances of every grid size against their own plans, and per
+    grid size the instance with the fewest screens against the oracle."""
     mix = [w.path for w in workloads.uneven_batch()][:256]
     batch = api.Batch(mix)
     srcs, u_in = _sources(mix, batch)
@@ -156,3 +157,10 @@ def test_grouped_mix_full_wave(api):
         assert torch.equal(outs[i], plan.propagate(srcs[i], seed=api.Batch.instance_seed(9, i), t=1)), i
         plan.close()
     say(f"[groups] serving-mix wave: {len(sample)} sampled instances bitwise")
+    # per grid size, the instance with the fewest screens against the oracle
+    for n in sorted({p.n for p in mix}):
+        i = min((k for k, p in enumerate(mix) if p.n == n), key=lambda k: mix[k].num_screens)
+        ref, _ = oracle_propagate(mix[i], api.Batch.instance_seed(9, i), srcs[i].cpu().numpy(), t=1)
+        e = rel_l2(outs[i].cpu().numpy(), ref)
+        say(f"[groups] instance {i}: N={n} M={mix[i].num_screens} against the oracle {e:.2e}")
+        assert e < TOL, (i, e)
